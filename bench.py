@@ -1,0 +1,155 @@
+"""Benchmark: batched TabNet inference on one MI355X (libtabnet, HIP/gfx950).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload adult108]
+
+One step is one tabnet_forward over the whole batch of the workload: every decision step
+of the hot path (input BN, feature-transformer passes, attentive transformer with the
+prior, sparsemax, prior update, decision and mask aggregation, final map), with logits,
+the aggregate mask and all per-step masks written to HBM.  Inputs are seeded synthetic
+rows shaped like the paper's Adult table (Sec. IV-A), resident in HBM before timing.
+
+The JSON line reports BF16 rows/s as `value`, the plain FP32 path on the same GPU beside
+it, the roofline of the fused kernel (algorithmic bytes per launch over the event-timed
+launch duration), and the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0      # dense
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def algorithmic(cfg, rows: int, with_steps: bool = True):
+    """Bytes and FLOPs of one forward: X read once; logits, masks_agg and (optionally) the
+    per-step masks written once (FP32).  FLOPs are 2 x MACs of the unpadded GEMMs."""
+    D, N, n_d, n_a, S = cfg.D, cfg.n_d + cfg.n_a, cfg.n_d, cfg.n_a, cfg.n_steps
+    byt = 4 * (D + cfg.n_out + D + (S * D if with_steps else 0))
+    k_first = D
+    macs_pass = k_first * 2 * N + (cfg.n_shared + cfg.n_indep - 1) * N * 2 * N
+    macs = (S + 1) * macs_pass + S * n_a * D + n_d * cfg.n_out
+    return byt * rows, 2 * macs * rows
+
+
+def time_forward(model, X, outs, steps: int, warmup: int):
+    import torch
+    lo, ag, ms = outs
+    for _ in range(warmup):
+        model.forward_into(X, lo, ag, ms)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        model.forward_into(X, lo, ag, ms)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(params, X, budget_s: float = 12.0):
+    """The FP64 oracle on the host's cores over a bounded sample of the same rows."""
+    from threadpoolctl import threadpool_info
+    from oracle import tabnet as oracle
+    chunk = 8192
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < X.shape[0]:
+        oracle.forward(params, X[done:done + chunk])
+        done += min(chunk, X.shape[0] - done)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": done / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {done} of the {X.shape[0]} benchmark rows, FP64 numpy oracle in "
+                      f"{chunk}-row chunks, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="adult108")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (rows are "
+              "independent, so the path shards by rows with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_19689_amd import synth, tabnet
+
+    name = args.workload
+    w = synth.WORKLOADS[name]
+    cfg, rows = w["cfg"], w["rows"]
+    params, Xh = synth.workload(name)
+    print(f"[bench] workload {name}: rows={rows} D={cfg.D} n_d=n_a={cfg.n_d} steps={cfg.n_steps}",
+          file=sys.stderr, flush=True)
+    X = torch.from_numpy(Xh).cuda()
+    res = {}
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, f"{name}.tnw")
+        synth.write_weights(params, path)
+        for prec in (["bf16"] if args.skip_fp32 else ["bf16", "fp32"]):
+            with tabnet.Model(path, prec) as m:
+                outs = m.outputs(rows, with_steps=True)
+                t, wall = time_forward(m, X, outs, args.steps, args.warmup)
+                res[prec] = (t, wall)
+                print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
+                      f"{rows * args.steps / t / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
+    t_bf16, wall_bf16 = res["bf16"]
+    per_launch = t_bf16 / args.steps
+    value = rows * args.steps / t_bf16
+    byt, flops = algorithmic(cfg, rows, with_steps=True)
+    achieved_gbs = byt / per_launch / 1e9
+    out = {
+        "metric": "TabNet rows/sec (BF16/FP8 vs FP32 plain, same GPU) + p50/p99 ms at fixed QPS",
+        "value": value,
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_launch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded Adult-shaped rows and Xavier-uniform weights; no dataset)",
+        "config": {"workload": name, "rows": rows, "D": cfg.D, "n_d": cfg.n_d, "n_a": cfg.n_a,
+                   "n_steps": cfg.n_steps, "n_shared": cfg.n_shared, "n_indep": cfg.n_indep,
+                   "n_out": cfg.n_out, "gamma": cfg.gamma, "masks_step": True,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "tabnet_forward_kernel<bf16>",
+                     "algorithmic_bytes_per_launch": byt,
+                     "mfma_tflops": flops / per_launch / 1e12},
+    }
+    if "fp32" in res:
+        t32 = res["fp32"][0]
+        out["fp32_rows_per_s"] = rows * args.steps / t32
+        out["bf16_over_fp32"] = t32 / t_bf16
+        out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
+    out["wall_s_bf16"] = wall_bf16
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(params, Xh)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,131 @@
+/*
+ * tabnet.h -- C ABI of libtabnet, batched TabNet inference on AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes.  The paper deploys TabNet so that every invocation
+ * returns predictions together with feature-attribution masks (Sec. III-B), the
+ * masks being produced inside the forward pass by sparsemax (Sec. V-C); the model is
+ * loaded into GPU memory once and reused across invocations of caller-chosen batch
+ * size (Sec. III-B).  TabNet itself is the model the paper cites (Sec. I, Sec. II-B):
+ * per decision step an attentive transformer scales its scores by a prior and
+ * applies sparsemax to obtain the step mask M_i; the masked, batch-normalised input
+ * goes through a feature transformer of GLU layers; the decision halves are summed
+ * after ReLU into the output map, and the aggregate mask is sum_i eta_i M_i
+ * normalised per row, with eta_i the row's total ReLU decision mass at step i.
+ *
+ * Conventions shared by every entry point
+ *   - Functions return a tabnet_status; no C++ exception crosses this boundary.
+ *     On a non-OK status tabnet_last_error() returns a message for the calling thread.
+ *   - Matrices are dense, row-major, float32, with no padding between rows.
+ *   - Device pointers are plain HIP device addresses on the handle's device; the
+ *     caller owns them and keeps them alive until the work that uses them finishes.
+ *   - Invalid arguments are rejected before any GPU work is enqueued.
+ */
+#ifndef TABNET_H
+#define TABNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TABNET_OK = 0,
+    TABNET_E_INVALID = -1,     /* bad argument or inconsistent model header            */
+    TABNET_E_OOM = -2,         /* device or host allocation failed                     */
+    TABNET_E_HIP = -3,         /* a HIP runtime call failed; the handle is now failed  */
+    TABNET_E_IO = -4,          /* weight file missing, truncated, or bad magic/version */
+    TABNET_E_ADMISSION = -5,   /* request larger than the server's memory budget       */
+    TABNET_E_TIMEOUT = -6,     /* wait ended before the request completed              */
+    TABNET_E_STOPPED = -7,     /* server stopped; request cancelled                    */
+    TABNET_E_UNSUPPORTED = -8  /* model shape outside the compiled kernel set          */
+} tabnet_status;
+
+typedef enum {
+    TABNET_FP32 = 0,      /* FP32 MFMA GEMMs, FP32 everything                            */
+    TABNET_BF16 = 1,      /* BF16 GEMM operands (RNE), FP32 accumulate and epilogues      */
+    TABNET_FP8_E4M3 = 2   /* E4M3 weights with one scale per output channel; see below   */
+} tabnet_precision;
+
+/* Model hyper-parameters as stored in the weight file.  N = n_d + n_a. */
+typedef struct {
+    int32_t D;          /* input features (columns of X)                               */
+    int32_t n_d;        /* decision width                                              */
+    int32_t n_a;        /* attention width                                             */
+    int32_t n_steps;    /* decision steps S (masks per row)                            */
+    int32_t n_shared;   /* GLU layers shared by every feature-transformer pass         */
+    int32_t n_indep;    /* GLU layers owned by each pass                               */
+    int32_t n_out;      /* output logits per row                                       */
+    int32_t reserved;
+    double gamma;       /* prior relaxation: P <- P * (gamma - M)                      */
+    double bn_eps;      /* batch-norm epsilon                                          */
+} tabnet_config;
+
+typedef struct tabnet_handle tabnet_handle;
+
+/*
+ * tabnet_load -- read a TNW1 weight file, fold every inference batch norm into the
+ * preceding linear map in FP64 (W' = diag(g / sqrt(v + eps)) W, b' = beta - s * mean;
+ * the input batch norm becomes a per-column affine map), round the folded weights to
+ * the requested precision, pack them in the MFMA operand order of the kernels and copy
+ * them to `device`.  The model is then resident: the paper loads its model into GPU
+ * memory once at cold start and reuses it (Sec. III-B).
+ *
+ *   path       TNW1 file (format: header of 64 bytes, then float32 parameters)
+ *   precision  a tabnet_precision value
+ *   device     HIP device ordinal
+ *   out        receives the new handle; the caller releases it with tabnet_free
+ *
+ * Errors: TABNET_E_IO (missing / truncated / bad magic), TABNET_E_INVALID (header
+ * fields out of range, e.g. n_d < 1 or gamma < 1), TABNET_E_UNSUPPORTED (no compiled
+ * kernel covers D, n_d + n_a or n_out), TABNET_E_OOM, TABNET_E_HIP.
+ *
+ * TABNET_FP8_E4M3 stores each GEMM weight row as E4M3 values q with one FP32 scale
+ * sigma_n = max_k |W'_nk| / 448, and feeds the GEMMs BF16 activations (the weights are
+ * widened to BF16 exactly on the way into the matrix cores); accumulation, the GLU and
+ * residual epilogues, the prior, sparsemax and aggregation stay in FP32.
+ */
+tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out);
+
+/* Copy the handle's model hyper-parameters to *out. */
+tabnet_status tabnet_get_config(const tabnet_handle* h, tabnet_config* out);
+
+/* Precision the handle was loaded with (a tabnet_precision value), or -1 for NULL. */
+int tabnet_get_precision(const tabnet_handle* h);
+
+/*
+ * tabnet_forward -- batched TabNet inference, asynchronous on `stream`.
+ *
+ *   X           device, float32 [B, D]: raw feature rows (before the input batch norm)
+ *   B           number of rows; 0 is valid and enqueues nothing
+ *   logits      device, float32 [B, n_out]: W_fin * sum_i ReLU(d_i) per row
+ *   masks_agg   device, float32 [B, D]: sum_i eta_i M_i divided by its row sum; a row
+ *               whose sum is 0 is written as zeros
+ *   masks_step  device, float32 [n_steps, B, D]: the sparsemax masks M_1..M_S; may be
+ *               NULL, in which case the per-step masks are not written
+ *   stream      hipStream_t to enqueue on; NULL means the device's null stream
+ *
+ * Every row is computed independently and in a fixed order, so a row's outputs do not
+ * depend on the other rows of the batch or on B.  Errors: TABNET_E_INVALID (NULL
+ * handle or required pointer, B < 0, B above 2^31 - 1), TABNET_E_HIP (launch failed;
+ * the handle then refuses further work).  Overlapping calls on one handle from several
+ * threads are not supported.
+ */
+tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float* logits,
+                             float* masks_agg, float* masks_step, void* stream);
+
+/* Release the device weights and the handle (NULL is ignored). Synchronises the device. */
+void tabnet_free(tabnet_handle* h);
+
+/* Message of the calling thread's last non-OK status ("" if none). Valid until the
+ * thread's next call into the library. */
+const char* tabnet_last_error(void);
+
+/* Library ABI version (major * 100 + minor). */
+int tabnet_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TABNET_H */

@@ -1,0 +1,44 @@
+/*
+ * tabnet_internal.h -- host-only hooks of libtabnet for tests (no GPU needed).
+ *
+ * They expose the load-time arithmetic of tabnet_load (batch-norm folding, rounding,
+ * header validation) so that it can be checked on a machine without a GPU.  None of
+ * them touches the HIP runtime.
+ */
+#ifndef TABNET_INTERNAL_H
+#define TABNET_INTERNAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tabnet.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* bfloat16 bits of x, round to nearest even. */
+uint16_t tabnet_hook_bf16_bits(double x);
+/* float8 E4M3FN bits of x, round to nearest even, saturating at +-448. */
+uint8_t tabnet_hook_e4m3_bits(double x);
+
+/* Parse and validate a TNW1 image held in memory (buffer of `len` bytes, caller-owned).
+ * On success fills *cfg.  Returns the status tabnet_load would return for that file. */
+tabnet_status tabnet_hook_parse(const void* buf, size_t len, tabnet_config* cfg);
+
+/* Fold FC layer `layer` of the model in `buf` (index into the concatenation of shared
+ * layers, step-specific layers pass by pass, then attentive layers) into W' and b'.
+ * Wf receives rows x cols doubles, bf receives rows doubles; *rows / *cols are set.
+ * Pass NULL Wf/bf to query the sizes. */
+tabnet_status tabnet_hook_fold(const void* buf, size_t len, int layer, double* Wf, double* bf,
+                               int* rows, int* cols);
+
+/* Packed sizes of the model for a precision: bytes of GEMM fragments and float count of
+ * the bias block. */
+tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precision,
+                                       int64_t* wts_bytes, int64_t* bias_floats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

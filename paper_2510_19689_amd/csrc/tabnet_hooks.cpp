@@ -1,0 +1,62 @@
+// Host-only test hooks (include/tabnet_internal.h).
+#include "../../include/tabnet_internal.h"
+
+#include <string>
+#include <vector>
+
+#include "tabnet_pack.hpp"
+
+using namespace tabnet;
+
+extern "C" {
+
+uint16_t tabnet_hook_bf16_bits(double x) { return bf16_bits_rne(x); }
+uint8_t tabnet_hook_e4m3_bits(double x) { return e4m3_bits_rne(x); }
+
+tabnet_status tabnet_hook_parse(const void* buf, size_t len, tabnet_config* cfg) {
+  if (!buf || !cfg) return TABNET_E_INVALID;
+  ModelRaw m;
+  std::string err;
+  tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
+  if (st == TABNET_OK) *cfg = m.cfg;
+  return st;
+}
+
+tabnet_status tabnet_hook_fold(const void* buf, size_t len, int layer, double* Wf, double* bf,
+                               int* rows, int* cols) {
+  if (!buf || !rows || !cols) return TABNET_E_INVALID;
+  ModelRaw m;
+  std::string err;
+  tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
+  if (st != TABNET_OK) return st;
+  std::vector<const LayerRaw*> all;
+  for (const auto& L : m.shared) all.push_back(&L);
+  for (const auto& p : m.indep)
+    for (const auto& L : p) all.push_back(&L);
+  for (const auto& L : m.att) all.push_back(&L);
+  if (layer < 0 || layer >= (int)all.size()) return TABNET_E_INVALID;
+  *rows = all[layer]->rows;
+  *cols = all[layer]->cols;
+  if (!Wf || !bf) return TABNET_OK;
+  std::vector<double> w, b;
+  fold_layer(*all[layer], m.cfg.bn_eps, &w, &b);
+  for (size_t i = 0; i < w.size(); ++i) Wf[i] = w[i];
+  for (size_t i = 0; i < b.size(); ++i) bf[i] = b[i];
+  return TABNET_OK;
+}
+
+tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precision,
+                                       int64_t* wts_bytes, int64_t* bias_floats) {
+  if (!buf || !wts_bytes || !bias_floats) return TABNET_E_INVALID;
+  ModelRaw m;
+  std::string err;
+  tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
+  if (st != TABNET_OK) return st;
+  Packed pk;
+  pack_model(m, precision, &pk);
+  *wts_bytes = (int64_t)pk.wts.size();
+  *bias_floats = (int64_t)pk.bias.size();
+  return TABNET_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Load-time model preparation (host only): batch-norm folding in FP64, rounding to the
+// GEMM operand precision, and packing into the MFMA fragment order the kernel reads.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tabnet.h"
+
+namespace tabnet {
+
+// One inference batch norm: y -> gamma (y - mean) / sqrt(var + eps) + beta.
+struct BNRaw {
+  const float *mean, *var, *gamma, *beta;
+};
+struct LayerRaw {        // W [rows][cols] row-major, then the BN of its rows
+  const float* W;
+  int rows, cols;
+  BNRaw bn;
+};
+struct ModelRaw {
+  tabnet_config cfg;
+  std::vector<float> storage;     // the file's float32 payload
+  BNRaw bn_in;
+  std::vector<LayerRaw> shared;              // n_shared
+  std::vector<std::vector<LayerRaw>> indep;  // n_steps + 1 passes x n_indep
+  std::vector<LayerRaw> att;                 // n_steps
+  const float* w_fin;                        // [n_out][n_d]
+};
+
+// Parses a TNW1 image.  Returns TABNET_OK or an error with *err set.
+tabnet_status parse_model(const unsigned char* data, size_t len, ModelRaw* m, std::string* err);
+int64_t model_param_count(const tabnet_config& c);
+tabnet_status validate_config(const tabnet_config& c, std::string* err);
+
+// Folded affine map of one FC+BN layer, in FP64:  y = W' u + b'.
+void fold_layer(const LayerRaw& L, double eps, std::vector<double>* Wf, std::vector<double>* bf);
+
+// Round-to-nearest-even of a double onto bfloat16 / E4M3FN (saturating at 448), as bits.
+uint16_t bf16_bits_rne(double x);
+uint8_t e4m3_bits_rne(double x);
+double bf16_value(uint16_t bits);
+double e4m3_value(uint8_t bits);
+
+// Kernel shape: tiles of 16 features.
+struct Shape {
+  int DT, NT, KA0;
+};
+Shape shape_of(const tabnet_config& c);
+
+// Packed image of a whole model for one precision.
+struct Packed {
+  std::vector<unsigned char> wts;   // GEMM A-operand fragments, 256-byte aligned per layer
+  std::vector<float> bias;          // per layer: C-layout shifts (and per-channel scales)
+  std::vector<float> in_affine;     // [2][16 DT]: input-BN scale, then shift
+  std::vector<float> wfin;          // [n_out][n_d]
+  std::vector<int64_t> ft_w;        // per unique feature-transformer layer
+  std::vector<int32_t> ft_b;
+  std::vector<int64_t> att_w;       // per step
+  std::vector<int32_t> att_b;
+};
+void pack_model(const ModelRaw& m, int precision, Packed* out);
+
+}  // namespace tabnet

@@ -1,0 +1,151 @@
+"""Python binding of libtabnet (include/tabnet.h): argument marshalling only.
+
+Every step of the forward runs in the HIP library; this module resolves pointers and
+streams from torch tensors and turns status codes into exceptions.  There is no other
+execution path: if libtabnet.so is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtabnet.so")
+
+OK, E_INVALID, E_OOM, E_HIP, E_IO, E_ADMISSION, E_TIMEOUT, E_STOPPED, E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+
+
+class TabNetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("n_d", ctypes.c_int32), ("n_a", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_shared", ctypes.c_int32),
+                ("n_indep", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("bn_eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libtabnet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libtabnet.so not found at {LIB_PATH}; build it with "
+                           "`python -m paper_2510_19689_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.tabnet_load.argtypes = [ctypes.c_char_p, i32, i32, ctypes.POINTER(vp)]
+    L.tabnet_load.restype = i32
+    L.tabnet_get_config.argtypes = [vp, ctypes.POINTER(Config)]
+    L.tabnet_get_config.restype = i32
+    L.tabnet_get_precision.argtypes = [vp]
+    L.tabnet_get_precision.restype = i32
+    L.tabnet_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.tabnet_forward.restype = i32
+    L.tabnet_free.argtypes = [vp]
+    L.tabnet_free.restype = None
+    L.tabnet_last_error.argtypes = []
+    L.tabnet_last_error.restype = ctypes.c_char_p
+    L.tabnet_abi_version.restype = i32
+    # host-only hooks (tabnet_internal.h)
+    L.tabnet_hook_bf16_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_bf16_bits.restype = ctypes.c_uint16
+    L.tabnet_hook_e4m3_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e4m3_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_parse.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(Config)]
+    L.tabnet_hook_parse.restype = i32
+    L.tabnet_hook_fold.argtypes = [vp, ctypes.c_size_t, i32, vp, vp,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.tabnet_hook_fold.restype = i32
+    L.tabnet_hook_packed_sizes.argtypes = [vp, ctypes.c_size_t, i32,
+                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.tabnet_hook_packed_sizes.restype = i32
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = lib().tabnet_last_error().decode(errors="replace")
+        raise TabNetError(status, msg)
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Model:
+    """A TabNet model resident on one GPU (tabnet_load / tabnet_free)."""
+
+    def __init__(self, path: str, precision="fp32", device: int = 0):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        check(lib().tabnet_load(os.fsencode(path), prec, device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.precision = prec
+        c = Config()
+        check(lib().tabnet_get_config(self._h, ctypes.byref(c)))
+        self.config = c
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tabnet_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def forward_into(self, X, logits, masks_agg, masks_step=None, stream=None) -> None:
+        """tabnet_forward on caller-provided device tensors (float32, contiguous)."""
+        B = int(X.shape[0])
+        check(lib().tabnet_forward(self._h, X.data_ptr(), B, logits.data_ptr(),
+                                   masks_agg.data_ptr(),
+                                   None if masks_step is None else masks_step.data_ptr(),
+                                   _stream_ptr(stream)))
+
+    def outputs(self, B: int, with_steps: bool = True):
+        import torch
+        c = self.config
+        dev = torch.device("cuda", self.device)
+        lo = torch.empty((B, c.n_out), dtype=torch.float32, device=dev)
+        ag = torch.empty((B, c.D), dtype=torch.float32, device=dev)
+        ms = torch.empty((c.n_steps, B, c.D), dtype=torch.float32, device=dev) if with_steps else None
+        return lo, ag, ms
+
+    def forward(self, X, with_steps: bool = True, stream=None) -> Tuple:
+        """Returns (logits[B, n_out], masks_agg[B, D], masks_step[S, B, D] or None)."""
+        import torch
+        if X.dtype != torch.float32 or not X.is_contiguous() or X.dim() != 2 or X.shape[1] != self.config.D:
+            raise ValueError(f"X must be a contiguous float32 [B, {self.config.D}] tensor")
+        lo, ag, ms = self.outputs(int(X.shape[0]), with_steps)
+        self.forward_into(X, lo, ag, ms, stream)
+        return lo, ag, ms

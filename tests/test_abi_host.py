@@ -1,0 +1,136 @@
+"""Host-side checks of libtabnet without a GPU: exported symbols, file validation,
+batch-norm folding and the load-time rounding (compared with torch's CPU casts)."""
+import ctypes
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2510_19689_amd import synth, tabnet as tb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(tb.LIB_PATH):
+        pytest.fail("libtabnet.so is not built (run __graft_entry__.build())")
+    return tb.lib()
+
+
+def declared_functions():
+    names = []
+    for hdr in ("tabnet.h", "tabnet_internal.h"):
+        src = open(os.path.join(ROOT, "include", hdr)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(tabnet_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "tabnet_forward" in names and "tabnet_load" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+    assert L.tabnet_abi_version() >= 100
+
+
+def test_missing_and_bad_files(tmp_path, L):
+    h = ctypes.c_void_p()
+    st = L.tabnet_load(str(tmp_path / "nope.tnw").encode(), 0, 0, ctypes.byref(h))
+    assert st == tb.E_IO and b"cannot open" in L.tabnet_last_error()
+    bad = tmp_path / "bad.tnw"
+    bad.write_bytes(b"XXXX" + b"\0" * 100)
+    assert L.tabnet_load(str(bad).encode(), 0, 0, ctypes.byref(h)) == tb.E_IO
+    p = synth.make_params(synth.WORKLOADS["hr35"]["cfg"], 1)
+    raw = synth.to_bytes(p)
+    trunc = tmp_path / "trunc.tnw"
+    trunc.write_bytes(raw[:-8])
+    assert L.tabnet_load(str(trunc).encode(), 0, 0, ctypes.byref(h)) == tb.E_IO
+    assert L.tabnet_load(str(trunc).encode(), 7, 0, ctypes.byref(h)) == tb.E_INVALID
+    assert L.tabnet_load(None, 0, 0, ctypes.byref(h)) == tb.E_INVALID
+
+
+def _hdr(raw, **kw):
+    fields = list(synth.HEADER.unpack_from(raw))
+    names = ["magic", "ver", "D", "n_d", "n_a", "S", "n_sh", "n_ind", "n_out", "res", "gamma", "eps", "n"]
+    for k, v in kw.items():
+        fields[names.index(k)] = v
+    return synth.HEADER.pack(*fields) + raw[synth.HEADER.size:]
+
+
+def test_header_validation(L):
+    p = synth.make_params(synth.WORKLOADS["hr35"]["cfg"], 1)
+    raw = synth.to_bytes(p)
+    c = tb.Config()
+    assert L.tabnet_hook_parse(raw, len(raw), ctypes.byref(c)) == tb.OK
+    assert (c.D, c.n_d, c.n_a, c.n_steps, c.n_shared, c.n_indep, c.n_out) == (35, 8, 8, 3, 2, 2, 2)
+    assert abs(c.gamma - 1.3) < 1e-15
+    for kw in (dict(n_d=0), dict(gamma=0.9), dict(n_out=0), dict(S=0), dict(eps=0.0), dict(n=5)):
+        bad = _hdr(raw, **kw)
+        assert L.tabnet_hook_parse(bad, len(bad), ctypes.byref(c)) == tb.E_INVALID, kw
+    nanraw = bytearray(raw)
+    nanraw[64:68] = struct.pack("<f", float("nan"))
+    assert L.tabnet_hook_parse(bytes(nanraw), len(nanraw), ctypes.byref(c)) == tb.E_INVALID
+
+
+def test_fold_matches_batch_norm(L):
+    """The library's folded affine map reproduces BN(u W^T) (torch, float64)."""
+    p = synth.make_params(synth.WORKLOADS["adult108"]["cfg"], 7)
+    raw = synth.to_bytes(p)
+    cfg = p["config"]
+    layers = p["shared"] + [l for pas in p["indep"] for l in pas] + p["att"]
+    rng = np.random.default_rng(0)
+    for li in (0, 1, 3, len(layers) - 1):
+        rows, cols = ctypes.c_int(), ctypes.c_int()
+        assert L.tabnet_hook_fold(raw, len(raw), li, None, None, ctypes.byref(rows), ctypes.byref(cols)) == 0
+        Wf = np.zeros((rows.value, cols.value))
+        bf = np.zeros(rows.value)
+        assert L.tabnet_hook_fold(raw, len(raw), li, Wf.ctypes.data, bf.ctypes.data,
+                                  ctypes.byref(rows), ctypes.byref(cols)) == 0
+        lay = layers[li]
+        u = torch.tensor(rng.normal(0, 1, (9, cols.value)))
+        y = u @ torch.tensor(lay["W"], dtype=torch.float64).T
+        bn = {k: torch.tensor(v, dtype=torch.float64) for k, v in lay["bn"].items()}
+        ref = torch.nn.functional.batch_norm(y, bn["mean"], bn["var"], bn["gamma"], bn["beta"],
+                                             training=False, eps=cfg.bn_eps).numpy()
+        got = u.numpy() @ Wf.T + bf
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_rounding_hooks_match_torch(L):
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(0, 1, 4000), rng.normal(0, 1e-4, 500), rng.uniform(-440, 440, 2000),
+                        [0.0, 1.0, -2.5, 2 ** -6, 2 ** -9, 3 * 2 ** -10]]).astype(np.float32)
+    bf_ref = torch.tensor(x).to(torch.bfloat16).view(torch.int16).numpy().astype(np.uint16)
+    e4_ref = torch.tensor(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    bf = np.array([L.tabnet_hook_bf16_bits(float(v)) for v in x], dtype=np.uint16)
+    e4 = np.array([L.tabnet_hook_e4m3_bits(float(v)) for v in x], dtype=np.uint8)
+    np.testing.assert_array_equal(bf, bf_ref)
+    np.testing.assert_array_equal(e4, e4_ref)
+    assert L.tabnet_hook_e4m3_bits(1000.0) == 0x7E and L.tabnet_hook_e4m3_bits(-1000.0) == 0xFE
+
+
+def test_packed_sizes(L):
+    """Fragment bytes: FP32 1 KiB per (16-row tile, 16-col tile); BF16 1 KiB per pair of
+    K tiles (an odd last tile padded to a pair); every layer 256-byte aligned."""
+    for name in ("hr35", "adult108", "wide200"):
+        cfg = synth.WORKLOADS[name]["cfg"]
+        p = synth.make_params(cfg, 1)
+        raw = synth.to_bytes(p)
+        DT, NT, KA0 = -(-cfg.D // 16), -(-cfg.N // 16), cfg.n_d // 16
+        sh_k, ind_k = synth.layer_in_dims(cfg)
+        ks = sh_k + ind_k * (cfg.n_steps + 1)
+
+        def frag(MT, KT, prec):
+            b = MT * KT * 1024 if prec == 0 else MT * ((KT + 1) // 2) * 1024
+            return -(-b // 256) * 256
+        for prec in (0, 1):
+            exp = sum(frag(2 * NT, -(-k // 16), prec) for k in ks) + cfg.n_steps * frag(DT, NT - KA0, prec)
+            wb, bfl = ctypes.c_int64(), ctypes.c_int64()
+            assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(bfl)) == 0
+            assert wb.value == exp, (name, prec)
+            assert bfl.value == len(ks) * 2 * NT * 16 + cfg.n_steps * DT * 16
