@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of TabNet, time a plain device-to-device copy of this many "
+                         "bytes (the reference for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (rows are "
@@ -93,6 +96,21 @@ def main():
     import numpy as np
     import torch
     from paper_2510_19689_amd import synth, tabnet
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.warmup):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"copy_bytes": n * 4, "s_per_copy": dt, "GB_s": 2 * n * 4 / dt / 1e9}))
+        return
 
     name = args.workload
     w = synth.WORKLOADS[name]

@@ -13,6 +13,8 @@
 namespace tabnet {
 struct KernelEntry;
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0);
+size_t kernel_lds_bytes(const KernelEntry* k, int D);
+hipError_t prepare_kernel(const KernelEntry* k, int D);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
 }  // namespace tabnet
 
@@ -25,10 +27,10 @@ struct tabnet_handle {
   Shape shape;
   const KernelEntry* kernel;
   unsigned char* d_wts = nullptr;
-  float* d_bias = nullptr;
+  ChunkRec* d_chunks = nullptr;
   float* d_affine = nullptr;
   float* d_wfin = nullptr;
-  LayerTable lt;
+  int n_chunks = 0;
   bool failed = false;
 };
 
@@ -46,11 +48,12 @@ tabnet_status hip_fail(tabnet_handle* h, hipError_t e, const char* what) {
 
 void release(tabnet_handle* h) {
   if (h->d_wts) (void)hipFree(h->d_wts);
-  if (h->d_bias) (void)hipFree(h->d_bias);
+  if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_affine) (void)hipFree(h->d_affine);
   if (h->d_wfin) (void)hipFree(h->d_wfin);
   h->d_wts = nullptr;
-  h->d_bias = h->d_affine = h->d_wfin = nullptr;
+  h->d_chunks = nullptr;
+  h->d_affine = h->d_wfin = nullptr;
 }
 
 template <class T>
@@ -119,6 +122,12 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
 
+  if (kernel_lds_bytes(k, m.cfg.D) > 160 * 1024) {
+    return fail(TABNET_E_UNSUPPORTED, "tabnet_load: the model needs more LDS than a workgroup has");
+  }
+  e = prepare_kernel(k, m.cfg.D);
+  if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+
   Packed pk;
   pack_model(m, precision, &pk);
   tabnet_handle* h = new tabnet_handle();
@@ -127,17 +136,9 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   h->device = device;
   h->shape = sh;
   h->kernel = k;
-  std::memset(&h->lt, 0, sizeof h->lt);
-  for (size_t i = 0; i < pk.ft_w.size(); ++i) {
-    h->lt.w[i] = pk.ft_w[i];
-    h->lt.b[i] = pk.ft_b[i];
-  }
-  for (size_t i = 0; i < pk.att_w.size(); ++i) {
-    h->lt.aw[i] = pk.att_w[i];
-    h->lt.ab[i] = pk.att_b[i];
-  }
+  h->n_chunks = (int)pk.chunks.size();
   if ((st = upload(h, pk.wts, &h->d_wts, "weights")) != TABNET_OK ||
-      (st = upload(h, pk.bias, &h->d_bias, "biases")) != TABNET_OK ||
+      (st = upload(h, pk.chunks, &h->d_chunks, "chunk table")) != TABNET_OK ||
       (st = upload(h, pk.in_affine, &h->d_affine, "input affine")) != TABNET_OK ||
       (st = upload(h, pk.wfin, &h->d_wfin, "final map")) != TABNET_OK) {
     release(h);
@@ -171,7 +172,8 @@ tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float*
   a.masks_agg = masks_agg;
   a.masks_step = masks_step;
   a.wts = h->d_wts;
-  a.bias = h->d_bias;
+  a.chunks = h->d_chunks;
+  a.n_chunks = h->n_chunks;
   a.in_affine = h->d_affine;
   a.wfin = h->d_wfin;
   a.B = B;
@@ -183,7 +185,6 @@ tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float*
   a.n_ind = h->cfg.n_indep;
   a.n_out = h->cfg.n_out;
   a.gamma = (float)h->cfg.gamma;
-  a.lt = h->lt;
   hipError_t e = launch_forward(h->kernel, a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(h, e, "tabnet_forward: kernel launch");
   return TABNET_OK;

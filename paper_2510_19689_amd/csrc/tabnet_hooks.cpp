@@ -46,8 +46,8 @@ tabnet_status tabnet_hook_fold(const void* buf, size_t len, int layer, double* W
 }
 
 tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precision,
-                                       int64_t* wts_bytes, int64_t* bias_floats) {
-  if (!buf || !wts_bytes || !bias_floats) return TABNET_E_INVALID;
+                                       int64_t* wts_bytes, int64_t* n_chunks) {
+  if (!buf || !wts_bytes || !n_chunks) return TABNET_E_INVALID;
   ModelRaw m;
   std::string err;
   tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
@@ -55,7 +55,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   Packed pk;
   pack_model(m, precision, &pk);
   *wts_bytes = (int64_t)pk.wts.size();
-  *bias_floats = (int64_t)pk.bias.size();
+  *n_chunks = (int64_t)pk.chunks.size();
   return TABNET_OK;
 }
 

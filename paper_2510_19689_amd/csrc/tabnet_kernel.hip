@@ -1,7 +1,12 @@
 // Fused TabNet inference kernel for gfx950.  Layout and data flow: tabnet_kernel.hpp.
+#include <hip/hip_runtime.h>
+
 #include "tabnet_kernel.hpp"
 
 namespace tabnet {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kSqrtHalf = 0.70710678118654752f;
@@ -37,9 +42,54 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, b);
 }
 
+// Compare-exchange: a <- max, b <- min.
+__device__ __forceinline__ void cex(float& a, float& b) {
+  const float hi = fmaxf(a, b), lo = fminf(a, b);
+  a = hi;
+  b = lo;
+}
+
+// The 8 values {t1, t2} of the row's 4 lanes (t1 >= t2 in each), sorted descending into
+// v[0..7], identically in all 4 lanes: merge pairs across lanes 16 apart into sorted
+// quadruples, then quadruples across lanes 32 apart by a bitonic merge.
+__device__ __forceinline__ void top8_sorted(float t1, float t2, float (&v)[8]) {
+  const float u1 = xor_shfl(t1, 16), u2 = xor_shfl(t2, 16);
+  float q[4];
+  q[0] = fmaxf(t1, u1);
+  q[3] = fminf(t2, u2);
+  float m1 = fminf(t1, u1), m2 = fmaxf(t2, u2);
+  q[1] = fmaxf(m1, m2);
+  q[2] = fminf(m1, m2);
+  // bitonic sequence: own quadruple descending, partner's ascending
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = q[k];
+    v[7 - k] = xor_shfl(q[k], 32);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) cex(v[k], v[k + 4]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    cex(v[k], v[k + 2]);
+    cex(v[k + 4], v[k + 6]);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) cex(v[k], v[k + 1]);
+}
+
 // logistic(g) = 1 / (1 + 2^(-g log2 e))
 __device__ __forceinline__ float sigmoid_fast(float g) {
   return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-g * kLog2e));
+}
+
+// LDS writes by this wave are complete (cross-lane reuse inside the wave).
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// LDS writes of every wave are complete and every wave has arrived.  Global memory
+// operations stay in flight (no vmcnt wait), so the weight prefetch keeps overlapping.
+__device__ __forceinline__ void lds_block_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
 }
 
 // ------------------------------------------------------------------------------------
@@ -64,18 +114,15 @@ struct BOp<1, KT, R> {        // BF16: two packed dwords per tile
   }
 };
 
-// acc[rb] += W'(tile mt, all K) * B[rb]  for one 16-row output tile.
-//   FP32 fragments: per (mt, kt) 64 lanes x float4 (one float per 16x16x4 MFMA).
-//   BF16 fragments: per (mt, kb) 64 lanes x 8 bf16 (pairs of K tiles, 16x16x32 MFMA);
-//                   an odd trailing K tile is stored as a pair whose second tile is zero.
+// acc[rb] += W'(one output tile, all K) * B[rb]; `fr` points at the tile's fragments
+// in LDS (kblocks(PREC, KT) fragments of 1 KiB).
 template <int PREC, int KT, int R>
-__device__ __forceinline__ void mma_tile(const unsigned char* __restrict__ wl, int mt,
-                                         const BOp<PREC, KT, R>& b, f4 (&acc)[R], int lane) {
+__device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC, KT, R>& b,
+                                         f4 (&acc)[R], int lane) {
   if constexpr (PREC == 0) {
-    const f4* w = reinterpret_cast<const f4*>(wl) + (size_t)mt * KT * 64 + lane;
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
-      f4 a = w[kt * 64];
+      const f4 a = *reinterpret_cast<const f4*>(fr + kt * kFrag + lane * 16);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -83,105 +130,169 @@ __device__ __forceinline__ void mma_tile(const unsigned char* __restrict__ wl, i
           acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b.v[rb][kt][r], acc[rb], 0, 0, 0);
     }
   } else {
-    // K tiles are taken in pairs; an odd trailing tile is paired with zeros (its
-    // fragment's upper half is zero on the weight side too).  Only the 16x16x32 BF16
-    // MFMA is used on purpose: every accumulator chain has one instruction shape.
+    // Only the 16x16x32 BF16 MFMA is used, so every accumulator chain has one
+    // instruction shape; an odd trailing K tile is paired with zeros.
     constexpr int KP = (KT + 1) / 2;
-    const unsigned char* base = wl + (size_t)mt * KP * 1024;
 #pragma unroll
     for (int kb = 0; kb < KP; ++kb) {
-      s8 a = *reinterpret_cast<const s8*>(base + (size_t)kb * 1024 + lane * 16);
+      const s8 a = *reinterpret_cast<const s8*>(fr + kb * kFrag + lane * 16);
 #pragma unroll
       for (int rb = 0; rb < R; ++rb) {
+        constexpr int dummy = 0;
         const bool full = 2 * kb + 1 < KT;
         uint32_t q[4] = {b.v[rb][2 * kb][0], b.v[rb][2 * kb][1],
-                         full ? b.v[rb][full ? 2 * kb + 1 : 0][0] : 0u,
-                         full ? b.v[rb][full ? 2 * kb + 1 : 0][1] : 0u};
-        s8 bb = __builtin_bit_cast(s8, q);
+                         full ? b.v[rb][full ? 2 * kb + 1 : dummy][0] : 0u,
+                         full ? b.v[rb][full ? 2 * kb + 1 : dummy][1] : 0u};
+        const s8 bb = __builtin_bit_cast(s8, q);
         acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[rb], 0, 0, 0);
       }
     }
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Double-buffered weight stream through LDS, shared by the W waves of a workgroup.
+template <int W, int BUF>
+struct WeightStream {
+  static constexpr int T = 64 * W;
+  static constexpr int NSTG = (BUF / 16 + T - 1) / T;
+  unsigned char* lds;            // 2 * BUF bytes
+  const unsigned char* wts;
+  const ChunkRec* tab;
+  int n, idx, cur, next_bytes;
+  f4 stg[NSTG];
+
+  // Issue the global loads of the chunk after the current one into registers.
+  __device__ __forceinline__ void begin() {
+    next_bytes = 0;
+    if (idx + 1 < n) {
+      const ChunkRec r = tab[idx + 1];
+      const f4* src = reinterpret_cast<const f4*>(wts + r.off);
+      next_bytes = r.bytes;
+#pragma unroll
+      for (int j = 0; j < NSTG; ++j) {
+        const int p = (int)threadIdx.x + j * T;
+        if (p * 16 < next_bytes) stg[j] = src[p];
+      }
+    }
+  }
+  // Store them into the other buffer, wait for the whole workgroup, switch buffers.
+  __device__ __forceinline__ void end() {
+    if (idx + 1 < n) {
+      unsigned char* dst = lds + (cur ^ 1) * BUF;
+#pragma unroll
+      for (int j = 0; j < NSTG; ++j) {
+        const int p = (int)threadIdx.x + j * T;
+        if (p * 16 < next_bytes) *reinterpret_cast<f4*>(dst + p * 16) = stg[j];
+      }
+    }
+    lds_block_sync();
+    cur ^= 1;
+    ++idx;
+  }
+  __device__ __forceinline__ const unsigned char* ptr() const { return lds + cur * BUF; }
+};
+
 // One GLU layer: h <- GLU(u W'^T + b')  (first layer of a pass)
 //            or  h <- (h + GLU(h W'^T + b')) * sqrt(1/2).
-// Output tiles 0..NT-1 are the value half, NT..2NT-1 the gate half; value tile mt and
-// gate tile mt land in the same lanes and registers, so the GLU is lane-local.
-template <int PREC, int KT, int NT, int R>
-__device__ __forceinline__ void glu_layer(const unsigned char* __restrict__ wl,
-                                          const float* __restrict__ bl,
-                                          const BOp<PREC, KT, R>& b, float (&h)[R][NT][4],
-                                          bool first, int lane) {
+// Value tile mt and gate tile mt land in the same lanes and registers, so the GLU is
+// lane-local.  The layer's units arrive chunk by chunk through the weight stream.
+template <int PREC, int KT, int NT, int R, int UNIT, int UPC, int NCH, class WS>
+__device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
+                                          float (&h)[R][NT][4], bool first, int lane) {
+  constexpr int KB = kblocks(PREC, KT);
   const int g = lane >> 4;
-  float hn[R][NT][4];
+  // h is updated tile by tile in place: the B operand is a separate copy of the input.
 #pragma unroll
-  for (int mt = 0; mt < NT; ++mt) {
-    const f4 bv = *reinterpret_cast<const f4*>(bl + mt * 16 + 4 * g);
-    const f4 bg = *reinterpret_cast<const f4*>(bl + (NT + mt) * 16 + 4 * g);
-    f4 av[R], ag[R];
+  for (int c = 0; c < NCH; ++c) {
+    ws.begin();
+    const unsigned char* buf = ws.ptr();
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
-    mma_tile<PREC, KT, R>(wl, mt, b, av, lane);
-    mma_tile<PREC, KT, R>(wl, NT + mt, b, ag, lane);
+    for (int u = 0; u < UPC; ++u) {
+      const int mt = c * UPC + u;
+      if (mt < NT) {
+        const unsigned char* unit = buf + u * UNIT;
+        const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 16 * g);
+        const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 64 + 16 * g);
+        f4 av[R], ag[R];
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb)
+        for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
+        mma_tile<PREC, KT, R>(unit, b, av, lane);
+        mma_tile<PREC, KT, R>(unit + KB * kFrag, b, ag, lane);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float gl = av[rb][i] * sigmoid_fast(ag[rb][i]);
-        hn[rb][mt][i] = first ? gl : (h[rb][mt][i] + gl) * kSqrtHalf;
+        for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float sg = sigmoid_fast(ag[rb][i]);
+            h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
+          }
       }
+    }
+    ws.end();
   }
-#pragma unroll
-  for (int rb = 0; rb < R; ++rb)
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) h[rb][mt][i] = hn[rb][mt][i];
 }
 
-// Feature-transformer pass s on input u (DT tiles); result h (NT tiles).
-template <int PREC, int DT, int NT, int R>
-__device__ __forceinline__ void ft_pass(const FwdArgs& A, int s, const BOp<PREC, DT, R>& u,
+// Feature-transformer pass on input u (DT tiles); result h (NT tiles).  L = layers/pass.
+template <int PREC, int DT, int NT, int KA0, int R, class WS>
+__device__ __forceinline__ void ft_pass(WS& ws, int L, const BOp<PREC, DT, R>& u,
                                         float (&h)[R][NT][4], int lane) {
-  const int L = A.n_sh + A.n_ind;
-  auto lid = [&](int l) { return l < A.n_sh ? l : A.n_sh + s * A.n_ind + (l - A.n_sh); };
-  {
-    const int id = lid(0);
-    glu_layer<PREC, DT, NT, R>(A.wts + A.lt.w[id], A.bias + A.lt.b[id], u, h, true, lane);
-  }
+  constexpr Plan P = make_plan(PREC, DT, NT, KA0);
+  glu_layer<PREC, DT, NT, R, P.first.unit, P.first.upc, P.first.nchunks>(ws, u, h, true, lane);
   for (int l = 1; l < L; ++l) {
-    const int id = lid(l);
     BOp<PREC, NT, R> bh;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int t = 0; t < NT; ++t) bh.set(rb, t, h[rb][t]);
-    glu_layer<PREC, NT, NT, R>(A.wts + A.lt.w[id], A.bias + A.lt.b[id], bh, h, false, lane);
+    glu_layer<PREC, NT, NT, R, P.mid.unit, P.mid.upc, P.mid.nchunks>(ws, bh, h, false, lane);
+  }
+}
+
+// Copy n consecutive floats from this wave's LDS staging area to global memory, with
+// all 64 lanes writing consecutive 16-byte pieces (streaming stores).
+__device__ __forceinline__ void stage_out(const float* st, float* dst, int n, int lane) {
+  if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+    const int n4 = n & ~3;
+    for (int e = 4 * lane; e < n4; e += 256)
+      __builtin_nontemporal_store(*reinterpret_cast<const f4*>(st + e), reinterpret_cast<f4*>(dst + e));
+    for (int e = n4 + lane; e < n; e += 64) __builtin_nontemporal_store(st[e], dst + e);
+  } else {
+    for (int e = lane; e < n; e += 64) __builtin_nontemporal_store(st[e], dst + e);
   }
 }
 
 // ------------------------------------------------------------------------------------
-template <int PREC, int DT, int NT, int KA0, int R>
-__global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) {
+template <int PREC, int DT, int NT, int KA0, int R, int W>
+__global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
+  constexpr Plan PL = make_plan(PREC, DT, NT, KA0);
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
+  const int rl = lane & 15;
   const int D = A.D, n_d = A.n_d;
-  const int64_t row0 = ((int64_t)blockIdx.x * kWaves + wave) * (16 * R) + (lane & 15);
-  int64_t row[R];
+  const int64_t wrow0 = ((int64_t)blockIdx.x * W + wave) * (16 * R);   // first row of this wave
+  const int live_rows = (int)(A.B - wrow0 < 0 ? 0 : (A.B - wrow0 > 16 * R ? 16 * R : A.B - wrow0));
+  float* stage = reinterpret_cast<float*>(smem + 2 * PL.buf) + (size_t)wave * 16 * R * D;
   bool live[R];
 #pragma unroll
-  for (int rb = 0; rb < R; ++rb) {
-    row[rb] = row0 + 16 * rb;
-    live[rb] = row[rb] < A.B;
-  }
+  for (int rb = 0; rb < R; ++rb) live[rb] = 16 * rb + rl < live_rows;
   // Is feature 16 t + 4 g + i a real column?  Only the last tile can be partial.
   bool last_ok[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) last_ok[i] = 16 * (DT - 1) + 4 * g + i < D;
   auto feat_ok = [&](int t, int i) { return t < DT - 1 || last_ok[i]; };
+
+  WeightStream<W, PL.buf> ws;
+  ws.lds = smem;
+  ws.wts = A.wts;
+  ws.tab = A.chunks;
+  ws.n = A.n_chunks;
+  ws.idx = -1;
+  ws.cur = 1;
+  ws.begin();     // first chunk -> buffer 0
 
   // ---- input batch norm (folded to a per-column affine map) ----
   float x[R][DT][4];
@@ -193,7 +304,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
       float v[4] = {0.f, 0.f, 0.f, 0.f};
-      const float* xr = A.X + row[rb] * D + 16 * t + 4 * g;
+      const float* xr = A.X + (wrow0 + 16 * rb + rl) * D + 16 * t + 4 * g;
       if (live[rb]) {
         if (vec4) {
           if (feat_ok(t, 0)) {
@@ -210,6 +321,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
       for (int i = 0; i < 4; ++i) x[rb][t][i] = v[i] * sc[i] + sh[i];
     }
   }
+  ws.end();
 
   float P[R][DT][4], agg[R][DT][4], M[R][DT][4];
   float h[R][NT][4], acc[R][NT][4];
@@ -224,6 +336,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[rb][t][i] = 0.f;
   }
+  const int L = A.n_sh + A.n_ind;
 
   // ---- pass 0: only its attention half is used ----
   {
@@ -232,7 +345,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int t = 0; t < DT; ++t) u.set(rb, t, x[rb][t]);
-    ft_pass<PREC, DT, NT, R>(A, 0, u, h, lane);
+    ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
   }
 
   const int64_t step_stride = A.B * (int64_t)D;
@@ -244,44 +357,68 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
       for (int rb = 0; rb < R; ++rb)
 #pragma unroll
         for (int t = 0; t < KTA; ++t) ba.set(rb, t, h[rb][KA0 + t]);
-      const unsigned char* wa = A.wts + A.lt.aw[s - 1];
-      const float* baf = A.bias + A.lt.ab[s - 1];
+      constexpr int KBA = kblocks(PREC, KTA);
 #pragma unroll
-      for (int mt = 0; mt < DT; ++mt) {
-        const f4 bv = *reinterpret_cast<const f4*>(baf + mt * 16 + 4 * g);
-        f4 za[R];
+      for (int c = 0; c < PL.att.nchunks; ++c) {
+        ws.begin();
+        const unsigned char* buf = ws.ptr();
 #pragma unroll
-        for (int rb = 0; rb < R; ++rb) za[rb] = bv;
-        mma_tile<PREC, KTA, R>(wa, mt, ba, za, lane);
+        for (int u = 0; u < PL.att.upc; ++u) {
+          const int mt = c * PL.att.upc + u;
+          if (mt < DT) {
+            const unsigned char* unit = buf + u * PL.att.unit;
+            const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
+            f4 za[R];
 #pragma unroll
-        for (int rb = 0; rb < R; ++rb)
+            for (int rb = 0; rb < R; ++rb) za[rb] = bv;
+            mma_tile<PREC, KTA, R>(unit, ba, za, lane);
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * za[rb][i] : kNegBig;
+            for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * za[rb][i] : kNegBig;
+          }
+        }
+        ws.end();
       }
     }
     // ---- sparsemax per row: Newton iteration on sum(max(z - tau, 0)) = 1 ----
-    // Scores are shifted by the row maximum (w = z - zmax <= 0), the support lies in
-    // w > -1, and tau' = tau - zmax starts at its lower bound -1.  Each step sets
-    // tau' = (sum_{w > tau'} w - 1) / |{w > tau'}|, which moves tau' up monotonically
-    // and stops, exactly, once the support no longer shrinks.
+    // Scores are shifted by the row maximum (w = z - zmax <= 0).  For ANY set S of
+    // scores, (sum_S w - 1) / |S| is a lower bound of the threshold tau', and the best
+    // bound over the prefixes of a sorted list is exact once the list holds the support.
+    // The start is the best prefix bound of the row's top 8 candidates (the two largest
+    // scores of each of its 4 lanes), floored at -1.  From a lower bound, each step
+    // tau' = (sum_{w > tau'} w - 1) / |{w > tau'}| moves tau' up monotonically and stops,
+    // exactly, once the support no longer shrinks.
     {
       float tau[R];
       int kprev[R];
       bool done[R];
 #pragma unroll
       for (int rb = 0; rb < R; ++rb) {
-        float m = kNegBig;
+        float t1 = kNegBig, t2 = kNegBig;          // this lane's two largest scores
 #pragma unroll
         for (int t = 0; t < DT; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) m = fmaxf(m, M[rb][t][i]);
-        m = row_max(m);
+          for (int i = 0; i < 4; ++i) {
+            const float w = M[rb][t][i];
+            t2 = __builtin_amdgcn_fmed3f(t1, t2, w);
+            t1 = fmaxf(t1, w);
+          }
+        float v[8];
+        top8_sorted(t1, t2, v);
+        const float m = v[0];
 #pragma unroll
         for (int t = 0; t < DT; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) M[rb][t][i] -= m;   // padded: stays hugely negative
-        tau[rb] = -1.f;
+        float c = 0.f, best = -1.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          c += v[k] - m;
+          best = fmaxf(best, (c - 1.f) * (1.0f / (float)(k + 1)));
+        }
+        tau[rb] = best;
         kprev[rb] = 0x7fffffff;
         done[rb] = false;
       }
@@ -320,7 +457,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
 #pragma unroll
           for (int i = 0; i < 4; ++i) M[rb][t][i] = fmaxf(M[rb][t][i] - tau[rb], 0.f);
     }
-    // ---- step mask out, prior update, masked input ----
+    // ---- step mask out (through LDS, coalesced), prior update, masked input ----
     BOp<PREC, DT, R> u;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
@@ -334,25 +471,22 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
         }
         u.set(rb, t, uu);
       }
-      if (A.masks_step != nullptr && live[rb]) {
-        float* mr = A.masks_step + (int64_t)(s - 1) * step_stride + row[rb] * D + 4 * g;
+    }
+    if (A.masks_step != nullptr) {
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-          if (vec4) {
-            if (feat_ok(t, 0)) {
-              f4 q = {M[rb][t][0], M[rb][t][1], M[rb][t][2], M[rb][t][3]};
-              __builtin_nontemporal_store(q, reinterpret_cast<f4*>(mr + 16 * t));
-            }
-          } else {
+      for (int rb = 0; rb < R; ++rb) {
+        float* sr = stage + (16 * rb + rl) * D + 4 * g;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (feat_ok(t, i)) __builtin_nontemporal_store(M[rb][t][i], mr + 16 * t + i);
-          }
-        }
+        for (int t = 0; t < DT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
       }
+      lds_wave_sync();
+      stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
     }
     // ---- feature transformer pass s, decision aggregation ----
-    ft_pass<PREC, DT, NT, R>(A, s, u, h, lane);
+    ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
       float eta = 0.f;
@@ -376,6 +510,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
   // ---- outputs: logits = acc W_fin^T, masks_agg = agg / sum(agg) ----
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) {
+    const int64_t row = wrow0 + 16 * rb + rl;
     for (int o = 0; o < A.n_out; ++o) {
       const float* wf = A.wfin + o * n_d;
       float part = 0.f;
@@ -387,7 +522,7 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
           if (c < n_d) part += acc[rb][t][i] * wf[c];
         }
       part = row_sum(part);
-      if (live[rb] && g == (o & 3)) A.logits[row[rb] * A.n_out + o] = part;
+      if (live[rb] && g == (o & 3)) A.logits[row * A.n_out + o] = part;
     }
     float den = 0.f;
 #pragma unroll
@@ -396,48 +531,37 @@ __global__ void __launch_bounds__(64 * kWaves) tabnet_forward_kernel(FwdArgs A) 
       for (int i = 0; i < 4; ++i) den += agg[rb][t][i];
     den = row_sum(den);
     const float inv = den > 0.f ? 1.0f / den : 0.f;
-    if (live[rb]) {
-      float* ar = A.masks_agg + row[rb] * D + 4 * g;
+    float* sr = stage + (16 * rb + rl) * D + 4 * g;
 #pragma unroll
-      for (int t = 0; t < DT; ++t) {
-        if (vec4) {
-          if (feat_ok(t, 0)) {
-            f4 q = {agg[rb][t][0] * inv, agg[rb][t][1] * inv, agg[rb][t][2] * inv,
-                    agg[rb][t][3] * inv};
-            __builtin_nontemporal_store(q, reinterpret_cast<f4*>(ar + 16 * t));
-          }
-        } else {
+    for (int t = 0; t < DT; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (feat_ok(t, i)) __builtin_nontemporal_store(agg[rb][t][i] * inv, ar + 16 * t + i);
-        }
-      }
-    }
+      for (int i = 0; i < 4; ++i)
+        if (feat_ok(t, i)) sr[16 * t + i] = agg[rb][t][i] * inv;
   }
+  lds_wave_sync();
+  stage_out(stage, A.masks_agg + wrow0 * D, live_rows * D, lane);
 }
-
-}  // namespace tabnet
 
 // ------------------------------------------------------------------------------------
 // Compiled shapes.  (DT, NT, KA0) = (ceil(D/16), ceil((n_d+n_a)/16), floor(n_d/16)); R is
-// the number of 16-row blocks per wavefront, fixed per shape so that a row's arithmetic
-// never depends on the batch size.
-namespace tabnet {
-
+// the number of 16-row blocks per wavefront and W the wavefronts per workgroup, both
+// fixed per shape so that a row's arithmetic never depends on the batch size.
 struct KernelEntry {
-  int prec, DT, NT, KA0, R;
+  int prec, DT, NT, KA0, R, W;
   void (*fn)(FwdArgs);
+  Plan plan;
 };
 
-#define TABNET_SHAPE(P, DT, NT, KA0, R) {P, DT, NT, KA0, R, tabnet_forward_kernel<P, DT, NT, KA0, R>},
-#define TABNET_SHAPES(P)        \
-  TABNET_SHAPE(P, 1, 1, 0, 2)   \
-  TABNET_SHAPE(P, 2, 1, 0, 2)   \
-  TABNET_SHAPE(P, 3, 1, 0, 2)   \
-  TABNET_SHAPE(P, 4, 1, 0, 2)   \
-  TABNET_SHAPE(P, 4, 2, 1, 1)   \
-  TABNET_SHAPE(P, 7, 4, 2, 1)   \
-  TABNET_SHAPE(P, 13, 8, 4, 1)
+#define TABNET_SHAPE(P, DT, NT, KA0, R, W) \
+  {P, DT, NT, KA0, R, W, tabnet_forward_kernel<P, DT, NT, KA0, R, W>, make_plan(P, DT, NT, KA0)},
+#define TABNET_SHAPES(P)          \
+  TABNET_SHAPE(P, 1, 1, 0, 1, 4)  \
+  TABNET_SHAPE(P, 2, 1, 0, 1, 4)  \
+  TABNET_SHAPE(P, 3, 1, 0, 1, 4)  \
+  TABNET_SHAPE(P, 4, 1, 0, 1, 4)  \
+  TABNET_SHAPE(P, 4, 2, 1, 1, 4)  \
+  TABNET_SHAPE(P, 7, 4, 2, 1, 8)  \
+  TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1)};
 
@@ -447,11 +571,23 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0) {
   return nullptr;
 }
 
+size_t kernel_lds_bytes(const KernelEntry* k, int D) {
+  return 2 * (size_t)k->plan.buf + (size_t)k->W * 16 * k->R * D * sizeof(float);
+}
+
+hipError_t prepare_kernel(const KernelEntry* k, int D) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k->fn),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kernel_lds_bytes(k, D));
+}
+
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream) {
-  const int64_t rows_per_block = 16LL * k->R * kWaves;
+  const int64_t rows_per_block = 16LL * k->R * k->W;
   const int64_t blocks = (a.B + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * kWaves), 0, stream, a);
+  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W), kernel_lds_bytes(k, a.D), stream, a);
   return hipGetLastError();
 }
+
+const Plan* kernel_plan(const KernelEntry* k) { return &k->plan; }
+int kernel_waves(const KernelEntry* k) { return k->W; }
 
 }  // namespace tabnet

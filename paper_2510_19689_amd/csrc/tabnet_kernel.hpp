@@ -1,4 +1,5 @@
-// Fused TabNet inference kernel for gfx950 (MI355X).
+// Fused TabNet inference kernel for gfx950 (MI355X): shared definitions of the kernel
+// and of the host code that packs weights for it.
 //
 // One launch runs the whole forward for a batch.  Each wavefront owns R blocks of 16
 // rows and carries them through every decision step without leaving registers:
@@ -25,41 +26,84 @@
 // feeds the next layer (and the sparsemax, the prior, the masks) with no data movement
 // between lanes.  A row's D features are spread over the 4 lanes {r, r+16, r+32, r+48};
 // row reductions are in-lane sums plus two cross-lane exchanges.
+//
+// Weight stream.  The weights are the same for every row, so a workgroup of W waves
+// streams them through LDS once for all its rows: the packed GEMM weights are cut into
+// chunks, listed on the host in the order the kernel consumes them, and a double buffer
+// overlaps the global fetch of chunk c+1 with the MFMAs on chunk c.
+//
+// Packed layout of one GEMM (each starts 256-byte aligned), as a sequence of units:
+//   GLU layer, unit mt = 0..NT-1:  [value-tile fragments][gate-tile fragments]
+//                                  [16 value shifts][16 gate shifts]
+//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts]
+// A fragment is 64 lanes x 16 bytes: FP32 one per 16-wide K tile (a lane's float4 feeds
+// four 16x16x4 MFMAs), BF16 one per pair of K tiles (8 bf16 per lane, one 16x16x32 MFMA;
+// an odd last tile is paired with zeros).  Shifts are in C-layout order: slot 4 q + i
+// of tile mt is output feature 16 mt + 4 q + i.
 #pragma once
-#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tabnet {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s8 __attribute__((ext_vector_type(8)));
-typedef short s4 __attribute__((ext_vector_type(4)));
-
 constexpr int kMaxFtLayers = 96;   // n_shared + (n_steps + 1) * n_indep
 constexpr int kMaxSteps = 32;
-constexpr int kWaves = 4;          // wavefronts per workgroup
+constexpr int kFrag = 1024;        // bytes of one A fragment
+constexpr int kChunkTarget = 20480;
 
-// Byte offsets into the packed weight blob and float offsets into the bias blob.
-struct LayerTable {
-  int64_t w[kMaxFtLayers];
-  int32_t b[kMaxFtLayers];
-  int64_t aw[kMaxSteps];
-  int32_t ab[kMaxSteps];
+struct ChunkRec {
+  int64_t off;     // byte offset into the packed weights
+  int32_t bytes;   // multiple of 16
+  int32_t pad;
 };
+
+struct GemmPlan {
+  int unit;      // bytes per unit (one output tile, or value+gate tile pair)
+  int nunits;
+  int upc;       // units per chunk
+  int nchunks;
+};
+
+constexpr int kblocks(int prec, int KT) { return prec == 0 ? KT : (KT + 1) / 2; }
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Units per chunk: balanced chunks of at most kChunkTarget bytes (one unit if a single
+// unit is larger).
+constexpr GemmPlan gemm_plan(int unit, int nunits) {
+  const int nch0 = cdiv(unit * nunits, kChunkTarget);
+  int upc = cdiv(nunits, nch0 < 1 ? 1 : nch0);
+  const int cap = kChunkTarget / unit < 1 ? 1 : kChunkTarget / unit;
+  if (upc > cap) upc = cap;
+  return GemmPlan{unit, nunits, upc, cdiv(nunits, upc)};
+}
+
+struct Plan {
+  GemmPlan first, mid, att;
+  int buf;       // bytes of one LDS weight buffer
+};
+
+constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+// prec: 0 FP32, 1 BF16.  DT = ceil(D/16), NT = ceil(N/16), KA0 = floor(n_d/16).
+constexpr Plan make_plan(int prec, int DT, int NT, int KA0) {
+  const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128, NT);
+  const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128, NT);
+  const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64, DT);
+  const int buf = imax(first.upc * first.unit, imax(mid.upc * mid.unit, att.upc * att.unit));
+  return Plan{first, mid, att, buf};
+}
 
 struct FwdArgs {
   const float* X;
   float* logits;
   float* masks_agg;
   float* masks_step;          // may be null
-  const unsigned char* wts;   // packed GEMM weights
-  const float* bias;          // folded shifts (and per-channel scales), C-layout order
+  const unsigned char* wts;   // packed GEMM units
+  const ChunkRec* chunks;     // consumption order
   const float* in_affine;     // [2][16*DT]: input BN scale then shift, zero-padded
   const float* wfin;          // [n_out][n_d] float32
   int64_t B;
-  int D, n_d, n_a, n_steps, n_sh, n_ind, n_out;
+  int D, n_d, n_a, n_steps, n_sh, n_ind, n_out, n_chunks;
   float gamma;
-  LayerTable lt;
 };
 
 }  // namespace tabnet

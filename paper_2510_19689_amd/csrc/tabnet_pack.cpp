@@ -1,6 +1,7 @@
 // Load-time model preparation: parse TNW1, fold batch norms (FP64), round, pack.
 #include "tabnet_pack.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -239,96 +240,51 @@ Shape shape_of(const tabnet_config& c) {
 
 namespace {
 
-// A GEMM as the kernel sees it: MT output tiles x KT input tiles.  row_of(mt, i) gives
-// the row of Wf feeding output slot 16 mt + i (or -1: zero row); col_of(kin) maps the
-// kernel's K index (16 t + 4 g + j over the KT tiles) to a column of Wf (or -1).
-struct GemmView {
-  const std::vector<double>* Wf;
-  int cols;
-  int MT, KT;
-  int (*row_of)(const void*, int, int);
-  int (*col_of)(const void*, int);
-  const void* ctx;
-};
-
-// Per-row quantisation scales for FP8 (one per Wf row); 1 for the other precisions.
-void row_scales(const GemmView& g, int precision, int rows, std::vector<double>* sc) {
-  sc->assign(rows, 1.0);
-  if (precision != TABNET_FP8_E4M3) return;
-  for (int r = 0; r < rows; ++r) {
-    double amax = 0;
-    for (int k = 0; k < g.cols; ++k) amax = std::fmax(amax, std::fabs((*g.Wf)[(size_t)r * g.cols + k]));
-    (*sc)[r] = amax > 0 ? amax / 448.0 : 1.0;
-  }
-}
-
 void emit(std::vector<unsigned char>* out, const void* p, size_t n) {
   const unsigned char* b = (const unsigned char*)p;
   out->insert(out->end(), b, b + n);
 }
 
-// Appends the A-operand fragments of one GEMM to `wts` (aligned) and returns its offset.
-int64_t pack_gemm(const GemmView& g, int precision, const std::vector<double>& sc,
-                  std::vector<unsigned char>* wts) {
-  wts->resize(align256(wts->size()), 0);
-  const int64_t off = (int64_t)wts->size();
-  auto wv = [&](int mt, int i, int kin) -> double {
-    const int r = g.row_of(g.ctx, mt, i);
-    const int c = g.col_of(g.ctx, kin);
+// One A-operand fragment group: output tile rows row_of(i) (i = 0..15, -1 = zero row) of
+// the folded weights Wf [rows][cols], K over KT tiles with col_of(kin) mapping the
+// kernel's K index 16 t + 4 q + j to a column of Wf (-1 = zero).
+template <class RowOf, class ColOf>
+void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precision, RowOf row_of,
+                    ColOf col_of, std::vector<unsigned char>* wts) {
+  auto wv = [&](int i, int kin) -> double {
+    const int r = row_of(i);
+    const int c = (kin < 16 * KT) ? col_of(kin) : -1;
     if (r < 0 || c < 0) return 0.0;
-    return (*g.Wf)[(size_t)r * g.cols + c] / sc[r];
+    return Wf[(size_t)r * cols + c];
   };
-  for (int mt = 0; mt < g.MT; ++mt) {
-    if (precision == TABNET_FP32) {
-      for (int kt = 0; kt < g.KT; ++kt)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int i = lane & 15, q = lane >> 4;
-          float v[4];
-          for (int r = 0; r < 4; ++r) v[r] = (float)wv(mt, i, 16 * kt + 4 * q + r);
-          emit(wts, v, sizeof v);
+  if (precision == TABNET_FP32) {
+    for (int kt = 0; kt < KT; ++kt)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, q = lane >> 4;
+        float v[4];
+        for (int r = 0; r < 4; ++r) v[r] = (float)wv(i, 16 * kt + 4 * q + r);
+        emit(wts, v, sizeof v);
+      }
+  } else {
+    const int KP = (KT + 1) / 2;   // an odd last tile is paired with a zero tile
+    for (int kb = 0; kb < KP; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, q = lane >> 4;
+        uint16_t v[8];
+        for (int j = 0; j < 8; ++j) {
+          const int t = 2 * kb + j / 4;
+          const double x = t < KT ? wv(i, 16 * t + 4 * q + (j & 3)) : 0.0;
+          v[j] = bf16_bits_rne(x);
         }
-    } else {
-      const int KP = (g.KT + 1) / 2;   // an odd last tile is paired with a zero tile
-      for (int kb = 0; kb < KP; ++kb)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int i = lane & 15, q = lane >> 4;
-          uint16_t v[8];
-          for (int j = 0; j < 8; ++j) {
-            const int t = 2 * kb + j / 4;
-            const double x = t < g.KT ? wv(mt, i, 16 * t + 4 * q + (j & 3)) : 0.0;
-            v[j] = precision == TABNET_BF16 ? bf16_bits_rne(x) : bf16_bits_rne(e4m3_value(e4m3_bits_rne(x)));
-          }
-          emit(wts, v, sizeof v);
-        }
-    }
+        emit(wts, v, sizeof v);
+      }
   }
-  return off;
 }
 
-struct GluCtx {
-  int N, NT, K;
-};
-int glu_row(const void* c, int mt, int i) {
-  const GluCtx* x = (const GluCtx*)c;
-  const int half = mt / x->NT, ch = 16 * (mt % x->NT) + i;
-  return ch < x->N ? half * x->N + ch : -1;
-}
-int plain_col(const void* c, int kin) {
-  const GluCtx* x = (const GluCtx*)c;
-  return kin < x->K ? kin : -1;
-}
-struct AttCtx {
-  int D, n_d, N, KA0;
-};
-int att_row(const void* c, int mt, int i) {
-  const AttCtx* x = (const AttCtx*)c;
-  const int d = 16 * mt + i;
-  return d < x->D ? d : -1;
-}
-int att_col(const void* c, int kin) {
-  const AttCtx* x = (const AttCtx*)c;
-  const int ch = 16 * x->KA0 + kin;   // channel of h
-  return (ch >= x->n_d && ch < x->N) ? ch - x->n_d : -1;
+void emit_shifts(const std::vector<double>& bf, int rows_valid, int first_row, std::vector<unsigned char>* wts) {
+  float v[16];
+  for (int i = 0; i < 16; ++i) v[i] = i < rows_valid ? (float)bf[first_row + i] : 0.f;
+  emit(wts, v, sizeof v);
 }
 
 }  // namespace
@@ -337,6 +293,8 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
   const tabnet_config& c = m.cfg;
   const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
+  const int kprec = precision == TABNET_FP32 ? 0 : 1;
+  const Plan plan = make_plan(kprec, sh.DT, sh.NT, sh.KA0);
   *out = Packed();
   // input BN as a per-column affine map
   out->in_affine.assign(32 * sh.DT, 0.f);
@@ -345,49 +303,63 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
     out->in_affine[j] = (float)s;
     out->in_affine[16 * sh.DT + j] = (float)((double)m.bn_in.beta[j] - s * (double)m.bn_in.mean[j]);
   }
-  // Bias block of one GEMM: for each output tile, 16 floats in C-layout order
-  // (slot 4 q + i of tile mt is output feature 16 mt + 4 q + i).  FP8 appends the
-  // per-output scales in the same order.
-  auto add_bias = [&](const std::vector<double>& bf, const std::vector<double>& sc, int MT,
-                      int (*row_of)(const void*, int, int), const void* ctx) {
-    const int32_t off = (int32_t)out->bias.size();
-    for (int mt = 0; mt < MT; ++mt)
-      for (int i = 0; i < 16; ++i) {
-        const int r = row_of(ctx, mt, i);
-        out->bias.push_back(r < 0 ? 0.f : (float)bf[r]);
-      }
-    if (precision == TABNET_FP8_E4M3)
-      for (int mt = 0; mt < MT; ++mt)
-        for (int i = 0; i < 16; ++i) {
-          const int r = row_of(ctx, mt, i);
-          out->bias.push_back(r < 0 ? 0.f : (float)sc[r]);
-        }
-    return off;
-  };
   std::vector<const LayerRaw*> ft;
   for (const auto& L : m.shared) ft.push_back(&L);
   for (const auto& pass : m.indep)
     for (const auto& L : pass) ft.push_back(&L);
-  std::vector<double> Wf, bf, sc;
+  std::vector<double> Wf, bf;
+  auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
+  // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
-    GluCtx ctx{N, sh.NT, L->cols};
-    // K tiles: the first layer of a pass reads the D features, the others the N channels
-    GemmView g{&Wf, L->cols, 2 * sh.NT, (L->cols + 15) / 16, glu_row, plain_col, &ctx};
-    row_scales(g, precision, L->rows, &sc);
-    out->ft_w.push_back(pack_gemm(g, precision, sc, &out->wts));
-    out->ft_b.push_back(add_bias(bf, sc, 2 * sh.NT, glu_row, &ctx));
+    const int KT = (L->cols + 15) / 16;   // the first layer of a pass reads D features, the others N
+    const int K = L->cols;
+    align();
+    out->ft_off.push_back((int64_t)out->wts.size());
+    for (int mt = 0; mt < sh.NT; ++mt) {
+      const size_t unit0 = out->wts.size();
+      for (int half = 0; half < 2; ++half)
+        emit_fragments(
+            Wf, L->cols, KT, precision,
+            [&](int i) { const int ch = 16 * mt + i; return ch < N ? half * N + ch : -1; },
+            [&](int kin) { return kin < K ? kin : -1; }, &out->wts);
+      const int nv = std::min(16, N - 16 * mt);
+      emit_shifts(bf, nv, 16 * mt, &out->wts);
+      emit_shifts(bf, nv, N + 16 * mt, &out->wts);
+      (void)unit0;
+    }
   }
+  // attentive layers: unit mt = [fragments over the attention half of h][shifts]
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
-    AttCtx ctx{c.D, c.n_d, N, sh.KA0};
-    GemmView g{&Wf, L.cols, sh.DT, sh.NT - sh.KA0, att_row, att_col, &ctx};
-    row_scales(g, precision, L.rows, &sc);
-    out->att_w.push_back(pack_gemm(g, precision, sc, &out->wts));
-    out->att_b.push_back(add_bias(bf, sc, sh.DT, att_row, &ctx));
+    const int KTA = sh.NT - sh.KA0;
+    align();
+    out->att_off.push_back((int64_t)out->wts.size());
+    for (int mt = 0; mt < sh.DT; ++mt) {
+      emit_fragments(
+          Wf, L.cols, KTA, precision,
+          [&](int i) { const int d = 16 * mt + i; return d < c.D ? d : -1; },
+          [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
+          &out->wts);
+      emit_shifts(bf, std::min(16, c.D - 16 * mt), 16 * mt, &out->wts);
+    }
   }
-  out->wts.resize(align256(out->wts.size()), 0);
+  align();
   out->wfin.assign(m.w_fin, m.w_fin + (size_t)c.n_out * c.n_d);
+  // The weight stream, in the order the kernel consumes it: pass 0's layers, then per
+  // step the attentive GEMM and that pass's layers.
+  auto add = [&](int64_t base, const GemmPlan& gp) {
+    for (int ch = 0; ch < gp.nchunks; ++ch) {
+      const int units = std::min(gp.upc, gp.nunits - ch * gp.upc);
+      out->chunks.push_back(ChunkRec{base + (int64_t)ch * gp.upc * gp.unit, units * gp.unit, 0});
+    }
+  };
+  const int L = c.n_shared + c.n_indep;
+  auto lid = [&](int s, int l) { return l < c.n_shared ? l : c.n_shared + s * c.n_indep + (l - c.n_shared); };
+  for (int s = 0; s <= c.n_steps; ++s) {
+    if (s > 0) add(out->att_off[s - 1], plan.att);
+    for (int l = 0; l < L; ++l) add(out->ft_off[lid(s, l)], l == 0 ? plan.first : plan.mid);
+  }
 }
 
 }  // namespace tabnet

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/tabnet.h"
+#include "tabnet_kernel.hpp"
 
 namespace tabnet {
 
@@ -51,14 +52,12 @@ Shape shape_of(const tabnet_config& c);
 
 // Packed image of a whole model for one precision.
 struct Packed {
-  std::vector<unsigned char> wts;   // GEMM A-operand fragments, 256-byte aligned per layer
-  std::vector<float> bias;          // per layer: C-layout shifts (and per-channel scales)
+  std::vector<unsigned char> wts;   // GEMM units (fragments + shifts), 256-byte aligned per GEMM
+  std::vector<ChunkRec> chunks;     // weight-stream chunks in the kernel's consumption order
   std::vector<float> in_affine;     // [2][16 DT]: input-BN scale, then shift
   std::vector<float> wfin;          // [n_out][n_d]
-  std::vector<int64_t> ft_w;        // per unique feature-transformer layer
-  std::vector<int32_t> ft_b;
-  std::vector<int64_t> att_w;       // per step
-  std::vector<int32_t> att_b;
+  std::vector<int64_t> ft_off;      // per unique feature-transformer layer
+  std::vector<int64_t> att_off;     // per step
 };
 void pack_model(const ModelRaw& m, int precision, Packed* out);
 

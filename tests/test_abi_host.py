@@ -115,22 +115,36 @@ def test_rounding_hooks_match_torch(L):
 
 
 def test_packed_sizes(L):
-    """Fragment bytes: FP32 1 KiB per (16-row tile, 16-col tile); BF16 1 KiB per pair of
-    K tiles (an odd last tile padded to a pair); every layer 256-byte aligned."""
+    """Packed bytes follow the documented unit layout: a GLU layer is NT units of
+    [value fragments][gate fragments][32 shifts], an attentive layer DT units of
+    [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32) or per pair
+    of K tiles (BF16, an odd last tile padded); every GEMM starts 256-byte aligned.
+    The chunk count is the number of weight-stream pieces of at most 20 KiB (balanced,
+    one unit if a unit is larger) over pass 0, then per step attentive + pass."""
+    def cdiv(a, b):
+        return -(-a // b)
+
+    def chunks(unit, n, target=20480):
+        upc = cdiv(n, cdiv(unit * n, target))
+        upc = min(upc, max(1, target // unit))
+        return cdiv(n, upc)
+
     for name in ("hr35", "adult108", "wide200"):
         cfg = synth.WORKLOADS[name]["cfg"]
         p = synth.make_params(cfg, 1)
         raw = synth.to_bytes(p)
-        DT, NT, KA0 = -(-cfg.D // 16), -(-cfg.N // 16), cfg.n_d // 16
+        DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-
-        def frag(MT, KT, prec):
-            b = MT * KT * 1024 if prec == 0 else MT * ((KT + 1) // 2) * 1024
-            return -(-b // 256) * 256
         for prec in (0, 1):
-            exp = sum(frag(2 * NT, -(-k // 16), prec) for k in ks) + cfg.n_steps * frag(DT, NT - KA0, prec)
-            wb, bfl = ctypes.c_int64(), ctypes.c_int64()
-            assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(bfl)) == 0
-            assert wb.value == exp, (name, prec)
-            assert bfl.value == len(ks) * 2 * NT * 16 + cfg.n_steps * DT * 16
+            kb = (lambda KT: KT) if prec == 0 else (lambda KT: cdiv(KT, 2))
+            glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 for k in set(ks)}
+            att_unit = kb(NT - KA0) * 1024 + 64
+            exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
+            first, mid = chunks(2 * kb(DT) * 1024 + 128, NT), chunks(2 * kb(NT) * 1024 + 128, NT)
+            nl = cfg.n_shared + cfg.n_indep
+            exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT)
+            wb, nch = ctypes.c_int64(), ctypes.c_int64()
+            assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == 0
+            assert wb.value == exp, (name, prec, wb.value, exp)
+            assert nch.value == exp_chunks, (name, prec, nch.value, exp_chunks)
