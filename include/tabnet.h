@@ -125,6 +125,86 @@ const char* tabnet_last_error(void);
 /* Library ABI version (major * 100 + minor). */
 int tabnet_abi_version(void);
 
+/* ------------------------------------------------------------------------------------
+ * Serving: continuous batching of variable-row requests.
+ *
+ * The paper serves TabNet per invocation with a batch size chosen at invocation time
+ * (Sec. III-B) and names dynamic batching as the next optimisation (Sec. VI-D).  The
+ * server batches requests as they arrive: a scheduler thread admits queued requests in
+ * arrival order while their bytes fit a memory budget, packs the rows of the admitted
+ * requests (a request may be split across launches) into one of `slots` launch buffers,
+ * and enqueues copy-in, the fused forward and copy-out on that slot's stream, so
+ * launches overlap on the device while later requests are being admitted.  A completion
+ * thread copies each finished slice to the caller's buffers.  Every row is computed by
+ * the same kernel as tabnet_forward, so a request's results do not depend on what it was
+ * batched with.
+ * ------------------------------------------------------------------------------------ */
+typedef struct tabnet_server tabnet_server;
+
+typedef struct {
+    uint64_t mem_budget_bytes;     /* bytes of admitted, unfinished requests; 0 -> 8 GiB      */
+    int32_t max_rows_per_launch;   /* rows per launch buffer; 0 -> 65536                     */
+    int32_t slots;                 /* launch buffers (launches in flight); 0 -> 3, max 8     */
+    int32_t with_step_masks;       /* 1: requests may ask for masks_step                      */
+    int32_t use_graph;             /* 1: each slot's launch is a captured HIP graph          */
+    int32_t reserved[4];
+} tabnet_serve_opts;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, cancelled;
+    uint64_t rows_completed, launches;
+    double p50_us, p99_us, p999_us, max_us, mean_us;  /* completion - arrival              */
+    double rows_per_s;             /* completed rows / (last completion - first arrival)     */
+    double mean_rows_per_launch;
+    uint64_t inflight_bytes, peak_inflight_bytes;
+} tabnet_serve_stats;
+
+/*
+ * tabnet_serve_start -- start a server over n_models resident models (handles stay owned
+ * by the caller and must outlive the server; they must all be on one device).
+ * opts may be NULL for the defaults.  Errors: TABNET_E_INVALID, TABNET_E_OOM, TABNET_E_HIP.
+ */
+tabnet_status tabnet_serve_start(tabnet_handle* const* models, int n_models,
+                                 const tabnet_serve_opts* opts, tabnet_server** out);
+
+/*
+ * tabnet_serve_submit -- enqueue a request of `rows` rows for model index `model`.
+ *   X_host           host, float32 [rows, D]; read during the call (copied), may be reused after
+ *   logits_host      host, float32 [rows, n_out]; written before the request completes
+ *   masks_agg_host   host, float32 [rows, D]
+ *   masks_step_host  host, float32 [n_steps, rows, D] or NULL (ignored unless the server was
+ *                    started with with_step_masks)
+ *   arrival_ns       arrival time on the steady clock (tabnet_serve_now_ns), or 0 for "now";
+ *                    latency is measured from it
+ *   req_id           receives the request id
+ * Output buffers must stay valid until tabnet_serve_wait / poll reports completion.
+ * Errors: TABNET_E_INVALID; TABNET_E_ADMISSION if the request alone exceeds the budget;
+ * TABNET_E_STOPPED after tabnet_serve_stop.  Thread-safe.
+ */
+tabnet_status tabnet_serve_submit(tabnet_server* s, int model, const float* X_host, int64_t rows,
+                                  float* logits_host, float* masks_agg_host, float* masks_step_host,
+                                  int64_t arrival_ns, uint64_t* req_id);
+
+/* Wait up to timeout_us (< 0: forever) for a request.  TABNET_OK once its outputs are
+ * written (the id is then released), TABNET_E_TIMEOUT, TABNET_E_STOPPED if it was cancelled,
+ * TABNET_E_HIP if its launch failed, TABNET_E_INVALID for an unknown id.  Thread-safe. */
+tabnet_status tabnet_serve_wait(tabnet_server* s, uint64_t req_id, int64_t timeout_us);
+
+/* Non-blocking: *done = 1 (and the id is released) once the request finished; the status
+ * is what tabnet_serve_wait would return. */
+tabnet_status tabnet_serve_poll(tabnet_server* s, uint64_t req_id, int* done);
+
+/* Counters and latency percentiles since start or the last reset. */
+tabnet_status tabnet_serve_get_stats(tabnet_server* s, tabnet_serve_stats* out);
+tabnet_status tabnet_serve_reset_stats(tabnet_server* s);
+
+/* Steady-clock time in nanoseconds (the clock of arrival_ns). */
+int64_t tabnet_serve_now_ns(void);
+
+/* Stop admitting, cancel queued requests (they report TABNET_E_STOPPED), finish the
+ * launches in flight, join the threads and free the server. */
+tabnet_status tabnet_serve_stop(tabnet_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,29 +10,9 @@
 #include "tabnet_kernel.hpp"
 #include "tabnet_pack.hpp"
 
-namespace tabnet {
-struct KernelEntry;
-const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0);
-size_t kernel_lds_bytes(const KernelEntry* k, int D);
-hipError_t prepare_kernel(const KernelEntry* k, int D);
-hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
-}  // namespace tabnet
+#include "tabnet_handle.hpp"
 
 using namespace tabnet;
-
-struct tabnet_handle {
-  tabnet_config cfg;
-  int precision;
-  int device;
-  Shape shape;
-  const KernelEntry* kernel;
-  unsigned char* d_wts = nullptr;
-  ChunkRec* d_chunks = nullptr;
-  float* d_affine = nullptr;
-  float* d_wfin = nullptr;
-  int n_chunks = 0;
-  bool failed = false;
-};
 
 namespace {
 thread_local std::string g_err;
@@ -166,26 +146,7 @@ tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float*
   if (!X || !logits || !masks_agg) return fail(TABNET_E_INVALID, "tabnet_forward: NULL X, logits or masks_agg");
   tabnet_status st = ensure_device(h);
   if (st != TABNET_OK) return st;
-  FwdArgs a;
-  a.X = X;
-  a.logits = logits;
-  a.masks_agg = masks_agg;
-  a.masks_step = masks_step;
-  a.wts = h->d_wts;
-  a.chunks = h->d_chunks;
-  a.n_chunks = h->n_chunks;
-  a.in_affine = h->d_affine;
-  a.wfin = h->d_wfin;
-  a.B = B;
-  a.D = h->cfg.D;
-  a.n_d = h->cfg.n_d;
-  a.n_a = h->cfg.n_a;
-  a.n_steps = h->cfg.n_steps;
-  a.n_sh = h->cfg.n_shared;
-  a.n_ind = h->cfg.n_indep;
-  a.n_out = h->cfg.n_out;
-  a.gamma = (float)h->cfg.gamma;
-  hipError_t e = launch_forward(h->kernel, a, (hipStream_t)stream);
+  hipError_t e = tabnet::enqueue_forward(h, X, B, nullptr, logits, masks_agg, masks_step, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(h, e, "tabnet_forward: kernel launch");
   return TABNET_OK;
 }
@@ -198,3 +159,39 @@ void tabnet_free(tabnet_handle* h) {
 }
 
 }  // extern "C"
+
+namespace tabnet {
+
+FwdArgs forward_args(const tabnet_handle* h, const float* X, int64_t B, const int64_t* B_dev,
+                     float* logits, float* masks_agg, float* masks_step) {
+  FwdArgs a;
+  a.X = X;
+  a.logits = logits;
+  a.masks_agg = masks_agg;
+  a.masks_step = masks_step;
+  a.wts = h->d_wts;
+  a.chunks = h->d_chunks;
+  a.n_chunks = h->n_chunks;
+  a.in_affine = h->d_affine;
+  a.wfin = h->d_wfin;
+  a.B = B;
+  a.B_dev = B_dev;
+  a.D = h->cfg.D;
+  a.n_d = h->cfg.n_d;
+  a.n_a = h->cfg.n_a;
+  a.n_steps = h->cfg.n_steps;
+  a.n_sh = h->cfg.n_shared;
+  a.n_ind = h->cfg.n_indep;
+  a.n_out = h->cfg.n_out;
+  a.gamma = (float)h->cfg.gamma;
+  return a;
+}
+
+hipError_t enqueue_forward(const tabnet_handle* h, const float* X, int64_t B, const int64_t* B_dev,
+                           float* logits, float* masks_agg, float* masks_step, hipStream_t stream) {
+  return launch_forward(h->kernel, forward_args(h, X, B, B_dev, logits, masks_agg, masks_step), stream);
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace tabnet

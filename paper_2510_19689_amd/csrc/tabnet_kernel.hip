@@ -152,6 +152,12 @@ __device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC
 
 // ------------------------------------------------------------------------------------
 // Double-buffered weight stream through LDS, shared by the W waves of a workgroup.
+// With TABNET_LDS_DMA the chunk goes straight from global memory into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes base + 16 l); otherwise it is staged
+// through registers and stored with ds_write.
+#ifndef TABNET_LDS_DMA
+#define TABNET_LDS_DMA 1
+#endif
 template <int W, int BUF>
 struct WeightStream {
   static constexpr int T = 64 * W;
@@ -160,24 +166,43 @@ struct WeightStream {
   const unsigned char* wts;
   const ChunkRec* tab;
   int n, idx, cur, next_bytes;
+#if !TABNET_LDS_DMA
   f4 stg[NSTG];
+#endif
 
-  // Issue the global loads of the chunk after the current one into registers.
+  // Issue the global loads of the chunk after the current one.
   __device__ __forceinline__ void begin() {
     next_bytes = 0;
     if (idx + 1 < n) {
       const ChunkRec r = tab[idx + 1];
-      const f4* src = reinterpret_cast<const f4*>(wts + r.off);
       next_bytes = r.bytes;
+#if TABNET_LDS_DMA
+      const unsigned char* src = wts + r.off;
+      unsigned char* dst = lds + (cur ^ 1) * BUF;
+      const int wave = (int)threadIdx.x >> 6;
+#pragma unroll
+      for (int j = 0; j < NSTG; ++j) {
+        const int p = (int)threadIdx.x + j * T;
+        if (p * 16 < next_bytes)
+          __builtin_amdgcn_global_load_lds(
+              (const void __attribute__((address_space(1)))*)(src + (size_t)p * 16),
+              (void __attribute__((address_space(3)))*)(dst + (j * T + wave * 64) * 16), 16, 0, 0);
+      }
+#else
+      const f4* src = reinterpret_cast<const f4*>(wts + r.off);
 #pragma unroll
       for (int j = 0; j < NSTG; ++j) {
         const int p = (int)threadIdx.x + j * T;
         if (p * 16 < next_bytes) stg[j] = src[p];
       }
+#endif
     }
   }
-  // Store them into the other buffer, wait for the whole workgroup, switch buffers.
+  // Complete them, wait for the whole workgroup, switch buffers.
   __device__ __forceinline__ void end() {
+#if TABNET_LDS_DMA
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#else
     if (idx + 1 < n) {
       unsigned char* dst = lds + (cur ^ 1) * BUF;
 #pragma unroll
@@ -186,6 +211,7 @@ struct WeightStream {
         if (p * 16 < next_bytes) *reinterpret_cast<f4*>(dst + p * 16) = stg[j];
       }
     }
+#endif
     lds_block_sync();
     cur ^= 1;
     ++idx;
@@ -268,13 +294,16 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
+  const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
+  // A workgroup past the live rows leaves before its first barrier (all its waves alike).
+  if ((int64_t)blockIdx.x * (16 * R * W) >= B) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int rl = lane & 15;
   const int D = A.D, n_d = A.n_d;
   const int64_t wrow0 = ((int64_t)blockIdx.x * W + wave) * (16 * R);   // first row of this wave
-  const int live_rows = (int)(A.B - wrow0 < 0 ? 0 : (A.B - wrow0 > 16 * R ? 16 * R : A.B - wrow0));
+  const int live_rows = (int)(B - wrow0 < 0 ? 0 : (B - wrow0 > 16 * R ? 16 * R : B - wrow0));
   float* stage = reinterpret_cast<float*>(smem + 2 * PL.buf) + (size_t)wave * 16 * R * D;
   bool live[R];
 #pragma unroll
@@ -348,7 +377,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
   }
 
-  const int64_t step_stride = A.B * (int64_t)D;
+  const int64_t step_stride = B * (int64_t)D;
   for (int s = 1; s <= A.n_steps; ++s) {
     // ---- attentive transformer: z = P * (a W_att'^T + b_att') ----
     {
@@ -552,6 +581,12 @@ struct KernelEntry {
   Plan plan;
 };
 
+#ifndef TABNET_ADULT_R
+#define TABNET_ADULT_R 1
+#endif
+#ifndef TABNET_ADULT_W
+#define TABNET_ADULT_W 8
+#endif
 #define TABNET_SHAPE(P, DT, NT, KA0, R, W) \
   {P, DT, NT, KA0, R, W, tabnet_forward_kernel<P, DT, NT, KA0, R, W>, make_plan(P, DT, NT, KA0)},
 #define TABNET_SHAPES(P)          \
@@ -560,7 +595,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 3, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 2, 1, 1, 4)  \
-  TABNET_SHAPE(P, 7, 4, 2, 1, 8)  \
+  TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
   TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1)};

@@ -101,7 +101,8 @@ struct FwdArgs {
   const ChunkRec* chunks;     // consumption order
   const float* in_affine;     // [2][16*DT]: input BN scale then shift, zero-padded
   const float* wfin;          // [n_out][n_d] float32
-  int64_t B;
+  int64_t B;                  // rows (grid size); the live count if B_dev is null
+  const int64_t* B_dev;       // if set: live row count in device memory, <= B
   int D, n_d, n_a, n_steps, n_sh, n_ind, n_out, n_chunks;
   float gamma;
 };

@@ -11,7 +11,7 @@ import os
 from typing import Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtabnet.so")
+LIB_PATH = os.environ.get("TABNET_LIB") or os.path.join(HERE, "libtabnet.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_IO, E_ADMISSION, E_TIMEOUT, E_STOPPED, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
