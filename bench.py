@@ -65,14 +65,111 @@ def cpu_baseline(params, X, budget_s: float = 12.0):
     from oracle import tabnet as oracle
     chunk = 8192
     done, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < X.shape[0]:
-        oracle.forward(params, X[done:done + chunk])
-        done += min(chunk, X.shape[0] - done)
+    while time.perf_counter() - t0 < budget_s:      # cycles over the batch until the budget
+        start = done % X.shape[0]
+        n = min(chunk, X.shape[0] - start)
+        oracle.forward(params, X[start:start + n])
+        done += n
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": done / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {done} of the {X.shape[0]} benchmark rows, FP64 numpy oracle in "
-                      f"{chunk}-row chunks, {dt:.1f} s"}
+            "sample": f"{done} rows ({done / X.shape[0]:.2f} passes over the {X.shape[0]} benchmark "
+                      f"rows), FP64 numpy oracle in {chunk}-row chunks, {dt:.1f} s"}
+
+
+def _ring_alloc(spans, head: int, need: int, size: int):
+    """First-in-first-out ring of output space: spans holds (start, end, id) of the live
+    allocations in order; returns the start of a free contiguous run or None."""
+    if need > size:
+        raise ValueError("request larger than the output ring")
+    if not spans:
+        return 0
+    tail = spans[0][0]
+    if head > tail or (head == tail and not spans):   # live region [tail, head) does not wrap
+        if head + need <= size:
+            return head
+        return 0 if need <= tail else None
+    return head if head + need <= tail else None      # wrapped: free run is [head, tail)
+
+
+def serve_bench(model, Xpool, rates, warm_s: float, dur_s: float, step_masks: bool = False):
+    """Open-loop Poisson load against the continuous-batching server (one model).
+
+    Request sizes are log-uniform over 1..4096 rows; arrivals and sizes come from the
+    seeded request stream.  Latency is measured by the library from each request's
+    scheduled arrival to the completion of its copy-out, so a late submission counts
+    against the server (no coordinated omission)."""
+    import collections
+    import threading
+
+    import numpy as np
+    from paper_2510_19689_amd import synth, tabnet
+
+    cfg = model.config
+    per_row = cfg.n_out + cfg.D + (cfg.n_steps * cfg.D if step_masks else 0)
+    RING = 1 << 26                      # floats of output space in flight (256 MiB)
+    out = []
+    for lam in rates:
+        t_arr, rows = synth.request_stream(lam, warm_s + dur_s, seed=synth.REQUEST_SEED)
+        ring = np.empty(RING, np.float32)
+        spans = collections.deque()      # (start, end, req_id) in submission order
+        lock = threading.Condition()
+        head = [0]
+        done_sub = [False]
+        with tabnet.Server([model], max_rows_per_launch=65536, slots=3, with_step_masks=step_masks) as srv:
+            def waiter():
+                while True:
+                    with lock:
+                        while not spans and not done_sub[0]:
+                            lock.wait()
+                        if not spans:
+                            return
+                        rid = spans[0][2]
+                    srv.wait(rid)
+                    with lock:
+                        spans.popleft()
+                        lock.notify_all()
+            th = threading.Thread(target=waiter)
+            th.start()
+            start = srv.now_ns() + 2_000_000
+            measured_from = int(np.searchsorted(t_arr, warm_s))
+            rows_meas = 0
+            for i, (ta, r) in enumerate(zip(t_arr, rows)):
+                r = int(r)
+                if i == measured_from:
+                    srv.reset_stats()
+                need = r * per_row
+                with lock:
+                    while (base := _ring_alloc(spans, head[0], need, RING)) is None:
+                        lock.wait()
+                lo = ring[base:base + r * cfg.n_out].reshape(r, cfg.n_out)
+                ag = ring[base + r * cfg.n_out:base + r * (cfg.n_out + cfg.D)].reshape(r, cfg.D)
+                ms = (ring[base + r * (cfg.n_out + cfg.D):base + need].reshape(cfg.n_steps, r, cfg.D)
+                      if step_masks else None)
+                off = (i * 7919) % (Xpool.shape[0] - r)
+                target = start + int(ta * 1e9)
+                while srv.now_ns() < target:
+                    pass
+                rid = srv.submit(0, Xpool[off:off + r], lo, ag, ms, arrival_ns=target)
+                if i >= measured_from:
+                    rows_meas += r
+                with lock:
+                    spans.append((base, base + need, rid))
+                    head[0] = base + need
+                    lock.notify_all()
+            with lock:
+                done_sub[0] = True
+                lock.notify_all()
+            th.join()
+            st = srv.stats()
+        out.append({"rate_req_s": lam, "requests": int(st["completed"]), "offered_rows_per_s": rows_meas / dur_s,
+                    "rows_per_s": st["rows_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
+                    "p999_ms": st["p999_us"] / 1e3, "mean_rows_per_launch": st["mean_rows_per_launch"],
+                    "launches": int(st["launches"])})
+        print(f"[bench] serve {lam} req/s: p50 {st['p50_us']/1e3:.3f} ms p99 {st['p99_us']/1e3:.3f} ms "
+              f"{st['rows_per_s']/1e6:.2f} M rows/s, {st['mean_rows_per_launch']:.0f} rows/launch",
+              file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -83,6 +180,9 @@ def main():
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
+                    help="request rates (req/s) of the serving leg; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of TabNet, time a plain device-to-device copy of this many "
                          "bytes (the reference for scaling HBM byte counters)")
@@ -130,6 +230,12 @@ def main():
                 res[prec] = (t, wall)
                 print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
                       f"{rows * args.steps / t / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
+                del outs
+        serving = None
+        if args.serve_rates:
+            rates = [int(r) for r in args.serve_rates.split(",") if r]
+            with tabnet.Model(path, "bf16") as m:
+                serving = serve_bench(m, Xh, rates, warm_s=0.5, dur_s=args.serve_seconds)
     t_bf16, wall_bf16 = res["bf16"]
     per_launch = t_bf16 / args.steps
     value = rows * args.steps / t_bf16
@@ -164,6 +270,10 @@ def main():
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
     out["wall_s_bf16"] = wall_bf16
+    if serving is not None:
+        out["serving"] = {"model": name, "precision": "bf16", "masks": "logits + masks_agg",
+                          "request_rows": "log-uniform 1..4096", "arrivals": "Poisson, open loop",
+                          "points": serving}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, Xh)
     print(json.dumps(out), flush=True)

@@ -38,6 +38,15 @@ tabnet_status tabnet_hook_fold(const void* buf, size_t len, int layer, double* W
 tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precision,
                                        int64_t* wts_bytes, int64_t* n_chunks);
 
+/* A server whose device side is a CPU stand-in (no GPU needed), for testing the
+ * scheduling: admission, ordering, splitting across launches, scattering, cancellation.
+ * Its "model" writes logits[r][o] = X[r][o % D] + o, masks_agg = 2 X and
+ * masks_step[s] = X + s; each launch additionally sleeps delay_us microseconds.
+ * Stop it with tabnet_serve_stop. */
+tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs, int n_models,
+                                           const tabnet_serve_opts* opts, int delay_us,
+                                           tabnet_server** out);
+
 #ifdef __cplusplus
 }
 #endif

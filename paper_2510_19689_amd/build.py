@@ -25,6 +25,9 @@ SOURCES = [
     "tabnet_pack.cpp",
     "tabnet_api.cpp",
     "tabnet_hooks.cpp",
+    "tabnet_serve.cpp",
+    "tabnet_serve_exec.cpp",
+    "tabnet_serve_fake.cpp",
 ]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall",

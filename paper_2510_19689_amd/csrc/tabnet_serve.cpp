@@ -1,0 +1,402 @@
+// Serving runtime: continuous batching of variable-row requests onto the fused forward.
+//
+// The paper serves TabNet per invocation with a batch size chosen at invocation time
+// (Sec. III-B) and names dynamic batching as its next optimisation (Sec. VI-D).  Here:
+//
+//   submit (any thread)  ->  pending queue (FIFO)
+//   scheduler thread     ->  admits pending requests in order while their bytes fit the
+//                            budget; packs admitted rows (a request may be split) into a
+//                            free slot's pinned input buffer; the executor enqueues
+//                            copy-in, the forward and copy-out on the slot's stream
+//   completion thread    ->  takes slots in launch order, waits for their copy-out,
+//                            copies each slice to its request's buffers, completes
+//                            requests, returns bytes to the budget and the slot to the pool
+//
+// The device work sits behind an Executor interface: the HIP executor owns the streams,
+// device and pinned buffers and (optionally) one captured graph per slot and model; a
+// fake executor lets the scheduling logic run on a machine without a GPU.
+#include "tabnet_serve.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace tabnet {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+namespace {
+
+enum class ReqState { Pending, Admitted, Done, Cancelled, Failed };
+
+struct Request {
+  uint64_t id;
+  int model;
+  int64_t rows;
+  std::vector<float> X;          // copied at submit
+  float* logits;
+  float* magg;
+  float* msteps;                 // may be null
+  int64_t arrival_ns;
+  uint64_t bytes;
+  int64_t rows_launched = 0;
+  int64_t rows_done = 0;
+  ReqState state = ReqState::Pending;
+};
+
+struct Segment {                 // rows [src_row, src_row + rows) of a request, at slot row dst_row
+  std::shared_ptr<Request> req;
+  int64_t src_row, rows, dst_row;
+};
+
+struct Launch {
+  int slot;
+  int model;
+  int64_t rows;
+  std::vector<Segment> segs;
+};
+
+}  // namespace
+
+struct ServerImpl {
+  std::vector<ModelInfo> models;
+  Executor* exec = nullptr;
+  tabnet_serve_opts opts;
+  uint64_t budget;
+  int64_t max_rows;
+  int nslots;
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_comp, cv_done;
+  std::deque<std::shared_ptr<Request>> pending;      // not yet admitted
+  std::deque<std::shared_ptr<Request>> admitted;     // admitted, rows left to launch
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> live;
+  std::deque<Launch> inflight;                       // launch order
+  std::vector<int> free_slots;
+  uint64_t next_id = 1;
+  uint64_t inflight_bytes = 0, peak_bytes = 0;
+  bool stopping = false, sched_exited = false;
+  int waiters = 0;               // threads inside server_wait
+
+  // statistics since the last reset
+  uint64_t n_sub = 0, n_adm = 0, n_done = 0, n_rej = 0, n_cancel = 0, rows_done = 0, launches = 0;
+  uint64_t launched_rows = 0;
+  int64_t first_arrival = 0, last_done = 0;
+  std::vector<double> lat_us;
+
+  std::thread sched_thr, comp_thr;
+
+  uint64_t req_bytes(int model, int64_t rows) const {
+    return (uint64_t)rows * models[model].bytes_per_row;
+  }
+
+  void scheduler() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      // admission: FIFO, stop at the first request that does not fit
+      while (!pending.empty() && inflight_bytes + pending.front()->bytes <= budget) {
+        auto r = pending.front();
+        pending.pop_front();
+        r->state = ReqState::Admitted;
+        inflight_bytes += r->bytes;
+        peak_bytes = std::max(peak_bytes, inflight_bytes);
+        ++n_adm;
+        admitted.push_back(r);
+      }
+      if (stopping && admitted.empty()) break;
+      if (admitted.empty() || free_slots.empty()) {
+        cv_sched.wait(lk);
+        continue;
+      }
+      Launch L;
+      L.slot = free_slots.back();
+      free_slots.pop_back();
+      L.model = admitted.front()->model;
+      L.rows = 0;
+      while (!admitted.empty() && L.rows < max_rows && admitted.front()->model == L.model) {
+        auto r = admitted.front();
+        const int64_t take = std::min(r->rows - r->rows_launched, max_rows - L.rows);
+        L.segs.push_back(Segment{r, r->rows_launched, take, L.rows});
+        r->rows_launched += take;
+        L.rows += take;
+        if (r->rows_launched == r->rows) admitted.pop_front();
+      }
+      lk.unlock();
+      // gather the rows into the slot's input buffer and enqueue the launch
+      const int D = models[L.model].cfg.D;
+      float* in = exec->input(L.slot);
+      for (const Segment& sg : L.segs)
+        std::memcpy(in + sg.dst_row * D, sg.req->X.data() + sg.src_row * D, (size_t)sg.rows * D * sizeof(float));
+      const bool ok = exec->launch(L.slot, L.model, L.rows);
+      lk.lock();
+      ++launches;
+      launched_rows += L.rows;
+      if (!ok) {
+        for (Segment& sg : L.segs) fail_request(sg.req);
+        free_slots.push_back(L.slot);
+        continue;
+      }
+      inflight.push_back(std::move(L));
+      cv_comp.notify_one();
+    }
+    sched_exited = true;
+    cv_comp.notify_all();
+  }
+
+  void fail_request(const std::shared_ptr<Request>& r) {   // mu held
+    if (r->state == ReqState::Failed) return;
+    if (r->state == ReqState::Admitted) inflight_bytes -= r->bytes;
+    r->state = ReqState::Failed;
+    cv_done.notify_all();
+  }
+
+  void completer() {
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      if (inflight.empty()) {
+        if (sched_exited) break;
+        cv_comp.wait(lk);
+        continue;
+      }
+      Launch L = std::move(inflight.front());
+      inflight.pop_front();
+      lk.unlock();
+      const bool ok = exec->wait(L.slot);
+      const ModelInfo& mi = models[L.model];
+      const int D = mi.cfg.D, n_out = mi.cfg.n_out, S = mi.cfg.n_steps;
+      if (ok) {
+        const float* lo = exec->out_logits(L.slot);
+        const float* ag = exec->out_agg(L.slot);
+        const float* ms = exec->out_steps(L.slot);
+        for (const Segment& sg : L.segs) {
+          Request& r = *sg.req;
+          std::memcpy(r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4);
+          std::memcpy(r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4);
+          if (r.msteps && ms)
+            for (int s = 0; s < S; ++s)
+              std::memcpy(r.msteps + ((int64_t)s * r.rows + sg.src_row) * D,
+                          ms + ((int64_t)s * L.rows + sg.dst_row) * D, (size_t)sg.rows * D * 4);
+        }
+      }
+      const int64_t t = now_ns();
+      lk.lock();
+      for (const Segment& sg : L.segs) {
+        Request& r = *sg.req;
+        if (!ok) {
+          fail_request(sg.req);
+          continue;
+        }
+        r.rows_done += sg.rows;
+        if (r.rows_done == r.rows && r.state == ReqState::Admitted) {
+          r.state = ReqState::Done;
+          inflight_bytes -= r.bytes;
+          ++n_done;
+          rows_done += (uint64_t)r.rows;
+          lat_us.push_back((double)(t - r.arrival_ns) * 1e-3);
+          last_done = std::max(last_done, t);
+          r.X.clear();
+          r.X.shrink_to_fit();
+        }
+      }
+      free_slots.push_back(L.slot);
+      cv_done.notify_all();
+      cv_sched.notify_one();
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------------
+tabnet_status server_create(std::vector<ModelInfo> models, Executor* exec, const tabnet_serve_opts& o,
+                            ServerImpl** out) {
+  ServerImpl* s = new ServerImpl();
+  s->models = std::move(models);
+  s->exec = exec;
+  s->opts = o;
+  s->budget = o.mem_budget_bytes;
+  s->max_rows = o.max_rows_per_launch;
+  s->nslots = o.slots;
+  for (int i = s->nslots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  s->sched_thr = std::thread([s] { s->scheduler(); });
+  s->comp_thr = std::thread([s] { s->completer(); });
+  *out = s;
+  return TABNET_OK;
+}
+
+tabnet_status server_submit(ServerImpl* s, int model, const float* X, int64_t rows, float* logits,
+                            float* magg, float* msteps, int64_t arrival_ns, uint64_t* id) {
+  if (!s || !X || !logits || !magg || !id || rows <= 0 || model < 0 || model >= (int)s->models.size()) {
+    set_error("tabnet_serve_submit: invalid argument");
+    return TABNET_E_INVALID;
+  }
+  const ModelInfo& mi = s->models[model];
+  auto r = std::make_shared<Request>();
+  r->model = model;
+  r->rows = rows;
+  r->logits = logits;
+  r->magg = magg;
+  r->msteps = s->opts.with_step_masks ? msteps : nullptr;
+  r->arrival_ns = arrival_ns > 0 ? arrival_ns : now_ns();
+  r->bytes = s->req_bytes(model, rows);
+  if (r->bytes > s->budget) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->n_rej;
+    set_error("tabnet_serve_submit: request larger than the memory budget");
+    return TABNET_E_ADMISSION;
+  }
+  r->X.assign(X, X + (size_t)rows * mi.cfg.D);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stopping) {
+    set_error("tabnet_serve_submit: server stopped");
+    return TABNET_E_STOPPED;
+  }
+  r->id = s->next_id++;
+  *id = r->id;
+  if (s->n_sub == 0 || r->arrival_ns < s->first_arrival) s->first_arrival = r->arrival_ns;
+  ++s->n_sub;
+  s->live[r->id] = r;
+  s->pending.push_back(r);
+  s->cv_sched.notify_one();
+  return TABNET_OK;
+}
+
+static tabnet_status state_status(ReqState st) {
+  switch (st) {
+    case ReqState::Done: return TABNET_OK;
+    case ReqState::Cancelled: return TABNET_E_STOPPED;
+    case ReqState::Failed: return TABNET_E_HIP;
+    default: return TABNET_E_TIMEOUT;
+  }
+}
+
+tabnet_status server_wait(ServerImpl* s, uint64_t id, int64_t timeout_us) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(id);
+  if (it == s->live.end()) {
+    set_error("tabnet_serve_wait: unknown request id");
+    return TABNET_E_INVALID;
+  }
+  std::shared_ptr<Request> r = it->second;
+  auto finished = [&] { return r->state != ReqState::Pending && r->state != ReqState::Admitted; };
+  ++s->waiters;
+  bool ok = true;
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, finished);
+  } else {
+    ok = s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), finished);
+  }
+  --s->waiters;
+  s->cv_done.notify_all();
+  if (!ok) {
+    set_error("tabnet_serve_wait: timed out");
+    return TABNET_E_TIMEOUT;
+  }
+  s->live.erase(id);
+  const tabnet_status st = state_status(r->state);
+  if (st != TABNET_OK) set_error("tabnet_serve_wait: request cancelled or failed");
+  return st;
+}
+
+tabnet_status server_poll(ServerImpl* s, uint64_t id, int* done) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->live.find(id);
+  if (it == s->live.end()) {
+    set_error("tabnet_serve_poll: unknown request id");
+    return TABNET_E_INVALID;
+  }
+  const ReqState st = it->second->state;
+  if (st == ReqState::Pending || st == ReqState::Admitted) {
+    *done = 0;
+    return TABNET_OK;
+  }
+  *done = 1;
+  s->live.erase(it);
+  return state_status(st);
+}
+
+static double pct(std::vector<double>& v, double p) {
+  if (v.empty()) return 0.0;
+  const size_t k = std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5));
+  std::nth_element(v.begin(), v.begin() + k, v.end());
+  return v[k];
+}
+
+tabnet_status server_stats(ServerImpl* s, tabnet_serve_stats* o) {
+  std::vector<double> lat;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(o, 0, sizeof *o);
+    o->submitted = s->n_sub;
+    o->admitted = s->n_adm;
+    o->completed = s->n_done;
+    o->rejected = s->n_rej;
+    o->cancelled = s->n_cancel;
+    o->rows_completed = s->rows_done;
+    o->launches = s->launches;
+    o->mean_rows_per_launch = s->launches ? (double)s->launched_rows / (double)s->launches : 0.0;
+    o->inflight_bytes = s->inflight_bytes;
+    o->peak_inflight_bytes = s->peak_bytes;
+    const double span = (double)(s->last_done - s->first_arrival) * 1e-9;
+    o->rows_per_s = (s->n_done && span > 0) ? (double)s->rows_done / span : 0.0;
+    lat = s->lat_us;
+  }
+  if (!lat.empty()) {
+    double sum = 0, mx = 0;
+    for (double x : lat) {
+      sum += x;
+      mx = std::max(mx, x);
+    }
+    o->mean_us = sum / (double)lat.size();
+    o->max_us = mx;
+    o->p50_us = pct(lat, 0.50);
+    o->p99_us = pct(lat, 0.99);
+    o->p999_us = pct(lat, 0.999);
+  }
+  return TABNET_OK;
+}
+
+tabnet_status server_reset_stats(ServerImpl* s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->n_sub = s->n_adm = s->n_done = s->n_rej = s->n_cancel = s->rows_done = s->launches = 0;
+  s->launched_rows = 0;
+  s->first_arrival = s->last_done = 0;
+  s->lat_us.clear();
+  s->peak_bytes = s->inflight_bytes;
+  return TABNET_OK;
+}
+
+tabnet_status server_stop(ServerImpl* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    for (auto& r : s->pending) {
+      r->state = ReqState::Cancelled;
+      ++s->n_cancel;
+    }
+    s->pending.clear();
+    s->cv_sched.notify_all();
+    s->cv_done.notify_all();
+  }
+  s->sched_thr.join();     // drains the admitted rows
+  s->comp_thr.join();      // completes the launches in flight
+  {
+    // every request is now finished; let threads blocked in server_wait leave first
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.notify_all();
+    s->cv_done.wait(lk, [s] { return s->waiters == 0; });
+  }
+  delete s->exec;
+  delete s;
+  return TABNET_OK;
+}
+
+}  // namespace tabnet

@@ -1,0 +1,69 @@
+// CPU stand-in executor of the serving runtime (no HIP): the scheduler's admission,
+// ordering, splitting and scattering can be tested, and sanitised, without a GPU.
+#include <algorithm>
+#include <chrono>
+#include <thread>
+#include <vector>
+
+#include "tabnet_serve.hpp"
+
+namespace tabnet {
+namespace {
+
+// ---------------------------------------------------------------- fake executor
+// Runs on the CPU: logits[r][o] = X[r][o % D] + o, masks_agg[r][j] = 2 X[r][j],
+// masks_step[s][r][j] = X[r][j] + s.  It exercises batching, splitting and scattering.
+class FakeExecutor : public Executor {
+ public:
+  std::vector<ModelInfo> models;
+  tabnet_serve_opts o;
+  Dims dm;
+  int delay_us = 0;
+  struct Slot {
+    std::vector<float> x, lo, ag, ms;
+  };
+  std::vector<Slot> slots;
+
+  void init() {
+    dm = max_dims(models);
+    const size_t R = (size_t)o.max_rows_per_launch;
+    slots.resize(o.slots);
+    for (Slot& s : slots) {
+      s.x.resize(R * dm.D);
+      s.lo.resize(R * dm.n_out);
+      s.ag.resize(R * dm.D);
+      if (o.with_step_masks) s.ms.resize(R * dm.S * dm.D);
+    }
+  }
+  float* input(int slot) override { return slots[slot].x.data(); }
+  bool launch(int slot, int model, int64_t rows) override {
+    Slot& s = slots[slot];
+    const int D = models[model].cfg.D, n_out = models[model].cfg.n_out, S = models[model].cfg.n_steps;
+    for (int64_t r = 0; r < rows; ++r) {
+      for (int oo = 0; oo < n_out; ++oo) s.lo[r * n_out + oo] = s.x[r * D + oo % D] + (float)oo;
+      for (int j = 0; j < D; ++j) s.ag[r * D + j] = 2.f * s.x[r * D + j];
+      if (!s.ms.empty())
+        for (int st = 0; st < S; ++st)
+          for (int j = 0; j < D; ++j) s.ms[((int64_t)st * rows + r) * D + j] = s.x[r * D + j] + (float)st;
+    }
+    if (delay_us > 0) std::this_thread::sleep_for(std::chrono::microseconds(delay_us));
+    return true;
+  }
+  bool wait(int) override { return true; }
+  const float* out_logits(int slot) override { return slots[slot].lo.data(); }
+  const float* out_agg(int slot) override { return slots[slot].ag.data(); }
+  const float* out_steps(int slot) override { return slots[slot].ms.empty() ? nullptr : slots[slot].ms.data(); }
+};
+
+}  // namespace
+
+Executor* make_fake_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, int delay_us) {
+  FakeExecutor* x = new FakeExecutor();
+  x->models = models;
+  x->o = o;
+  x->delay_us = delay_us;
+  x->init();
+  return x;
+}
+
+}  // namespace tabnet

@@ -33,6 +33,23 @@ class Config(ctypes.Structure):
                 ("bn_eps", ctypes.c_double)]
 
 
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_rows_per_launch", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("with_step_masks", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "rejected",
+                                                "cancelled", "rows_completed", "launches")] + \
+               [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "p999_us", "max_us", "mean_us",
+                                                "rows_per_s", "mean_rows_per_launch")] + \
+               [("inflight_bytes", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -72,6 +89,25 @@ def lib() -> ctypes.CDLL:
     L.tabnet_hook_packed_sizes.argtypes = [vp, ctypes.c_size_t, i32,
                                            ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.tabnet_hook_packed_sizes.restype = i32
+    L.tabnet_serve_start.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
+    L.tabnet_serve_start.restype = i32
+    L.tabnet_hook_serve_start_fake.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ServeOpts), i32,
+                                               ctypes.POINTER(vp)]
+    L.tabnet_hook_serve_start_fake.restype = i32
+    L.tabnet_serve_submit.argtypes = [vp, i32, vp, i64, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
+    L.tabnet_serve_submit.restype = i32
+    L.tabnet_serve_wait.argtypes = [vp, ctypes.c_uint64, i64]
+    L.tabnet_serve_wait.restype = i32
+    L.tabnet_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    L.tabnet_serve_poll.restype = i32
+    L.tabnet_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.tabnet_serve_get_stats.restype = i32
+    L.tabnet_serve_reset_stats.argtypes = [vp]
+    L.tabnet_serve_reset_stats.restype = i32
+    L.tabnet_serve_now_ns.argtypes = []
+    L.tabnet_serve_now_ns.restype = i64
+    L.tabnet_serve_stop.argtypes = [vp]
+    L.tabnet_serve_stop.restype = i32
     _lib = L
     return L
 
@@ -149,3 +185,68 @@ class Model:
         lo, ag, ms = self.outputs(int(X.shape[0]), with_steps)
         self.forward_into(X, lo, ag, ms, stream)
         return lo, ag, ms
+
+
+class Server:
+    """Continuous-batching server over resident models (tabnet_serve_*).
+
+    Host buffers passed to submit() must stay alive until the request is waited on;
+    the caller keeps references (numpy arrays) for that long.
+    """
+
+    def __init__(self, models=None, mem_budget_bytes: int = 0, max_rows_per_launch: int = 0,
+                 slots: int = 0, with_step_masks: bool = False, use_graph: bool = True,
+                 fake_configs=None, fake_delay_us: int = 0):
+        o = ServeOpts(mem_budget_bytes=mem_budget_bytes, max_rows_per_launch=max_rows_per_launch,
+                      slots=slots, with_step_masks=int(with_step_masks), use_graph=int(use_graph))
+        h = ctypes.c_void_p()
+        if fake_configs is not None:
+            arr = (Config * len(fake_configs))(*fake_configs)
+            check(lib().tabnet_hook_serve_start_fake(arr, len(fake_configs), ctypes.byref(o),
+                                                     fake_delay_us, ctypes.byref(h)))
+            self.configs = list(fake_configs)
+        else:
+            hs = (ctypes.c_void_p * len(models))(*[m.handle.value for m in models])
+            check(lib().tabnet_serve_start(hs, len(models), ctypes.byref(o), ctypes.byref(h)))
+            self.configs = [m.config for m in models]
+        self._s = h
+        self.with_step_masks = with_step_masks
+
+    def submit(self, model: int, X, logits, masks_agg, masks_step=None, arrival_ns: int = 0) -> int:
+        rid = ctypes.c_uint64()
+        check(lib().tabnet_serve_submit(self._s, model, X.ctypes.data, int(X.shape[0]), logits.ctypes.data,
+                                        masks_agg.ctypes.data,
+                                        None if masks_step is None else masks_step.ctypes.data,
+                                        int(arrival_ns), ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, timeout_us: int = -1) -> int:
+        return lib().tabnet_serve_wait(self._s, rid, timeout_us)
+
+    def poll(self, rid: int):
+        d = ctypes.c_int()
+        st = lib().tabnet_serve_poll(self._s, rid, ctypes.byref(d))
+        return st, bool(d.value)
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        check(lib().tabnet_serve_get_stats(self._s, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self) -> None:
+        check(lib().tabnet_serve_reset_stats(self._s))
+
+    @staticmethod
+    def now_ns() -> int:
+        return lib().tabnet_serve_now_ns()
+
+    def stop(self) -> None:
+        if self._s is not None and self._s.value:
+            check(lib().tabnet_serve_stop(self._s))
+            self._s = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

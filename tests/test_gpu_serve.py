@@ -1,0 +1,102 @@
+"""GPU serving: continuous batching must not change any request's result.
+
+Requests of random sizes (some larger than one launch, so they are split) are served
+in a mix; each request's logits and masks must be bit-identical to a tabnet_forward of
+that request alone, and a sample is checked against the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import tabnet as oracle  # noqa: E402
+from paper_2510_19689_amd import synth, tabnet as tb  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def models(tmp_path_factory):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    d = tmp_path_factory.mktemp("serve")
+    out = {}
+    for name in ("adult108", "hr35"):
+        p = synth.make_params(synth.WORKLOADS[name]["cfg"], synth.WEIGHT_SEED[name])
+        path = str(d / f"{name}.tnw")
+        synth.write_weights(p, path)
+        out[name] = (p, path)
+    return out
+
+
+def alone(model, X):
+    lo, ag, ms = model.forward(torch.from_numpy(X).cuda())
+    torch.cuda.synchronize()
+    return lo.cpu().numpy(), ag.cpu().numpy(), ms.cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_mix_equals_alone(models, use_graph):
+    pa, path_a = models["adult108"]
+    ph, path_h = models["hr35"]
+    _say(f"case serve mix use_graph={use_graph}")
+    with tb.Model(path_a, "bf16") as ma, tb.Model(path_h, "bf16") as mh:
+        cfgs = [ma.config, mh.config]
+        rng = np.random.default_rng(7)
+        Xa = synth.make_inputs("adult", 20000, 77)
+        Xh = synth.make_inputs("hr", 5000, 78)
+        reqs = []
+        with tb.Server([ma, mh], max_rows_per_launch=2048, slots=3, with_step_masks=True,
+                       use_graph=use_graph) as s:
+            for k in range(120):
+                m = 0 if k % 3 else 1
+                pool = Xa if m == 0 else Xh
+                rows = int(min(np.floor(np.exp(rng.uniform(0, np.log(4097)))), 4096))
+                off = int(rng.integers(0, pool.shape[0] - rows))
+                X = np.ascontiguousarray(pool[off:off + rows])
+                c = cfgs[m]
+                lo = np.full((rows, c.n_out), np.nan, np.float32)
+                ag = np.full((rows, c.D), np.nan, np.float32)
+                ms = np.full((c.n_steps, rows, c.D), np.nan, np.float32)
+                reqs.append((m, X, lo, ag, ms, s.submit(m, X, lo, ag, ms)))
+            for r in reqs:
+                assert s.wait(r[5]) == tb.OK
+            st = s.stats()
+            _say("serve stats", {k: st[k] for k in ("completed", "launches", "mean_rows_per_launch", "p50_us", "p99_us")})
+            assert st["completed"] == len(reqs)
+        for m, X, lo, ag, ms, _ in reqs:
+            a_lo, a_ag, a_ms = alone(ma if m == 0 else mh, X)
+            np.testing.assert_array_equal(lo, a_lo)
+            np.testing.assert_array_equal(ag, a_ag)
+            np.testing.assert_array_equal(ms, a_ms)
+        # a sample against the FP64 oracle (BF16 tolerances)
+        for m, X, lo, ag, ms, _ in reqs[:6]:
+            p = pa if m == 0 else ph
+            rlo, rag, rms = oracle.forward(p, X[:64])
+            assert np.abs(lo[:64] - rlo).max() <= 2e-2
+            assert np.abs(ag[:64] - rag).sum(-1).max() <= 1e-2
+
+
+def test_serve_without_step_masks_and_tiny_requests(models):
+    _, path_a = models["adult108"]
+    _say("case serve tiny requests")
+    with tb.Model(path_a, "fp32") as ma:
+        X = synth.make_inputs("adult", 300, 5)
+        with tb.Server([ma], max_rows_per_launch=64, slots=2) as s:
+            outs = []
+            for r in range(0, 300, 3):
+                x = np.ascontiguousarray(X[r:r + 3])
+                lo = np.empty((3, 2), np.float32)
+                ag = np.empty((3, 108), np.float32)
+                outs.append((r, lo, ag, s.submit(0, x, lo, ag)))
+            for r, lo, ag, i in outs:
+                assert s.wait(i) == tb.OK
+        a_lo, a_ag, _ = alone(ma, X)
+        for r, lo, ag, _ in outs:
+            np.testing.assert_array_equal(lo, a_lo[r:r + 3])
+            np.testing.assert_array_equal(ag, a_ag[r:r + 3])

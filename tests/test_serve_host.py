@@ -1,0 +1,174 @@
+"""Serving runtime on the CPU: the scheduler, admission, splitting and scattering run
+against the library's CPU stand-in executor (no GPU).  The stand-in's "model" writes
+logits[r][o] = X[r][o % D] + o, masks_agg = 2 X and masks_step[s] = X + s."""
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2510_19689_amd import tabnet as tb
+
+
+def cfg(D=7, n_out=3, S=2):
+    c = tb.Config()
+    c.D, c.n_d, c.n_a, c.n_steps, c.n_shared, c.n_indep, c.n_out = D, 4, 4, S, 1, 1, n_out
+    c.gamma, c.bn_eps = 1.3, 1e-5
+    return c
+
+
+def expect(X, c):
+    lo = np.stack([X[:, o % c.D] + o for o in range(c.n_out)], axis=1)
+    return lo, 2 * X, np.stack([X + s for s in range(c.n_steps)])
+
+
+def make_req(rng, rows, c, steps=True):
+    X = rng.normal(0, 1, (rows, c.D)).astype(np.float32)
+    lo = np.full((rows, c.n_out), np.nan, np.float32)
+    ag = np.full((rows, c.D), np.nan, np.float32)
+    ms = np.full((c.n_steps, rows, c.D), np.nan, np.float32) if steps else None
+    return X, lo, ag, ms
+
+
+def check(req, c):
+    X, lo, ag, ms = req
+    elo, eag, ems = expect(X, c)
+    np.testing.assert_array_equal(lo, elo)
+    np.testing.assert_array_equal(ag, eag)
+    if ms is not None:
+        np.testing.assert_array_equal(ms, ems)
+
+
+@pytest.mark.parametrize("max_rows,slots", [(64, 1), (100, 3), (4096, 2)])
+def test_requests_split_batched_and_scattered(max_rows, slots):
+    c = cfg()
+    rng = np.random.default_rng(0)
+    with tb.Server(fake_configs=[c], max_rows_per_launch=max_rows, slots=slots, with_step_masks=True) as s:
+        reqs, ids = [], []
+        for _ in range(60):
+            r = make_req(rng, int(rng.integers(1, 300)), c)
+            reqs.append(r)
+            ids.append(s.submit(0, *r))
+        for i in ids:
+            assert s.wait(i) == tb.OK
+        for r in reqs:
+            check(r, c)
+        st = s.stats()
+        assert st["completed"] == 60 and st["submitted"] == 60
+        assert st["rows_completed"] == sum(r[0].shape[0] for r in reqs)
+        assert st["mean_rows_per_launch"] <= max_rows
+        assert st["p50_us"] > 0 and st["p99_us"] >= st["p50_us"]
+        assert st["inflight_bytes"] == 0
+
+
+def test_two_models_and_optional_step_masks():
+    cs = [cfg(D=5, n_out=2, S=3), cfg(D=11, n_out=4, S=1)]
+    rng = np.random.default_rng(1)
+    with tb.Server(fake_configs=cs, max_rows_per_launch=50, with_step_masks=True) as s:
+        work = []
+        for k in range(40):
+            m = k % 2
+            r = make_req(rng, int(rng.integers(1, 120)), cs[m], steps=(k % 3 != 0))
+            work.append((m, r, s.submit(m, *r)))
+        for m, r, i in work:
+            assert s.wait(i) == tb.OK
+            check(r, cs[m])
+
+
+def test_without_step_masks_server_ignores_them():
+    c = cfg()
+    rng = np.random.default_rng(2)
+    with tb.Server(fake_configs=[c], with_step_masks=False) as s:
+        X, lo, ag, ms = make_req(rng, 10, c)
+        i = s.submit(0, X, lo, ag, ms)
+        assert s.wait(i) == tb.OK
+        check((X, lo, ag, None), c)
+        assert np.isnan(ms).all()
+
+
+def test_admission_budget():
+    c = cfg(D=8, n_out=2, S=2)
+    per_row = 4 * (8 + 2 + 8 + 2 * 8)
+    rng = np.random.default_rng(3)
+    with tb.Server(fake_configs=[c], mem_budget_bytes=per_row * 100, with_step_masks=True,
+                   fake_delay_us=2000) as s:
+        with pytest.raises(tb.TabNetError) as e:
+            s.submit(0, *make_req(rng, 101, c))
+        assert e.value.status == tb.E_ADMISSION
+        reqs = [make_req(rng, 60, c) for _ in range(6)]    # only one fits at a time
+        ids = [s.submit(0, *r) for r in reqs]
+        for i in ids:
+            assert s.wait(i) == tb.OK
+        for r in reqs:
+            check(r, c)
+        st = s.stats()
+        assert st["peak_inflight_bytes"] <= per_row * 100
+        assert st["rejected"] == 1
+
+
+def test_poll_wait_timeout_and_invalid():
+    c = cfg()
+    rng = np.random.default_rng(4)
+    with tb.Server(fake_configs=[c], fake_delay_us=200000, slots=1) as s:
+        r = make_req(rng, 5, c, steps=False)
+        i = s.submit(0, *r)
+        assert s.wait(i, timeout_us=1000) == tb.E_TIMEOUT
+        st, done = s.poll(i)
+        assert st == tb.OK and not done
+        assert s.wait(i) == tb.OK
+        assert s.wait(i) == tb.E_INVALID            # released after completion
+        assert s.wait(12345) == tb.E_INVALID
+        for bad in (dict(model=1), dict(model=-1)):
+            with pytest.raises(tb.TabNetError):
+                s.submit(bad["model"], *r)
+        with pytest.raises(tb.TabNetError):
+            s.submit(0, np.zeros((0, c.D), np.float32), r[1], r[2])
+
+
+def test_concurrent_submitters():
+    c = cfg(D=13, n_out=2, S=2)
+    results = []
+    errors = []
+    with tb.Server(fake_configs=[c], max_rows_per_launch=128, with_step_masks=True) as s:
+        def worker(seed):
+            rng = np.random.default_rng(seed)
+            try:
+                mine = []
+                for _ in range(25):
+                    r = make_req(rng, int(rng.integers(1, 200)), c)
+                    mine.append((r, s.submit(0, *r)))
+                for r, i in mine:
+                    assert s.wait(i) == tb.OK
+                    results.append(r)
+            except Exception as ex:  # pragma: no cover - reported below
+                errors.append(ex)
+        ts = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    assert not errors, errors
+    assert len(results) == 100
+    for r in results:
+        check(r, c)
+
+
+def test_stop_cancels_queued_and_finishes_inflight():
+    c = cfg()
+    rng = np.random.default_rng(5)
+    s = tb.Server(fake_configs=[c], fake_delay_us=50000, slots=1, max_rows_per_launch=8)
+    reqs = [make_req(rng, 8, c, steps=False) for _ in range(5)]
+    ids = [s.submit(0, *r) for r in reqs]
+    statuses = {}
+
+    def waiter(i):
+        statuses[i] = s.wait(i)
+    ts = [threading.Thread(target=waiter, args=(i,)) for i in ids]
+    for t in ts:
+        t.start()
+    s.stop()
+    for t in ts:
+        t.join()
+    assert set(statuses.values()) <= {tb.OK, tb.E_STOPPED}
+    for r, i in zip(reqs, ids):
+        if statuses[i] == tb.OK:
+            check(r, c)
