@@ -84,9 +84,7 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   tabnet_status st = parse_model(img.data(), img.size(), &m, &err);
   if (st != TABNET_OK) return fail(st, "tabnet_load: " + err);
   const Shape sh = shape_of(m.cfg);
-  const int kprec = precision == TABNET_FP32 ? 0 : 1;
-  if (precision == TABNET_FP8_E4M3)
-    return fail(TABNET_E_UNSUPPORTED, "tabnet_load: FP8 E4M3 kernels are not built in this library");
+  const int kprec = precision == TABNET_FP32 ? 0 : (precision == TABNET_BF16 ? 1 : 2);
   const KernelEntry* k = find_kernel(kprec, sh.DT, sh.NT, sh.KA0);
   if (!k) {
     char msg[256];

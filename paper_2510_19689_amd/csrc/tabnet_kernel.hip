@@ -12,26 +12,50 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kSqrtHalf = 0.70710678118654752f;
 constexpr float kNegBig = -3.0e38f;   // score of a padded feature: never in the support
 
-__device__ __forceinline__ float xor_shfl(float v, int m) { return __shfl_xor(v, m, 64); }
-__device__ __forceinline__ int xor_shfl(int v, int m) { return __shfl_xor(v, m, 64); }
+// Cross-lane pairs on the VALU: v_permlane16_swap exchanges rows (16 lanes) 0<->1 and
+// 2<->3, v_permlane32_swap the two halves of the wave.  Called with the same value as
+// both operands, the two results hold {own, partner} in an order that depends on the
+// lane, so their sum (or max) is the pair's sum (max), formed in the same operand order
+// in both lanes of the pair: the four lanes of a row end with bit-identical results.
+__device__ __forceinline__ float pair16_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair16_max(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float pair32_max(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ int pair16_sum(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(r[0] + r[1]);
+}
+__device__ __forceinline__ int pair32_sum(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(r[0] + r[1]);
+}
 
-// Sum / max over the 4 lanes {r, r+16, r+32, r+48} that hold one row.  IEEE addition is
-// commutative, so all four lanes obtain bit-identical results.
-__device__ __forceinline__ float row_sum(float v) {
-  v += xor_shfl(v, 16);
-  v += xor_shfl(v, 32);
-  return v;
+// The value held by the partner lane (lane ^ 16, lane ^ 32).
+__device__ __forceinline__ float partner16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float((threadIdx.x & 16) ? r[0] : r[1]);
 }
-__device__ __forceinline__ int row_sum(int v) {
-  v += xor_shfl(v, 16);
-  v += xor_shfl(v, 32);
-  return v;
+__device__ __forceinline__ float partner32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
 }
-__device__ __forceinline__ float row_max(float v) {
-  v = fmaxf(v, xor_shfl(v, 16));
-  v = fmaxf(v, xor_shfl(v, 32));
-  return v;
-}
+
+// Sum / max over the 4 lanes {r, r+16, r+32, r+48} that hold one row.
+__device__ __forceinline__ float row_sum(float v) { return pair32_sum(pair16_sum(v)); }
+__device__ __forceinline__ int row_sum(int v) { return pair32_sum(pair16_sum(v)); }
+__device__ __forceinline__ float row_max(float v) { return pair32_max(pair16_max(v)); }
 
 // Two floats -> two bfloat16 (round to nearest even) packed low/high in one dword.
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
@@ -53,7 +77,7 @@ __device__ __forceinline__ void cex(float& a, float& b) {
 // v[0..7], identically in all 4 lanes: merge pairs across lanes 16 apart into sorted
 // quadruples, then quadruples across lanes 32 apart by a bitonic merge.
 __device__ __forceinline__ void top8_sorted(float t1, float t2, float (&v)[8]) {
-  const float u1 = xor_shfl(t1, 16), u2 = xor_shfl(t2, 16);
+  const float u1 = partner16(t1), u2 = partner16(t2);
   float q[4];
   q[0] = fmaxf(t1, u1);
   q[3] = fminf(t2, u2);
@@ -64,7 +88,7 @@ __device__ __forceinline__ void top8_sorted(float t1, float t2, float (&v)[8]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     v[k] = q[k];
-    v[7 - k] = xor_shfl(q[k], 32);
+    v[7 - k] = partner32(q[k]);
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) cex(v[k], v[k + 4]);
@@ -113,6 +137,9 @@ struct BOp<1, KT, R> {        // BF16: two packed dwords per tile
     v[rb][t][1] = pack_bf16x2(x[2], x[3]);
   }
 };
+
+template <int KT, int R>
+struct BOp<2, KT, R> : BOp<1, KT, R> {};   // E4M3 weights: BF16 activations
 
 // acc[rb] += W'(one output tile, all K) * B[rb]; `fr` points at the tile's fragments
 // in LDS (kblocks(PREC, KT) fragments of 1 KiB).
@@ -245,13 +272,27 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
         for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
         mma_tile<PREC, KT, R>(unit, b, av, lane);
         mma_tile<PREC, KT, R>(unit + KB * kFrag, b, ag, lane);
+        if constexpr (PREC == 2) {
+          // per-channel dequantisation: the shifts were stored divided by the scale
+          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 128 + 16 * g);
+          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 192 + 16 * g);
 #pragma unroll
-        for (int rb = 0; rb < R; ++rb)
+          for (int rb = 0; rb < R; ++rb)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float sg = sigmoid_fast(ag[rb][i]);
-            h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
-          }
+            for (int i = 0; i < 4; ++i) {
+              const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(ag[rb][i] * (-kLog2e * sgt[i])));
+              const float v = av[rb][i] * sv[i];
+              h[rb][mt][i] = first ? v * sg : __builtin_fmaf(v, sg, h[rb][mt][i]) * kSqrtHalf;
+            }
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float sg = sigmoid_fast(ag[rb][i]);
+              h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
+            }
+        }
       }
     }
     ws.end();
@@ -401,11 +442,15 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
             for (int rb = 0; rb < R; ++rb) za[rb] = bv;
             mma_tile<PREC, KTA, R>(unit, ba, za, lane);
+            f4 scl = {1.f, 1.f, 1.f, 1.f};
+            if constexpr (PREC == 2) scl = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
 #pragma unroll
             for (int rb = 0; rb < R; ++rb)
 #pragma unroll
-              for (int i = 0; i < 4; ++i)
-                M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * za[rb][i] : kNegBig;
+              for (int i = 0; i < 4; ++i) {
+                const float hz = PREC == 2 ? za[rb][i] * scl[i] : za[rb][i];
+                M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
+              }
           }
         }
         ws.end();
@@ -425,15 +470,23 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       bool done[R];
 #pragma unroll
       for (int rb = 0; rb < R; ++rb) {
-        float t1 = kNegBig, t2 = kNegBig;          // this lane's two largest scores
+        // this lane's two largest scores, in two independent chains merged at the end
+        float a1 = kNegBig, a2 = kNegBig, b1 = kNegBig, b2 = kNegBig;
 #pragma unroll
         for (int t = 0; t < DT; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float w = M[rb][t][i];
-            t2 = __builtin_amdgcn_fmed3f(t1, t2, w);
-            t1 = fmaxf(t1, w);
+            if (i & 1) {
+              b2 = __builtin_amdgcn_fmed3f(b1, b2, w);
+              b1 = fmaxf(b1, w);
+            } else {
+              a2 = __builtin_amdgcn_fmed3f(a1, a2, w);
+              a1 = fmaxf(a1, w);
+            }
           }
+        const float t1 = fmaxf(a1, b1);
+        const float t2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
         float v[8];
         top8_sorted(t1, t2, v);
         const float m = v[0];
@@ -455,18 +508,19 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
         bool any_open = false;
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) {
-          float sm = 0.f;
-          int k = 0;
+          // four independent partial sums (one per slot i), combined in a fixed order
+          float sp[4] = {0.f, 0.f, 0.f, 0.f};
+          int kp[4] = {0, 0, 0, 0};
 #pragma unroll
           for (int t = 0; t < DT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const bool in = M[rb][t][i] > tau[rb];
-              sm += in ? M[rb][t][i] : 0.f;
-              k += in ? 1 : 0;
+              sp[i] += in ? M[rb][t][i] : 0.f;
+              kp[i] += in ? 1 : 0;
             }
-          sm = row_sum(sm);
-          k = row_sum(k);
+          float sm = row_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
+          int k = row_sum((kp[0] + kp[1]) + (kp[2] + kp[3]));
           if (!done[rb]) {
             if (k >= kprev[rb]) {
               done[rb] = true;
@@ -518,7 +572,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
-      float eta = 0.f;
+      float ep[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -526,9 +580,9 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           const bool dec = 16 * t + 4 * g + i < n_d;
           const float r = dec ? fmaxf(h[rb][t][i], 0.f) : 0.f;
           acc[rb][t][i] += r;
-          eta += r;
+          ep[i] += r;
         }
-      eta = row_sum(eta);
+      const float eta = row_sum((ep[0] + ep[1]) + (ep[2] + ep[3]));
 #pragma unroll
       for (int t = 0; t < DT; ++t)
 #pragma unroll
@@ -598,7 +652,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
   TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
-static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1)};
+static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)};
 
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0) {
   for (const auto& e : kKernels)

@@ -35,7 +35,8 @@
 // Packed layout of one GEMM (each starts 256-byte aligned), as a sequence of units:
 //   GLU layer, unit mt = 0..NT-1:  [value-tile fragments][gate-tile fragments]
 //                                  [16 value shifts][16 gate shifts]
-//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts]
+//                                  (E4M3: then [16 value scales][16 gate scales])
+//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (E4M3: then [16 scales])
 // A fragment is 64 lanes x 16 bytes: FP32 one per 16-wide K tile (a lane's float4 feeds
 // four 16x16x4 MFMAs), BF16 one per pair of K tiles (8 bf16 per lane, one 16x16x32 MFMA;
 // an odd last tile is paired with zeros).  Shifts are in C-layout order: slot 4 q + i
@@ -48,7 +49,7 @@ namespace tabnet {
 constexpr int kMaxFtLayers = 96;   // n_shared + (n_steps + 1) * n_indep
 constexpr int kMaxSteps = 32;
 constexpr int kFrag = 1024;        // bytes of one A fragment
-constexpr int kChunkTarget = 20480;
+constexpr int kChunkTarget = 40960;
 
 struct ChunkRec {
   int64_t off;     // byte offset into the packed weights
@@ -83,11 +84,14 @@ struct Plan {
 
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
-// prec: 0 FP32, 1 BF16.  DT = ceil(D/16), NT = ceil(N/16), KA0 = floor(n_d/16).
+// prec: 0 FP32, 1 BF16, 2 E4M3 weights (BF16 fragments holding the E4M3 codes, plus one
+// FP32 scale per output channel after the shifts).  DT = ceil(D/16), NT = ceil(N/16),
+// KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0) {
-  const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128, NT);
-  const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128, NT);
-  const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64, DT);
+  const int sc = prec == 2 ? 2 : 1;   // shifts, or shifts + scales
+  const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128 * sc, NT);
+  const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128 * sc, NT);
+  const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64 * sc, DT);
   const int buf = imax(first.upc * first.unit, imax(mid.upc * mid.unit, att.upc * att.unit));
   return Plan{first, mid, att, buf};
 }

@@ -281,10 +281,30 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
   }
 }
 
-void emit_shifts(const std::vector<double>& bf, int rows_valid, int first_row, std::vector<unsigned char>* wts) {
+// 16 per-output values (shifts or scales) of one tile; rows past rows_valid get `pad`.
+void emit_vals(const std::vector<double>& bf, int rows_valid, int first_row, float pad,
+               std::vector<unsigned char>* wts) {
   float v[16];
-  for (int i = 0; i < 16; ++i) v[i] = i < rows_valid ? (float)bf[first_row + i] : 0.f;
+  for (int i = 0; i < 16; ++i) v[i] = i < rows_valid ? (float)bf[first_row + i] : pad;
   emit(wts, v, sizeof v);
+}
+
+// E4M3 with one scale per output row: s_n = max_k |W'_nk| / 448 (1 for a zero row),
+// Wf <- E4M3(W' / s_n) (exact in BF16), shift <- b' / s_n so that s_n (acc + shift) = y.
+void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int rows, int cols,
+                        std::vector<double>* scale) {
+  scale->assign(rows, 1.0);
+  for (int r = 0; r < rows; ++r) {
+    double amax = 0;
+    for (int k = 0; k < cols; ++k) amax = std::fmax(amax, std::fabs((*Wf)[(size_t)r * cols + k]));
+    const double s = amax > 0 ? amax / 448.0 : 1.0;
+    (*scale)[r] = s;
+    for (int k = 0; k < cols; ++k) {
+      double& w = (*Wf)[(size_t)r * cols + k];
+      w = e4m3_value(e4m3_bits_rne(w / s));
+    }
+    (*bf)[r] /= s;
+  }
 }
 
 }  // namespace
@@ -293,7 +313,8 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
   const tabnet_config& c = m.cfg;
   const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
-  const int kprec = precision == TABNET_FP32 ? 0 : 1;
+  const int kprec = precision == TABNET_FP32 ? 0 : (precision == TABNET_BF16 ? 1 : 2);
+  const bool fp8 = precision == TABNET_FP8_E4M3;
   const Plan plan = make_plan(kprec, sh.DT, sh.NT, sh.KA0);
   *out = Packed();
   // input BN as a per-column affine map
@@ -307,11 +328,12 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
   for (const auto& L : m.shared) ft.push_back(&L);
   for (const auto& pass : m.indep)
     for (const auto& L : pass) ft.push_back(&L);
-  std::vector<double> Wf, bf;
+  std::vector<double> Wf, bf, sc;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
   // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
+    if (fp8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, &sc);
     const int KT = (L->cols + 15) / 16;   // the first layer of a pass reads D features, the others N
     const int K = L->cols;
     align();
@@ -324,14 +346,19 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
             [&](int i) { const int ch = 16 * mt + i; return ch < N ? half * N + ch : -1; },
             [&](int kin) { return kin < K ? kin : -1; }, &out->wts);
       const int nv = std::min(16, N - 16 * mt);
-      emit_shifts(bf, nv, 16 * mt, &out->wts);
-      emit_shifts(bf, nv, N + 16 * mt, &out->wts);
+      emit_vals(bf, nv, 16 * mt, 0.f, &out->wts);
+      emit_vals(bf, nv, N + 16 * mt, 0.f, &out->wts);
+      if (fp8) {
+        emit_vals(sc, nv, 16 * mt, 1.f, &out->wts);
+        emit_vals(sc, nv, N + 16 * mt, 1.f, &out->wts);
+      }
       (void)unit0;
     }
   }
   // attentive layers: unit mt = [fragments over the attention half of h][shifts]
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
+    if (fp8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, &sc);
     const int KTA = sh.NT - sh.KA0;
     align();
     out->att_off.push_back((int64_t)out->wts.size());
@@ -341,7 +368,8 @@ void pack_model(const ModelRaw& m, int precision, Packed* out) {
           [&](int i) { const int d = 16 * mt + i; return d < c.D ? d : -1; },
           [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
           &out->wts);
-      emit_shifts(bf, std::min(16, c.D - 16 * mt), 16 * mt, &out->wts);
+      emit_vals(bf, std::min(16, c.D - 16 * mt), 16 * mt, 0.f, &out->wts);
+      if (fp8) emit_vals(sc, std::min(16, c.D - 16 * mt), 16 * mt, 1.f, &out->wts);
     }
   }
   align();

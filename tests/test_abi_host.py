@@ -119,12 +119,12 @@ def test_packed_sizes(L):
     [value fragments][gate fragments][32 shifts], an attentive layer DT units of
     [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32) or per pair
     of K tiles (BF16, an odd last tile padded); every GEMM starts 256-byte aligned.
-    The chunk count is the number of weight-stream pieces of at most 20 KiB (balanced,
+    The chunk count is the number of weight-stream pieces of at most 40 KiB (balanced,
     one unit if a unit is larger) over pass 0, then per step attentive + pass."""
     def cdiv(a, b):
         return -(-a // b)
 
-    def chunks(unit, n, target=20480):
+    def chunks(unit, n, target=40960):
         upc = cdiv(n, cdiv(unit * n, target))
         upc = min(upc, max(1, target // unit))
         return cdiv(n, upc)
@@ -136,12 +136,13 @@ def test_packed_sizes(L):
         DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in (0, 1):
+        for prec in (0, 1, 2):
             kb = (lambda KT: KT) if prec == 0 else (lambda KT: cdiv(KT, 2))
-            glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 for k in set(ks)}
-            att_unit = kb(NT - KA0) * 1024 + 64
+            ex = 2 if prec == 2 else 1          # E4M3 units also carry one scale per output
+            glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 * ex for k in set(ks)}
+            att_unit = kb(NT - KA0) * 1024 + 64 * ex
             exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
-            first, mid = chunks(2 * kb(DT) * 1024 + 128, NT), chunks(2 * kb(NT) * 1024 + 128, NT)
+            first, mid = chunks(2 * kb(DT) * 1024 + 128 * ex, NT), chunks(2 * kb(NT) * 1024 + 128 * ex, NT)
             nl = cfg.n_shared + cfg.n_indep
             exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT)
             wb, nch = ctypes.c_int64(), ctypes.c_int64()

@@ -215,3 +215,22 @@ def test_full_size_adult108_sampled(tmp_path, prec):
     else:
         assert e["logit_abs"] <= 2e-2 and e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
         assert e["argmax"] >= 0.999, e
+
+
+@pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
+def test_fp8_weights_parity(tmp_path, name, B):
+    """E4M3 weights with one scale per output channel, BF16 activations.
+
+    Against FP64: logits |d| <= 2e-2 and argmax >= 99.9 %.  The masks move with the
+    weight rounding itself (an FP64 forward on the same E4M3 weights and BF16 activations
+    shows step-mask L1 up to 0.19 on these models, so no kernel can meet 1e-2 there); they
+    are gated at 0.25 (step) / 0.1 (aggregate) per row against FP64, and tightly against
+    FP64 on the same rounded operands, which isolates the kernel."""
+    params, X = synth.workload(name, rows=B)
+    _say(f"case fp8 {name} B={B}")
+    with load(params, tmp_path, "fp8") as m:
+        got = run(m, X)
+    e = check_reduced(got, params, X, "e4m3", "bf16", f"fp8 {name}")
+    assert e["logit_abs"] <= 2e-2, e
+    assert e["argmax"] >= 0.999, e
+    assert e["agg_l1"] <= 0.1 and e["step_l1"] <= 0.25, e
