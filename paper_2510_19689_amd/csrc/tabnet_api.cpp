@@ -100,10 +100,10 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
 
-  if (kernel_lds_bytes(k, m.cfg.D) > 160 * 1024) {
+  if (kernel_lds_bytes(k, m.cfg.D, m.cfg.n_out, m.cfg.n_d) > 160 * 1024) {
     return fail(TABNET_E_UNSUPPORTED, "tabnet_load: the model needs more LDS than a workgroup has");
   }
-  e = prepare_kernel(k, m.cfg.D);
+  e = prepare_kernel(k, m.cfg.D, m.cfg.n_out, m.cfg.n_d);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 
   Packed pk;

@@ -11,8 +11,8 @@
 namespace tabnet {
 struct KernelEntry;
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0);
-size_t kernel_lds_bytes(const KernelEntry* k, int D);
-hipError_t prepare_kernel(const KernelEntry* k, int D);
+size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d);
+hipError_t prepare_kernel(const KernelEntry* k, int D, int n_out, int n_d);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
 }  // namespace tabnet
 

@@ -346,6 +346,9 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   const int64_t wrow0 = ((int64_t)blockIdx.x * W + wave) * (16 * R);   // first row of this wave
   const int live_rows = (int)(B - wrow0 < 0 ? 0 : (B - wrow0 > 16 * R ? 16 * R : B - wrow0));
   float* stage = reinterpret_cast<float*>(smem + 2 * PL.buf) + (size_t)wave * 16 * R * D;
+  // the final map, staged in LDS behind the mask staging areas (visible after the first barrier)
+  float* wfin_s = reinterpret_cast<float*>(smem + 2 * PL.buf) + (size_t)W * 16 * R * D;
+  for (int e = threadIdx.x; e < A.n_out * n_d; e += 64 * W) wfin_s[e] = A.wfin[e];
   bool live[R];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) live[rb] = 16 * rb + rl < live_rows;
@@ -540,7 +543,21 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) M[rb][t][i] = fmaxf(M[rb][t][i] - tau[rb], 0.f);
     }
-    // ---- step mask out (through LDS, coalesced), prior update, masked input ----
+    // ---- step mask out (through LDS, coalesced) first, so that the stores drain while
+    // the prior update and the masked input are computed ----
+    if (A.masks_step != nullptr) {
+#pragma unroll
+      for (int rb = 0; rb < R; ++rb) {
+        float* sr = stage + (16 * rb + rl) * D + 4 * g;
+#pragma unroll
+        for (int t = 0; t < DT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
+      }
+      lds_wave_sync();
+      stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
+    }
     BOp<PREC, DT, R> u;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
@@ -554,19 +571,6 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
         }
         u.set(rb, t, uu);
       }
-    }
-    if (A.masks_step != nullptr) {
-#pragma unroll
-      for (int rb = 0; rb < R; ++rb) {
-        float* sr = stage + (16 * rb + rl) * D + 4 * g;
-#pragma unroll
-        for (int t = 0; t < DT; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
-      }
-      lds_wave_sync();
-      stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
     }
     // ---- feature transformer pass s, decision aggregation ----
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
@@ -595,7 +599,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   for (int rb = 0; rb < R; ++rb) {
     const int64_t row = wrow0 + 16 * rb + rl;
     for (int o = 0; o < A.n_out; ++o) {
-      const float* wf = A.wfin + o * n_d;
+      const float* wf = wfin_s + o * n_d;
       float part = 0.f;
 #pragma unroll
       for (int t = 0; t < NT; ++t)
@@ -660,19 +664,20 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0) {
   return nullptr;
 }
 
-size_t kernel_lds_bytes(const KernelEntry* k, int D) {
-  return 2 * (size_t)k->plan.buf + (size_t)k->W * 16 * k->R * D * sizeof(float);
+size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d) {
+  return 2 * (size_t)k->plan.buf + ((size_t)k->W * 16 * k->R * D + (size_t)n_out * n_d) * sizeof(float);
 }
 
-hipError_t prepare_kernel(const KernelEntry* k, int D) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k->fn),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kernel_lds_bytes(k, D));
+hipError_t prepare_kernel(const KernelEntry* k, int D, int n_out, int n_d) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k->fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kernel_lds_bytes(k, D, n_out, n_d));
 }
 
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream) {
   const int64_t rows_per_block = 16LL * k->R * k->W;
   const int64_t blocks = (a.B + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W), kernel_lds_bytes(k, a.D), stream, a);
+  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W), kernel_lds_bytes(k, a.D, a.n_out, a.n_d),
+                     stream, a);
   return hipGetLastError();
 }
 
