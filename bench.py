@@ -29,6 +29,39 @@ BF16_PEAK_TFLOPS = 2500.0      # dense
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
+KERNEL_SOURCES = ("paper_2510_19689_amd/csrc/tabnet_kernel.hip", "paper_2510_19689_amd/csrc/tabnet_kernel.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(name: str):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE, each scaled by
+    its reading for a plain device copy), from the committed profile summary; None when
+    the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"tabnet_forward_bf16_{name}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith(("kernel_source_sha256", "traffic_bytes_per_launch")):
+                k, v = line.strip().strip("-* `").split(":", 1)
+                vals[k.strip("` ")] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def algorithmic(cfg, rows: int, with_steps: bool = True):
     """Bytes and FLOPs of one forward: X read once; logits, masks_agg and (optionally) the
     per-step masks written once (FP32).  FLOPs are 2 x MACs of the unpadded GEMMs."""
@@ -259,7 +292,7 @@ def main():
                    "n_out": cfg.n_out, "gamma": cfg.gamma, "masks_step": True,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": profiled_traffic(name),
                      "kernel": "tabnet_forward_kernel<bf16>",
                      "algorithmic_bytes_per_launch": byt,
                      "mfma_tflops": flops / per_launch / 1e12},

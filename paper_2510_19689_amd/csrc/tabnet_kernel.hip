@@ -460,16 +460,18 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       }
     }
     // ---- sparsemax per row: Newton iteration on sum(max(z - tau, 0)) = 1 ----
-    // Scores are shifted by the row maximum (w = z - zmax <= 0).  For ANY set S of
-    // scores, (sum_S w - 1) / |S| is a lower bound of the threshold tau', and the best
-    // bound over the prefixes of a sorted list is exact once the list holds the support.
-    // The start is the best prefix bound of the row's top 8 candidates (the two largest
-    // scores of each of its 4 lanes), floored at -1.  From a lower bound, each step
-    // tau' = (sum_{w > tau'} w - 1) / |{w > tau'}| moves tau' up monotonically and stops,
-    // exactly, once the support no longer shrinks.
+    // For ANY set S of scores, (sum_S z - 1) / |S| is a lower bound of the threshold tau;
+    // over the prefixes of a sorted list the best such bound is exact once the list holds
+    // the support, and the largest score minus 1 is one too.  The start is the best
+    // prefix bound of the row's top 8 candidates (the two largest scores of each of its
+    // 4 lanes).  From a lower bound, each step tau <- (sum_{z > tau} z - 1) / |{z > tau}|
+    // moves tau up monotonically and stops, exactly, once the support no longer shrinks.
+    // If the first count equals the length kb of the best prefix and the prefix's smallest
+    // value lies above the new tau, the counted set is that prefix, it is the support,
+    // and the row is done after one pass.
     {
-      float tau[R];
-      int kprev[R];
+      float tau[R], vlast[R];
+      int kprev[R], kbest[R];
       bool done[R];
 #pragma unroll
       for (int rb = 0; rb < R; ++rb) {
@@ -492,18 +494,21 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
         const float t2 = fmaxf(fminf(a1, b1), fmaxf(a2, b2));
         float v[8];
         top8_sorted(t1, t2, v);
-        const float m = v[0];
-#pragma unroll
-        for (int t = 0; t < DT; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) M[rb][t][i] -= m;   // padded: stays hugely negative
-        float c = 0.f, best = -1.f;
+        float c = 0.f, best = v[0] - 1.f, vl = v[0];
+        int kb = 1;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          c += v[k] - m;
-          best = fmaxf(best, (c - 1.f) * (1.0f / (float)(k + 1)));
+          c += v[k];
+          const float bnd = (c - 1.f) * (1.0f / (float)(k + 1));
+          if (bnd > best) {
+            best = bnd;
+            kb = k + 1;
+            vl = v[k];
+          }
         }
         tau[rb] = best;
+        kbest[rb] = kb;
+        vlast[rb] = vl;
         kprev[rb] = 0x7fffffff;
         done[rb] = false;
       }
@@ -530,6 +535,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
             } else {
               tau[rb] = (sm - 1.f) / (float)k;
               kprev[rb] = k;
+              if (it == 0 && k == kbest[rb] && vlast[rb] > tau[rb]) done[rb] = true;
             }
           }
           any_open |= !done[rb];
