@@ -51,8 +51,9 @@ def profiled_traffic(name: str):
     vals = {}
     with open(path) as f:
         for line in f:
-            if ":" in line and line.strip().startswith(("kernel_source_sha256", "traffic_bytes_per_launch")):
-                k, v = line.strip().strip("-* `").split(":", 1)
+            line = line.strip().strip("-* `")
+            if ":" in line and line.startswith(("kernel_source_sha256", "traffic_bytes_per_launch")):
+                k, v = line.split(":", 1)
                 vals[k.strip("` ")] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
