@@ -10,9 +10,11 @@ Modules:
   rounding  -- bfloat16 / float8-E4M3FN round-to-nearest-even, from the formats' definitions
   tabnet    -- the vectorised float64 TabNet forward (optionally on rounded operands)
   scalar    -- a per-row pure-Python spelling of the same forward, to pin the first
+  stats     -- per-feature mean and population variance of masks over a set of rows
 
 Every function's pin lives in tests/ (marked not-gpu); none is "parity unpinned".
 """
 from .sparsemax import sparsemax, sparsemax_tau, sparsemax_support, sparsemax_bisect  # noqa: F401
 from .rounding import round_bf16, round_e4m3  # noqa: F401
 from .tabnet import forward, forward_chunked  # noqa: F401
+from .stats import column_mean_var, window_mean_var  # noqa: F401
