@@ -93,6 +93,41 @@ def time_forward(model, X, outs, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def time_mask_stats(masks, steps: int, warmup: int, per_graph: int = 20):
+    """Seconds per tabnet_mask_stats call over a device [B, D] mask matrix.  A call is two
+    short kernels, shorter than a Python-level launch, so `per_graph` calls are captured in
+    one HIP graph and the graph is replayed; HIP events on the replay stream time it."""
+    import torch
+    from paper_2510_19689_amd import tabnet
+    B, D = int(masks.shape[0]), int(masks.shape[1])
+    mean = torch.empty(D, dtype=torch.float64, device=masks.device)
+    var = torch.empty_like(mean)
+    ws = torch.empty(tabnet.mask_stats_workspace_bytes(B, D), dtype=torch.uint8, device=masks.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        tabnet.mask_stats_into(masks, mean, var, ws)      # warm the code object outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per_graph):
+            tabnet.mask_stats_into(masks, mean, var, ws)
+    reps = max(1, steps // per_graph)
+    for _ in range(max(1, warmup // per_graph)):
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (reps * per_graph)
+
+
 def cpu_baseline(params, X, budget_s: float = 12.0):
     """The FP64 oracle on the host's cores over a bounded sample of the same rows."""
     from threadpoolctl import threadpool_info
@@ -264,6 +299,11 @@ def main():
                 res[prec] = (t, wall)
                 print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
                       f"{rows * args.steps / t / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
+                if prec == "bf16":
+                    t_ms = time_mask_stats(outs[1], args.steps, args.warmup)
+                    res["mask_stats"] = t_ms
+                    print(f"[bench] mask_stats of masks_agg: {t_ms * 1e6:.2f} us, "
+                          f"{rows * cfg.D * 4 / t_ms / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
                 del outs
         serving = None
         if args.serve_rates:
@@ -304,6 +344,11 @@ def main():
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
     out["wall_s_bf16"] = wall_bf16
+    if "mask_stats" in res:
+        t_ms = res["mask_stats"]
+        gbs = rows * cfg.D * 4 / t_ms / 1e9
+        out["mask_stats"] = {"what": "per-feature mean and variance of masks_agg", "rows": rows, "D": cfg.D,
+                             "us_per_call": t_ms * 1e6, "GB_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
     if serving is not None:
         out["serving"] = {"model": name, "precision": "bf16", "masks": "logits + masks_agg",
                           "request_rows": "log-uniform 1..4096", "arrivals": "Poisson, open loop",

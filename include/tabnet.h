@@ -126,6 +126,39 @@ const char* tabnet_last_error(void);
 int tabnet_abi_version(void);
 
 /* ------------------------------------------------------------------------------------
+ * Mask statistics.
+ *
+ * The paper judges whether TabNet's explanations stay stable under production load by
+ * the variance of each feature's mask value over many served rows, reported next to
+ * each feature's importance (Sec. IV-B, Sec. V-C, Table IV).  These calls compute, on
+ * the GPU, the per-feature mean (importance over a set of rows) and the population
+ * variance of a mask matrix: for column d over the B rows,
+ *     mean_d = (1/B) sum_r m[r][d],   var_d = (1/B) sum_r (m[r][d] - mean_d)^2.
+ * Sums are taken in FP64 around the column's first value (shifted sums) and added in a
+ * fixed order: the result is the same on every run.
+ * ------------------------------------------------------------------------------------ */
+
+/* Bytes of device workspace tabnet_mask_stats needs for B rows of D columns (0 if B < 1
+ * or D < 1).  At most 1024 * 2 D * 8 bytes. */
+size_t tabnet_mask_stats_workspace_bytes(int64_t B, int32_t D);
+
+/*
+ * tabnet_mask_stats -- per-column mean and population variance, asynchronous on `stream`.
+ *
+ *   masks       device, float32 [B, D] row-major: e.g. masks_agg, or one step of masks_step
+ *   B, D        rows (>= 1) and columns (1 .. 2^24)
+ *   mean, var   device, float64 [D] each: outputs
+ *   workspace   device scratch of at least tabnet_mask_stats_workspace_bytes(B, D) bytes,
+ *               caller-owned; it must not be used by other work until this call's work ends
+ *   stream      hipStream_t on the calling thread's current device; NULL = null stream
+ *
+ * Errors: TABNET_E_INVALID (NULL pointer, B < 1, D out of range, workspace too small;
+ * nothing is enqueued), TABNET_E_HIP (launch failed).
+ */
+tabnet_status tabnet_mask_stats(const float* masks, int64_t B, int32_t D, double* mean, double* var,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------
  * Serving: continuous batching of variable-row requests.
  *
  * The paper serves TabNet per invocation with a batch size chosen at invocation time
@@ -147,7 +180,9 @@ typedef struct {
     int32_t slots;                 /* launch buffers (launches in flight); 0 -> 3, max 8     */
     int32_t with_step_masks;       /* 1: requests may ask for masks_step                      */
     int32_t use_graph;             /* 1: each slot's launch is a captured HIP graph          */
-    int32_t reserved[4];
+    int32_t mask_stats_window;     /* > 0: keep masks_agg statistics over each model's last
+                                      mask_stats_window launches (tabnet_serve_mask_stats)     */
+    int32_t reserved[3];
 } tabnet_serve_opts;
 
 typedef struct {
@@ -197,6 +232,21 @@ tabnet_status tabnet_serve_poll(tabnet_server* s, uint64_t req_id, int* done);
 /* Counters and latency percentiles since start or the last reset. */
 tabnet_status tabnet_serve_get_stats(tabnet_server* s, tabnet_serve_stats* out);
 tabnet_status tabnet_serve_reset_stats(tabnet_server* s);
+
+/*
+ * tabnet_serve_mask_stats -- per-feature mean and population variance of masks_agg over the
+ * rows of model `model`'s last mask_stats_window completed launches (since start or the last
+ * tabnet_serve_reset_stats): the served-load view of the mask stability the paper measures
+ * (Sec. IV-B, Sec. V-C).  Each launch's statistics are computed on the GPU right after its
+ * forward (tabnet_mask_stats' kernels, on the slot's stream) and the launches of the window
+ * are merged on the host in FP64, oldest first.
+ *   mean_host, var_host  host, float64 [D] of that model; zeros while no launch completed
+ *   rows                 receives the number of rows in the window (may be NULL)
+ * Errors: TABNET_E_INVALID (bad model index, NULL output, or the server was started with
+ * mask_stats_window = 0).  Thread-safe.
+ */
+tabnet_status tabnet_serve_mask_stats(tabnet_server* s, int model, double* mean_host, double* var_host,
+                                      int64_t* rows);
 
 /* Steady-clock time in nanoseconds (the clock of arrival_ns). */
 int64_t tabnet_serve_now_ns(void);

@@ -22,6 +22,7 @@ ARCH = "gfx950"
 
 SOURCES = [
     "tabnet_kernel.hip",
+    "tabnet_stats.hip",
     "tabnet_pack.cpp",
     "tabnet_api.cpp",
     "tabnet_hooks.cpp",

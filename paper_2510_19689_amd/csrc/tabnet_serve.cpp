@@ -93,6 +93,8 @@ struct ServerImpl {
   uint64_t launched_rows = 0;
   int64_t first_arrival = 0, last_done = 0;
   std::vector<double> lat_us;
+  // per model: statistics (mean[D], M2[D], n) of masks_agg of its last launches, oldest first
+  std::vector<std::deque<std::vector<double>>> mask_windows;
 
   std::thread sched_thr, comp_thr;
 
@@ -174,6 +176,11 @@ struct ServerImpl {
       const bool ok = exec->wait(L.slot);
       const ModelInfo& mi = models[L.model];
       const int D = mi.cfg.D, n_out = mi.cfg.n_out, S = mi.cfg.n_steps;
+      std::vector<double> mstats;
+      if (ok && opts.mask_stats_window > 0) {
+        const double* ms = exec->out_mask_stats(L.slot);
+        if (ms) mstats.assign(ms, ms + 2 * (size_t)D + 1);
+      }
       if (ok) {
         const float* lo = exec->out_logits(L.slot);
         const float* ag = exec->out_agg(L.slot);
@@ -190,6 +197,11 @@ struct ServerImpl {
       }
       const int64_t t = now_ns();
       lk.lock();
+      if (!mstats.empty()) {
+        auto& w = mask_windows[L.model];
+        w.push_back(std::move(mstats));
+        while ((int)w.size() > opts.mask_stats_window) w.pop_front();
+      }
       for (const Segment& sg : L.segs) {
         Request& r = *sg.req;
         if (!ok) {
@@ -225,6 +237,7 @@ tabnet_status server_create(std::vector<ModelInfo> models, Executor* exec, const
   s->budget = o.mem_budget_bytes;
   s->max_rows = o.max_rows_per_launch;
   s->nslots = o.slots;
+  s->mask_windows.resize(s->models.size());
   for (int i = s->nslots - 1; i >= 0; --i) s->free_slots.push_back(i);
   s->sched_thr = std::thread([s] { s->scheduler(); });
   s->comp_thr = std::thread([s] { s->completer(); });
@@ -371,6 +384,49 @@ tabnet_status server_reset_stats(ServerImpl* s) {
   s->first_arrival = s->last_done = 0;
   s->lat_us.clear();
   s->peak_bytes = s->inflight_bytes;
+  for (auto& w : s->mask_windows) w.clear();
+  return TABNET_OK;
+}
+
+// Merges the window's per-launch statistics, oldest first, with the pairwise update of
+// Chan, Golub and LeVeque: n = n_a + n_b, d = mean_b - mean_a, mean = mean_a + d n_b / n,
+// M2 = M2_a + M2_b + d^2 n_a n_b / n.
+tabnet_status server_mask_stats(ServerImpl* s, int model, double* mean, double* var, int64_t* rows) {
+  if (model < 0 || model >= (int)s->models.size() || !mean || !var) {
+    set_error("tabnet_serve_mask_stats: bad model index or NULL output");
+    return TABNET_E_INVALID;
+  }
+  if (s->opts.mask_stats_window <= 0) {
+    set_error("tabnet_serve_mask_stats: the server was started with mask_stats_window = 0");
+    return TABNET_E_INVALID;
+  }
+  const int D = s->models[model].cfg.D;
+  std::vector<double> m(D, 0.0), q(D, 0.0);
+  double n = 0.0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const std::vector<double>& e : s->mask_windows[model]) {
+      const double nb = e[2 * (size_t)D];
+      if (nb <= 0.0) continue;
+      const double nn = n + nb, f = nb / nn;
+      for (int d = 0; d < D; ++d) {
+        if (n == 0.0) {
+          m[d] = e[d];
+          q[d] = e[D + d];
+        } else {
+          const double dm = e[d] - m[d];
+          m[d] += dm * f;
+          q[d] += e[D + d] + dm * dm * n * f;
+        }
+      }
+      n = nn;
+    }
+  }
+  for (int d = 0; d < D; ++d) {
+    mean[d] = n > 0.0 ? m[d] : 0.0;
+    var[d] = n > 0.0 ? q[d] / n : 0.0;
+  }
+  if (rows) *rows = (int64_t)n;
   return TABNET_OK;
 }
 

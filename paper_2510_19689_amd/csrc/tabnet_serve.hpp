@@ -29,6 +29,9 @@ struct Executor {
   virtual const float* out_logits(int slot) = 0;      // [rows, n_out]
   virtual const float* out_agg(int slot) = 0;         // [rows, D]
   virtual const float* out_steps(int slot) = 0;       // [n_steps, rows, D] or null
+  // Statistics of the last launch's masks_agg when the server keeps them:
+  // mean[D], M2[D] (sums of squared deviations), n -- 2 D + 1 doubles of that model's D.
+  virtual const double* out_mask_stats(int slot) = 0;
 };
 
 // Largest D, n_out and n_steps over the served models (sizes of the slot buffers).
@@ -55,6 +58,7 @@ tabnet_status server_wait(ServerImpl* s, uint64_t id, int64_t timeout_us);
 tabnet_status server_poll(ServerImpl* s, uint64_t id, int* done);
 tabnet_status server_stats(ServerImpl* s, tabnet_serve_stats* o);
 tabnet_status server_reset_stats(ServerImpl* s);
+tabnet_status server_mask_stats(ServerImpl* s, int model, double* mean, double* var, int64_t* rows);
 tabnet_status server_stop(ServerImpl* s);   // joins the threads, deletes the executor and s
 
 Executor* make_hip_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, tabnet_status* st);

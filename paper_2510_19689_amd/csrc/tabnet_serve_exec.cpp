@@ -11,6 +11,7 @@
 #include "../../include/tabnet_internal.h"
 #include "tabnet_handle.hpp"
 #include "tabnet_serve.hpp"
+#include "tabnet_stats.hpp"
 
 namespace tabnet {
 namespace {
@@ -23,6 +24,8 @@ struct HipSlot {
   float *h_x = nullptr, *h_lo = nullptr, *h_ag = nullptr, *h_ms = nullptr;
   int64_t* d_rows = nullptr;     // live row count read by the kernel
   int64_t* h_rows = nullptr;     // pinned source of d_rows
+  void* d_sws = nullptr;         // mask-statistics workspace (max_rows_per_launch rows)
+  double *d_st = nullptr, *h_st = nullptr;   // mean[D], M2[D], n of the last launch
   std::vector<hipGraphExec_t> graphs;   // per model
   int model = 0;
   int64_t rows = 0;
@@ -58,6 +61,13 @@ class HipExecutor : public Executor {
         if ((e = hipMalloc(&s.d_ms, R * dm.S * dm.D * 4)) != hipSuccess) return e;
         if ((e = hipHostMalloc(&s.h_ms, R * dm.S * dm.D * 4, hipHostMallocDefault)) != hipSuccess) return e;
       }
+      if (o.mask_stats_window > 0) {
+        if ((e = hipMalloc(&s.d_sws, mask_stats_workspace_bytes((int64_t)R, dm.D))) != hipSuccess) return e;
+        if ((e = hipMalloc(&s.d_st, (2 * (size_t)dm.D + 1) * sizeof(double))) != hipSuccess) return e;
+        if ((e = hipHostMalloc(&s.h_st, (2 * (size_t)dm.D + 1) * sizeof(double), hipHostMallocDefault)) !=
+            hipSuccess)
+          return e;
+      }
       if (o.use_graph) {
         // One graph per model: the live row count (pinned -> device) and the forward,
         // whose grid covers max_rows_per_launch and which reads the count on the device.
@@ -67,9 +77,12 @@ class HipExecutor : public Executor {
           if ((e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
           hipError_t e1 = hipMemcpyAsync(s.d_rows, s.h_rows, sizeof(int64_t), hipMemcpyHostToDevice, s.stream);
           hipError_t e2 = enqueue_forward(m.handle, s.d_x, (int64_t)R, s.d_rows, s.d_lo, s.d_ag, s.d_ms, s.stream);
+          hipError_t e3 = hipSuccess;
+          if (e2 == hipSuccess && o.mask_stats_window > 0) e3 = enqueue_stats(s, m.cfg.D, (int64_t)R, s.d_rows);
           if ((e = hipStreamEndCapture(s.stream, &g)) != hipSuccess) return e;
           if (e1 != hipSuccess) return e1;
           if (e2 != hipSuccess) return e2;
+          if (e3 != hipSuccess) return e3;
           e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
           (void)hipGraphDestroy(g);
           if (e != hipSuccess) return e;
@@ -78,6 +91,12 @@ class HipExecutor : public Executor {
       }
     }
     return hipSuccess;
+  }
+
+  // Statistics of the slot's masks_agg (rows, or the live count in rows_dev): mean, M2, n.
+  hipError_t enqueue_stats(HipSlot& s, int D, int64_t rows, const int64_t* rows_dev) {
+    return enqueue_mask_stats(s.d_ag, rows, rows_dev, D, s.d_st, nullptr, s.d_st + D, s.d_st + 2 * (size_t)D,
+                              s.d_sws, s.stream);
   }
 
   ~HipExecutor() override {
@@ -90,6 +109,9 @@ class HipExecutor : public Executor {
       for (float* p : {s.d_x, s.d_lo, s.d_ag, s.d_ms})
         if (p) (void)hipFree(p);
       if (s.d_rows) (void)hipFree(s.d_rows);
+      if (s.d_sws) (void)hipFree(s.d_sws);
+      if (s.d_st) (void)hipFree(s.d_st);
+      if (s.h_st) (void)hipHostFree(s.h_st);
       for (float* p : {s.h_x, s.h_lo, s.h_ag, s.h_ms})
         if (p) (void)hipHostFree(p);
       if (s.h_rows) (void)hipHostFree(s.h_rows);
@@ -110,9 +132,15 @@ class HipExecutor : public Executor {
     if (o.use_graph) {
       *s.h_rows = rows;
       if (hipGraphLaunch(s.graphs[model], s.stream) != hipSuccess) return false;
-    } else if (enqueue_forward(m.handle, s.d_x, rows, nullptr, s.d_lo, s.d_ag, s.d_ms, s.stream) != hipSuccess) {
-      return false;
+    } else {
+      if (enqueue_forward(m.handle, s.d_x, rows, nullptr, s.d_lo, s.d_ag, s.d_ms, s.stream) != hipSuccess)
+        return false;
+      if (o.mask_stats_window > 0 && enqueue_stats(s, D, rows, nullptr) != hipSuccess) return false;
     }
+    if (o.mask_stats_window > 0 &&
+        hipMemcpyAsync(s.h_st, s.d_st, (2 * (size_t)D + 1) * sizeof(double), hipMemcpyDeviceToHost, s.stream) !=
+            hipSuccess)
+      return false;
     if (hipMemcpyAsync(s.h_lo, s.d_lo, (size_t)rows * n_out * 4, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
       return false;
     if (hipMemcpyAsync(s.h_ag, s.d_ag, (size_t)rows * D * 4, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
@@ -140,6 +168,7 @@ class HipExecutor : public Executor {
   const float* out_logits(int slot) override { return slots[slot].h_lo; }
   const float* out_agg(int slot) override { return slots[slot].h_ag; }
   const float* out_steps(int slot) override { return slots[slot].h_ms; }
+  const double* out_mask_stats(int slot) override { return slots[slot].h_st; }
 };
 
 }  // namespace
@@ -176,8 +205,8 @@ tabnet_status fill_opts(const tabnet_serve_opts* in, tabnet_serve_opts* o) {
   if (o->max_rows_per_launch == 0) o->max_rows_per_launch = 65536;
   if (o->slots == 0) o->slots = 3;
   if (in == nullptr) o->use_graph = 1;
-  if (o->max_rows_per_launch < 1 || o->slots < 1 || o->slots > 8) {
-    set_error("tabnet_serve_start: max_rows_per_launch must be >= 1 and slots in [1, 8]");
+  if (o->max_rows_per_launch < 1 || o->slots < 1 || o->slots > 8 || o->mask_stats_window < 0) {
+    set_error("tabnet_serve_start: max_rows_per_launch must be >= 1, slots in [1, 8], mask_stats_window >= 0");
     return TABNET_E_INVALID;
   }
   return TABNET_OK;
@@ -268,6 +297,12 @@ tabnet_status tabnet_serve_get_stats(tabnet_server* s, tabnet_serve_stats* out) 
 tabnet_status tabnet_serve_reset_stats(tabnet_server* s) {
   if (!s) return TABNET_E_INVALID;
   return server_reset_stats(s->impl);
+}
+
+tabnet_status tabnet_serve_mask_stats(tabnet_server* s, int model, double* mean_host, double* var_host,
+                                      int64_t* rows) {
+  if (!s) return TABNET_E_INVALID;
+  return server_mask_stats(s->impl, model, mean_host, var_host, rows);
 }
 
 int64_t tabnet_serve_now_ns(void) { return now_ns(); }

@@ -21,6 +21,7 @@ class FakeExecutor : public Executor {
   int delay_us = 0;
   struct Slot {
     std::vector<float> x, lo, ag, ms;
+    std::vector<double> st;      // mean[D], M2[D], n of the last launch's masks_agg
   };
   std::vector<Slot> slots;
 
@@ -46,6 +47,21 @@ class FakeExecutor : public Executor {
         for (int st = 0; st < S; ++st)
           for (int j = 0; j < D; ++j) s.ms[((int64_t)st * rows + r) * D + j] = s.x[r * D + j] + (float)st;
     }
+    if (o.mask_stats_window > 0) {
+      // two-pass column statistics of this launch's masks_agg (the GPU computes the same
+      // three quantities in its statistics kernels)
+      s.st.assign(2 * (size_t)D + 1, 0.0);
+      for (int j = 0; j < D; ++j) {
+        double sum = 0.0;
+        for (int64_t r = 0; r < rows; ++r) sum += s.ag[r * D + j];
+        const double mean = sum / (double)rows;
+        double q = 0.0;
+        for (int64_t r = 0; r < rows; ++r) q += ((double)s.ag[r * D + j] - mean) * ((double)s.ag[r * D + j] - mean);
+        s.st[j] = mean;
+        s.st[D + j] = q;
+      }
+      s.st[2 * (size_t)D] = (double)rows;
+    }
     if (delay_us > 0) std::this_thread::sleep_for(std::chrono::microseconds(delay_us));
     return true;
   }
@@ -53,6 +69,7 @@ class FakeExecutor : public Executor {
   const float* out_logits(int slot) override { return slots[slot].lo.data(); }
   const float* out_agg(int slot) override { return slots[slot].ag.data(); }
   const float* out_steps(int slot) override { return slots[slot].ms.empty() ? nullptr : slots[slot].ms.data(); }
+  const double* out_mask_stats(int slot) override { return slots[slot].st.empty() ? nullptr : slots[slot].st.data(); }
 };
 
 }  // namespace

@@ -36,7 +36,8 @@ class Config(ctypes.Structure):
 class ServeOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_rows_per_launch", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("with_step_masks", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("use_graph", ctypes.c_int32), ("mask_stats_window", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class ServeStats(ctypes.Structure):
@@ -104,6 +105,12 @@ def lib() -> ctypes.CDLL:
     L.tabnet_serve_get_stats.restype = i32
     L.tabnet_serve_reset_stats.argtypes = [vp]
     L.tabnet_serve_reset_stats.restype = i32
+    L.tabnet_serve_mask_stats.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
+    L.tabnet_serve_mask_stats.restype = i32
+    L.tabnet_mask_stats_workspace_bytes.argtypes = [i64, ctypes.c_int32]
+    L.tabnet_mask_stats_workspace_bytes.restype = ctypes.c_size_t
+    L.tabnet_mask_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.tabnet_mask_stats.restype = i32
     L.tabnet_serve_now_ns.argtypes = []
     L.tabnet_serve_now_ns.restype = i64
     L.tabnet_serve_stop.argtypes = [vp]
@@ -187,6 +194,34 @@ class Model:
         return lo, ag, ms
 
 
+def mask_stats_workspace_bytes(B: int, D: int) -> int:
+    return int(lib().tabnet_mask_stats_workspace_bytes(int(B), int(D)))
+
+
+def mask_stats_into(masks, mean, var, workspace, stream=None) -> None:
+    """tabnet_mask_stats on caller-provided device tensors: masks float32 [B, D],
+    mean / var float64 [D], workspace a device tensor of at least
+    mask_stats_workspace_bytes(B, D) bytes."""
+    B, D = int(masks.shape[0]), int(masks.shape[1])
+    check(lib().tabnet_mask_stats(masks.data_ptr(), B, D, mean.data_ptr(), var.data_ptr(),
+                                  workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                  _stream_ptr(stream)))
+
+
+def mask_stats(masks, stream=None):
+    """Per-column mean and population variance (float64 [D] tensors) of a device
+    float32 [B, D] mask matrix."""
+    import torch
+    if masks.dtype != torch.float32 or masks.dim() != 2 or not masks.is_contiguous():
+        raise ValueError("masks must be a contiguous float32 [B, D] tensor")
+    B, D = int(masks.shape[0]), int(masks.shape[1])
+    mean = torch.empty(D, dtype=torch.float64, device=masks.device)
+    var = torch.empty(D, dtype=torch.float64, device=masks.device)
+    ws = torch.empty(max(mask_stats_workspace_bytes(B, D), 1), dtype=torch.uint8, device=masks.device)
+    mask_stats_into(masks, mean, var, ws, stream)
+    return mean, var
+
+
 class Server:
     """Continuous-batching server over resident models (tabnet_serve_*).
 
@@ -196,9 +231,10 @@ class Server:
 
     def __init__(self, models=None, mem_budget_bytes: int = 0, max_rows_per_launch: int = 0,
                  slots: int = 0, with_step_masks: bool = False, use_graph: bool = True,
-                 fake_configs=None, fake_delay_us: int = 0):
+                 mask_stats_window: int = 0, fake_configs=None, fake_delay_us: int = 0):
         o = ServeOpts(mem_budget_bytes=mem_budget_bytes, max_rows_per_launch=max_rows_per_launch,
-                      slots=slots, with_step_masks=int(with_step_masks), use_graph=int(use_graph))
+                      slots=slots, with_step_masks=int(with_step_masks), use_graph=int(use_graph),
+                      mask_stats_window=int(mask_stats_window))
         h = ctypes.c_void_p()
         if fake_configs is not None:
             arr = (Config * len(fake_configs))(*fake_configs)
@@ -235,6 +271,18 @@ class Server:
 
     def reset_stats(self) -> None:
         check(lib().tabnet_serve_reset_stats(self._s))
+
+    def mask_stats(self, model: int):
+        """(mean [D], var [D], rows) of masks_agg over the model's last mask_stats_window
+        launches (numpy float64)."""
+        import numpy as np
+        D = self.configs[model].D
+        mean = np.zeros(D, np.float64)
+        var = np.zeros(D, np.float64)
+        rows = ctypes.c_int64()
+        check(lib().tabnet_serve_mask_stats(self._s, model, mean.ctypes.data, var.ctypes.data,
+                                            ctypes.byref(rows)))
+        return mean, var, rows.value
 
     @staticmethod
     def now_ns() -> int:

@@ -149,3 +149,33 @@ def test_packed_sizes(L):
             assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == 0
             assert wb.value == exp, (name, prec, wb.value, exp)
             assert nch.value == exp_chunks, (name, prec, nch.value, exp_chunks)
+
+
+def test_mask_stats_workspace_and_argument_checks(L):
+    # workspace: 2 D doubles per block of rows; a block is a multiple of 16 x (1024 // D)
+    # rows (16 row loads in flight per thread) and there are at most 1024 blocks
+    assert tb.mask_stats_workspace_bytes(0, 5) == 0
+    assert tb.mask_stats_workspace_bytes(5, 0) == 0
+    assert tb.mask_stats_workspace_bytes(1, 5) == 10 * 8
+    assert tb.mask_stats_workspace_bytes(3264, 5) == 10 * 8           # 204 lanes x 16 rows
+    assert tb.mask_stats_workspace_bytes(3265, 5) == 2 * 10 * 8
+    assert tb.mask_stats_workspace_bytes(65536, 108) == 456 * 216 * 8  # 144-row blocks
+    assert tb.mask_stats_workspace_bytes(10 ** 6, 200) == 962 * 400 * 8  # 1040-row blocks
+    assert tb.mask_stats_workspace_bytes(100, 3000) == 7 * 6000 * 8    # 16-row blocks
+    for B, D in [(1, 1), (10 ** 7, 3), (123457, 77), (5, 4096)]:
+        assert tb.mask_stats_workspace_bytes(B, D) <= 1024 * 2 * D * 8
+    # argument errors are reported before anything is enqueued (no GPU is touched)
+    fake = ctypes.c_void_p(0x1000)
+    need = tb.mask_stats_workspace_bytes(100, 7)
+    cases = [
+        (None, 100, 7, fake, fake, fake, need),
+        (fake, 100, 7, None, fake, fake, need),
+        (fake, 100, 7, fake, None, fake, need),
+        (fake, 100, 7, fake, fake, None, need),
+        (fake, 0, 7, fake, fake, fake, need),
+        (fake, -3, 7, fake, fake, fake, need),
+        (fake, 100, 0, fake, fake, fake, need),
+        (fake, 100, 7, fake, fake, fake, need - 1),
+    ]
+    for m, B, D, mean, var, ws, nb in cases:
+        assert L.tabnet_mask_stats(m, B, D, mean, var, ws, nb, None) == tb.E_INVALID

@@ -172,3 +172,43 @@ def test_stop_cancels_queued_and_finishes_inflight():
     for r, i in zip(reqs, ids):
         if statuses[i] == tb.OK:
             check(r, c)
+
+
+def test_mask_stats_window_over_launches():
+    # one request per launch (slots=1, submitted one at a time): the window of the last K
+    # launches is the rows of the last K requests; the stand-in's masks_agg is 2 X
+    from oracle import stats as ostats
+    c = cfg(D=6, n_out=2, S=2)
+    rng = np.random.default_rng(9)
+    for K in (1, 3, 50):
+        with tb.Server(fake_configs=[c], slots=1, max_rows_per_launch=512, mask_stats_window=K) as s:
+            mean, var, rows = s.mask_stats(0)
+            assert rows == 0 and not mean.any() and not var.any()
+            aggs = []
+            for n in (5, 40, 1, 300, 77, 12):
+                X, lo, ag, _ = make_req(rng, n, c, steps=False)
+                assert s.wait(s.submit(0, X, lo, ag)) == tb.OK
+                aggs.append(ag.copy())
+                mean, var, rows = s.mask_stats(0)
+                em, ev, erows = ostats.window_mean_var(aggs, K)
+                assert rows == erows
+                np.testing.assert_allclose(mean, em, rtol=1e-12, atol=1e-15)
+                np.testing.assert_allclose(var, ev, rtol=1e-10, atol=1e-15)
+            s.reset_stats()
+            assert s.mask_stats(0)[2] == 0
+
+
+def test_mask_stats_errors():
+    c = cfg()
+    with tb.Server(fake_configs=[c]) as s:
+        with pytest.raises(tb.TabNetError) as e:
+            s.mask_stats(0)                    # window 0: statistics off
+        assert e.value.status == tb.E_INVALID
+    with tb.Server(fake_configs=[c], mask_stats_window=2) as s:
+        buf = np.zeros(c.D, np.float64)
+        for model in (1, -1):
+            assert tb.lib().tabnet_serve_mask_stats(s._s, model, buf.ctypes.data, buf.ctypes.data,
+                                                    None) == tb.E_INVALID
+        assert tb.lib().tabnet_serve_mask_stats(s._s, 0, None, buf.ctypes.data, None) == tb.E_INVALID
+    with pytest.raises(tb.TabNetError):
+        tb.Server(fake_configs=[c], mask_stats_window=-1)
