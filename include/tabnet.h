@@ -130,7 +130,7 @@ int tabnet_abi_version(void);
  *
  * The paper judges whether TabNet's explanations stay stable under production load by
  * the variance of each feature's mask value over many served rows, reported next to
- * each feature's importance (Sec. IV-B, Sec. V-C, Table IV).  These calls compute, on
+ * each feature's importance (Sec. IV-C, Sec. V-C, Table IV).  These calls compute, on
  * the GPU, the per-feature mean (importance over a set of rows) and the population
  * variance of a mask matrix: for column d over the B rows,
  *     mean_d = (1/B) sum_r m[r][d],   var_d = (1/B) sum_r (m[r][d] - mean_d)^2.
@@ -237,7 +237,7 @@ tabnet_status tabnet_serve_reset_stats(tabnet_server* s);
  * tabnet_serve_mask_stats -- per-feature mean and population variance of masks_agg over the
  * rows of model `model`'s last mask_stats_window completed launches (since start or the last
  * tabnet_serve_reset_stats): the served-load view of the mask stability the paper measures
- * (Sec. IV-B, Sec. V-C).  Each launch's statistics are computed on the GPU right after its
+ * (Sec. IV-C, Sec. V-C).  Each launch's statistics are computed on the GPU right after its
  * forward (tabnet_mask_stats' kernels, on the slot's stream) and the launches of the window
  * are merged on the host in FP64, oldest first.
  *   mean_host, var_host  host, float64 [D] of that model; zeros while no launch completed

@@ -4,7 +4,7 @@ Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import 
 module; it shares no code with the HIP path.
 
 What it computes.  The paper judges whether TabNet's masks stay stable under load by the
-variance of each feature's mask value over many served rows (Sec. IV-B, Sec. V-C: 100
+variance of each feature's mask value over many served rows (Sec. IV-C, Sec. V-C: 100
 random samples at peak throughput), and reports per-feature importance next to it
 (Table IV).  The paper gives no formula for its stability score; the computable part is
 the per-feature mean (the importance of feature d over a set of rows) and the

@@ -3,7 +3,7 @@
 //
 // The paper judges the stability of TabNet's explanations under load by the variance of
 // each feature's mask value over many served rows, next to each feature's importance
-// (Sec. IV-B, Sec. V-C, Table IV).  These kernels compute both for any set of rows, as
+// (Sec. IV-C, Sec. V-C, Table IV).  These kernels compute both for any set of rows, as
 // shifted sums: with K_d = m[0][d] (the column's first value, which every workgroup can
 // read), S1_d = sum_r (m[r][d] - K_d) and S2_d = sum_r (m[r][d] - K_d)^2 in FP64 give
 //     mean_d = K_d + S1_d / B,   M2_d = S2_d - S1_d^2 / B,   var_d = M2_d / B.
