@@ -222,37 +222,59 @@ def read_weights(path: str) -> dict:
 
 # ----------------------------------------------------------------------------- inputs
 
-def make_inputs(kind: str, rows: int, seed: int) -> np.ndarray:
-    """Seeded feature matrix X[rows, D] (float32, row-major) for one workload family."""
+def _raw_columns(kind: str, rows: int, seed: int):
+    """The raw columns of the HR- and Adult-shaped inputs, in column order: a list of
+    (cardinality, width, values) with cardinality 0 for a continuous column (values are
+    the float32 column) and > 0 for a categorical one (values are int64 levels and the
+    column carries a float32 [cardinality, width] embedding table)."""
     rng = _rng(seed)
+    cols = []
     if kind == "hr":
         # 26 continuous N(0,1); 9 categorical columns with 2..10 levels, each level
         # carrying a seeded scalar value (a 1-wide embedding of its one-hot code).
         card = rng.integers(2, 11, size=9)
         tables = [rng.standard_normal(int(c)) for c in card]
-        X = np.empty((rows, 35), dtype=np.float32)
-        X[:, :26] = rng.standard_normal((rows, 26))
+        cont = rng.standard_normal((rows, 26))
+        cols += [(0, 1, _f32(cont[:, j])) for j in range(26)]
         for j in range(9):
             lv = rng.integers(0, int(card[j]), size=rows)
-            X[:, 26 + j] = tables[j][lv]
-        return X
+            cols.append((int(card[j]), 1, lv, _f32(tables[j]).reshape(-1, 1)))
+        return cols
     if kind == "adult":
         # 6 log-normal(0,1) columns standardised with the distribution's own moments
         # (so a row never depends on its batch), then 8 categorical columns embedded
         # at widths 16,16,14,14,12,10,10,10; the widest vocabulary has 42 levels.
         card = np.concatenate([[42], rng.integers(2, 43, size=7)])
         tables = [rng.standard_normal((int(c), d)) for c, d in zip(card, ADULT_EMBED_DIMS)]
-        X = np.empty((rows, 108), dtype=np.float32)
         mu = math.exp(0.5)
         sd = math.sqrt((math.e - 1.0) * math.e)
-        X[:, :6] = (rng.lognormal(0.0, 1.0, (rows, 6)) - mu) / sd
-        col = 6
+        cont = _f32((rng.lognormal(0.0, 1.0, (rows, 6)) - mu) / sd)
+        cols += [(0, 1, cont[:, j]) for j in range(6)]
         for c, tab in zip(card, tables):
             lv = rng.integers(0, int(c), size=rows)
-            X[:, col:col + tab.shape[1]] = tab[lv]
-            col += tab.shape[1]
-        assert col == 108
+            cols.append((int(c), tab.shape[1], lv, _f32(tab)))
+        return cols
+    raise ValueError(f"input family {kind!r} has no categorical columns")
+
+
+def make_inputs(kind: str, rows: int, seed: int) -> np.ndarray:
+    """Seeded feature matrix X[rows, D] (float32, row-major) for one workload family.
+
+    HR- and Adult-shaped rows are the embedded form of make_raw_inputs(kind, rows, seed):
+    a categorical column contributes its level's row of its embedding table."""
+    if kind in ("hr", "adult"):
+        cols = _raw_columns(kind, rows, seed)
+        D = sum(c[1] for c in cols)
+        X = np.empty((rows, D), dtype=np.float32)
+        at = 0
+        for c in cols:
+            if c[0] == 0:
+                X[:, at] = c[2]
+            else:
+                X[:, at:at + c[1]] = c[3][c[2]]
+            at += c[1]
         return X
+    rng = _rng(seed)
     if kind == "wide":
         # 200 continuous N(0,1); 20 seeded columns have each entry zeroed with p = 0.3.
         X = rng.standard_normal((rows, 200), dtype=np.float32)
@@ -265,6 +287,29 @@ def make_inputs(kind: str, rows: int, seed: int) -> np.ndarray:
     if kind == "normal":
         raise ValueError("use make_normal_inputs for plain Gaussian inputs")
     raise ValueError(f"unknown input family {kind!r}")
+
+
+def make_raw_inputs(kind: str, rows: int, seed: int):
+    """The same rows as make_inputs(kind, rows, seed) before embedding.
+
+    Returns (X_raw, cards, dims, tables): X_raw[rows, C] float32 holds the continuous
+    values and, in categorical columns, the level as an exact float; cards[C] (0 for a
+    continuous column), dims[C] (embedding widths, 1 for a continuous column) as int32;
+    tables the categorical columns' float32 embedding tables, each [card, dim] row-major,
+    concatenated in column order."""
+    cols = _raw_columns(kind, rows, seed)
+    C = len(cols)
+    X = np.empty((rows, C), dtype=np.float32)
+    cards = np.zeros(C, np.int32)
+    dims = np.zeros(C, np.int32)
+    tabs = []
+    for j, c in enumerate(cols):
+        cards[j], dims[j] = c[0], c[1]
+        X[:, j] = c[2]
+        if c[0] > 0:
+            tabs.append(c[3].reshape(-1))
+    tables = np.concatenate(tabs).astype(np.float32) if tabs else np.zeros(0, np.float32)
+    return X, cards, dims, tables
 
 
 def make_normal_inputs(rows: int, D: int, seed: int, scale: float = 1.0) -> np.ndarray:
