@@ -93,6 +93,24 @@ def time_forward(model, X, outs, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def time_forward_raw(model, X_raw, outs, steps: int, warmup: int) -> float:
+    """Seconds per tabnet_forward_raw launch (HIP events on the launch stream)."""
+    import torch
+    lo, ag, ms = outs
+    for _ in range(warmup):
+        model.forward_raw_into(X_raw, lo, ag, ms)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        model.forward_raw_into(X_raw, lo, ag, ms)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
 def time_mask_stats(masks, steps: int, warmup: int, per_graph: int = 20):
     """Seconds per tabnet_mask_stats call over a device [B, D] mask matrix.  A call is two
     short kernels, shorter than a Python-level launch, so `per_graph` calls are captured in
@@ -304,6 +322,20 @@ def main():
                     res["mask_stats"] = t_ms
                     print(f"[bench] mask_stats of masks_agg: {t_ms * 1e6:.2f} us, "
                           f"{rows * cfg.D * 4 / t_ms / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+                    if w["data"] in ("adult", "hr"):
+                        # the same rows before embedding: gather in the kernel, masks per raw column
+                        X_raw, cards, dims, tables = synth.make_raw_inputs(w["data"], rows, synth.DATA_SEED[name])
+                        m.set_embeddings(cards, dims, tables)
+                        Xr = torch.from_numpy(X_raw).cuda()
+                        C = X_raw.shape[1]
+                        routs = (torch.empty((rows, cfg.n_out), dtype=torch.float32, device="cuda"),
+                                 torch.empty((rows, C), dtype=torch.float32, device="cuda"),
+                                 torch.empty((cfg.n_steps, rows, C), dtype=torch.float32, device="cuda"))
+                        t_raw = time_forward_raw(m, Xr, routs, args.steps, args.warmup)
+                        res["raw"] = (t_raw, C)
+                        print(f"[bench] bf16 raw rows (C={C}): {t_raw * 1e6:.1f} us/forward, "
+                              f"{rows / t_raw / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
+                        del routs, Xr
                 del outs
         serving = None
         if args.serve_rates:
@@ -344,7 +376,12 @@ def main():
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
     out["wall_s_bf16"] = wall_bf16
-    if "mask_stats" in res:
+    if "raw" in res:
+        t_raw, C = res["raw"]
+        rb = 4 * (C + cfg.n_out + C + cfg.n_steps * C)
+        out["raw_rows"] = {"what": "BF16 forward on raw rows: embedding gathered in the kernel, masks per raw column",
+                           "columns": C, "rows_per_s": rows / t_raw, "us_per_forward": t_raw * 1e6,
+                           "algorithmic_bytes_per_row": rb, "GB_s": rb * rows / t_raw / 1e9}
         t_ms = res["mask_stats"]
         gbs = rows * cfg.D * 4 / t_ms / 1e9
         out["mask_stats"] = {"what": "per-feature mean and variance of masks_agg", "rows": rows, "D": cfg.D,

@@ -115,6 +115,49 @@ int tabnet_get_precision(const tabnet_handle* h);
 tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float* logits,
                              float* masks_agg, float* masks_step, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * Raw rows: categorical embedding in front of the model, masks per raw column.
+ *
+ * The paper's records reach the model after a preprocessing stage (Sec. III-A); the UCI
+ * Adult rows carry 14 raw features (Sec. IV-A), and auditors read importance per raw
+ * feature (Table IV) from the masks each invocation returns (Sec. III-B).  The model the
+ * paper cites embeds every categorical column: level l of column c becomes row l of the
+ * column's table, so C raw columns become D = sum_c dim_c model features (continuous
+ * columns pass through).  The raw-row forward gathers the embeddings inside the fused
+ * kernel (the D-wide rows never exist in memory) and writes each mask per raw column:
+ * the sum of the column's model features.
+ * ------------------------------------------------------------------------------------ */
+
+/*
+ * tabnet_set_embeddings -- attach a categorical embedding to a loaded model (replacing any
+ * earlier one; waits for the device to be idle when it replaces one).
+ *   n_cols   raw columns C, in order; the model features are the columns' widths laid end to end
+ *   cards    host int32 [C]: levels of each categorical column; 0 marks a continuous column
+ *   dims     host int32 [C]: embedding width of each column (1 for a continuous column);
+ *            sum(dims) must equal the model's D
+ *   tables   host float32: the categorical columns' tables, each [card, dim] row-major,
+ *            concatenated in column order (copied; may be NULL if no column is categorical)
+ * Errors: TABNET_E_INVALID (bad spec), TABNET_E_UNSUPPORTED, TABNET_E_OOM, TABNET_E_HIP.
+ */
+tabnet_status tabnet_set_embeddings(tabnet_handle* h, int32_t n_cols, const int32_t* cards, const int32_t* dims,
+                                    const float* tables);
+
+/*
+ * tabnet_forward_raw -- tabnet_forward on raw rows, asynchronous on `stream`.
+ *   X_raw            device, float32 [B, C]: continuous values, and in a categorical column the
+ *                    level as a float (0, 1, ..., card - 1).  A value that is not such a level
+ *                    (negative, too large, fractional, NaN) embeds as a zero vector.
+ *   logits           device, float32 [B, n_out]
+ *   masks_agg_cols   device, float32 [B, C]: the aggregate mask summed over each column's features
+ *   masks_step_cols  device, float32 [n_steps, B, C] or NULL: each step mask, summed the same way
+ * The logits equal those of tabnet_forward on the embedded rows bit for bit, and each column's
+ * mask is the FP32 sum of that forward's masks over the column's features (formed on the
+ * matrix cores as a product with the 0/1 feature-to-column map).
+ * Errors: as tabnet_forward, and TABNET_E_INVALID if no embedding was set.
+ */
+tabnet_status tabnet_forward_raw(tabnet_handle* h, const float* X_raw, int64_t B, float* logits,
+                                 float* masks_agg_cols, float* masks_step_cols, void* stream);
+
 /* Release the device weights and the handle (NULL is ignored). Synchronises the device. */
 void tabnet_free(tabnet_handle* h);
 

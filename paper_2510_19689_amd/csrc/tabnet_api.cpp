@@ -27,6 +27,10 @@ tabnet_status hip_fail(tabnet_handle* h, hipError_t e, const char* what) {
 }
 
 void release(tabnet_handle* h) {
+  if (h->d_emb_meta) (void)hipFree(h->d_emb_meta);
+  if (h->d_emb_tables) (void)hipFree(h->d_emb_tables);
+  h->d_emb_meta = nullptr;
+  h->d_emb_tables = nullptr;
   if (h->d_wts) (void)hipFree(h->d_wts);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_affine) (void)hipFree(h->d_affine);
@@ -85,7 +89,7 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   if (st != TABNET_OK) return fail(st, "tabnet_load: " + err);
   const Shape sh = shape_of(m.cfg);
   const int kprec = precision == TABNET_FP32 ? 0 : (precision == TABNET_BF16 ? 1 : 2);
-  const KernelEntry* k = find_kernel(kprec, sh.DT, sh.NT, sh.KA0);
+  const KernelEntry* k = find_kernel(kprec, sh.DT, sh.NT, sh.KA0, false);
   if (!k) {
     char msg[256];
     std::snprintf(msg, sizeof msg,
@@ -100,10 +104,10 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   e = hipSetDevice(device);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
 
-  if (kernel_lds_bytes(k, m.cfg.D, m.cfg.n_out, m.cfg.n_d) > 160 * 1024) {
+  if (kernel_lds_bytes(k, m.cfg.D, m.cfg.n_out, m.cfg.n_d, 0, 0) > (size_t)kMaxLdsBytes) {
     return fail(TABNET_E_UNSUPPORTED, "tabnet_load: the model needs more LDS than a workgroup has");
   }
-  e = prepare_kernel(k, m.cfg.D, m.cfg.n_out, m.cfg.n_d);
+  e = prepare_kernel(k);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 
   Packed pk;
@@ -149,6 +153,81 @@ tabnet_status tabnet_forward(tabnet_handle* h, const float* X, int64_t B, float*
   return TABNET_OK;
 }
 
+tabnet_status tabnet_set_embeddings(tabnet_handle* h, int32_t n_cols, const int32_t* cards, const int32_t* dims,
+                                    const float* tables) {
+  if (!h || !cards || !dims) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: NULL argument");
+  if (h->failed) return fail(TABNET_E_HIP, "tabnet_set_embeddings: handle failed earlier on a HIP error");
+  const int D = h->cfg.D;
+  if (n_cols < 1 || n_cols > D) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: n_cols must be in [1, D]");
+  // per model feature f: {raw column, levels (0: continuous), index of f's entry in level
+  // 0's table row, table row width}
+  std::vector<int> meta(4 * (size_t)D);
+  int64_t at = 0, base = 0;
+  for (int c = 0; c < n_cols; ++c) {
+    if (cards[c] < 0 || dims[c] < 1 || (cards[c] == 0 && dims[c] != 1) || cards[c] > (1 << 24))
+      return fail(TABNET_E_INVALID,
+                  "tabnet_set_embeddings: need cards in [0, 2^24], dims >= 1, and dim 1 for a continuous column");
+    if (at + dims[c] > D) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: the widths add up to more than D");
+    for (int k = 0; k < dims[c]; ++k) {
+      int* d = &meta[4 * (size_t)(at + k)];
+      d[0] = c;
+      d[1] = cards[c];
+      d[2] = (int)(base + k);
+      d[3] = dims[c];
+    }
+    at += dims[c];
+    base += (int64_t)cards[c] * dims[c];
+    if (base > 0x7fffffffLL) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: tables too large");
+  }
+  if (at != D) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: the widths must add up to D");
+  if (base > 0 && !tables) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: NULL tables");
+  const KernelEntry* k = find_kernel(h->precision, h->shape.DT, h->shape.NT, h->shape.KA0, true);
+  if (!k) return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: no compiled raw-row kernel for this shape");
+  if (kernel_lds_bytes(k, D, h->cfg.n_out, h->cfg.n_d, n_cols, 0) > (size_t)kMaxLdsBytes)
+    return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: the raw-row kernel needs more LDS than a workgroup has");
+  const bool tab_lds = kernel_lds_bytes(k, D, h->cfg.n_out, h->cfg.n_d, n_cols, (int)base) <= (size_t)kMaxLdsBytes;
+  tabnet_status st = ensure_device(h);
+  if (st != TABNET_OK) return st;
+  hipError_t e = prepare_kernel(k);
+  if (e != hipSuccess) return hip_fail(h, e, "hipFuncSetAttribute");
+  // replace any earlier embedding; the device must be idle for the old buffers to go
+  if (h->d_emb_meta || h->d_emb_tables) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
+    if (h->d_emb_meta) (void)hipFree(h->d_emb_meta);
+    if (h->d_emb_tables) (void)hipFree(h->d_emb_tables);
+    h->d_emb_meta = nullptr;
+    h->d_emb_tables = nullptr;
+    h->emb_C = 0;
+  }
+  std::vector<float> tab(tables ? tables : nullptr, tables ? tables + base : nullptr);
+  if ((st = upload(h, meta, &h->d_emb_meta, "embedding map")) != TABNET_OK ||
+      (st = upload(h, tab, &h->d_emb_tables, "embedding tables")) != TABNET_OK)
+    return st;
+  h->kernel_raw = k;
+  h->emb_C = n_cols;
+  h->emb_tab_len = (int)base;
+  h->emb_tab_lds = tab_lds;
+  return TABNET_OK;
+}
+
+tabnet_status tabnet_forward_raw(tabnet_handle* h, const float* X_raw, int64_t B, float* logits,
+                                 float* masks_agg_cols, float* masks_step_cols, void* stream) {
+  if (!h) return fail(TABNET_E_INVALID, "tabnet_forward_raw: NULL handle");
+  if (h->failed) return fail(TABNET_E_HIP, "tabnet_forward_raw: handle failed earlier on a HIP error");
+  if (h->emb_C == 0) return fail(TABNET_E_INVALID, "tabnet_forward_raw: no embedding set (tabnet_set_embeddings)");
+  if (B < 0 || B > 0x7fffffffLL) return fail(TABNET_E_INVALID, "tabnet_forward_raw: B out of range");
+  if (B == 0) return TABNET_OK;
+  if (!X_raw || !logits || !masks_agg_cols)
+    return fail(TABNET_E_INVALID, "tabnet_forward_raw: NULL X_raw, logits or masks_agg_cols");
+  tabnet_status st = ensure_device(h);
+  if (st != TABNET_OK) return st;
+  hipError_t e = tabnet::enqueue_forward_raw(h, X_raw, B, nullptr, logits, masks_agg_cols, masks_step_cols,
+                                             (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(h, e, "tabnet_forward_raw: kernel launch");
+  return TABNET_OK;
+}
+
 void tabnet_free(tabnet_handle* h) {
   if (!h) return;
   if (ensure_device(h) == TABNET_OK) (void)hipDeviceSynchronize();
@@ -182,12 +261,28 @@ FwdArgs forward_args(const tabnet_handle* h, const float* X, int64_t B, const in
   a.n_ind = h->cfg.n_indep;
   a.n_out = h->cfg.n_out;
   a.gamma = (float)h->cfg.gamma;
+  a.emb_meta = nullptr;
+  a.emb_tables = nullptr;
+  a.C = 0;
+  a.tab_len = 0;
+  a.tab_lds = 0;
   return a;
 }
 
 hipError_t enqueue_forward(const tabnet_handle* h, const float* X, int64_t B, const int64_t* B_dev,
                            float* logits, float* masks_agg, float* masks_step, hipStream_t stream) {
   return launch_forward(h->kernel, forward_args(h, X, B, B_dev, logits, masks_agg, masks_step), stream);
+}
+
+hipError_t enqueue_forward_raw(const tabnet_handle* h, const float* X_raw, int64_t B, const int64_t* B_dev,
+                               float* logits, float* masks_agg, float* masks_step, hipStream_t stream) {
+  FwdArgs a = forward_args(h, X_raw, B, B_dev, logits, masks_agg, masks_step);
+  a.emb_meta = h->d_emb_meta;
+  a.emb_tables = h->d_emb_tables;
+  a.C = h->emb_C;
+  a.tab_len = h->emb_tab_len;
+  a.tab_lds = h->emb_tab_lds ? 1 : 0;
+  return launch_forward(h->kernel_raw, a, stream);
 }
 
 void set_error(const std::string& msg) { g_err = msg; }

@@ -10,9 +10,9 @@
 
 namespace tabnet {
 struct KernelEntry;
-const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0);
-size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d);
-hipError_t prepare_kernel(const KernelEntry* k, int D, int n_out, int n_d);
+const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw);
+size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
+hipError_t prepare_kernel(const KernelEntry* k);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
 }  // namespace tabnet
 
@@ -28,6 +28,13 @@ struct tabnet_handle {
   float* d_wfin = nullptr;
   int n_chunks = 0;
   bool failed = false;
+  // categorical embedding of raw rows (tabnet_set_embeddings); C = 0 until set
+  const tabnet::KernelEntry* kernel_raw = nullptr;
+  int* d_emb_meta = nullptr;
+  float* d_emb_tables = nullptr;
+  int emb_C = 0;
+  int emb_tab_len = 0;           // floats in d_emb_tables
+  bool emb_tab_lds = false;      // the tables fit in LDS beside everything else
 };
 
 namespace tabnet {
@@ -38,6 +45,9 @@ FwdArgs forward_args(const tabnet_handle* h, const float* X, int64_t B, const in
                      float* logits, float* masks_agg, float* masks_step);
 hipError_t enqueue_forward(const tabnet_handle* h, const float* X, int64_t B, const int64_t* B_dev,
                            float* logits, float* masks_agg, float* masks_step, hipStream_t stream);
+// The same over raw rows X_raw[B, C] (needs tabnet_set_embeddings): masks per raw column.
+hipError_t enqueue_forward_raw(const tabnet_handle* h, const float* X_raw, int64_t B, const int64_t* B_dev,
+                               float* logits, float* masks_agg, float* masks_step, hipStream_t stream);
 // Sets the calling thread's tabnet_last_error message.
 void set_error(const std::string& msg);
 }  // namespace tabnet

@@ -328,8 +328,72 @@ __device__ __forceinline__ void stage_out(const float* st, float* dst, int n, in
   }
 }
 
+// Membership of the lane's features in raw column `col`: bit 4 t + i is set when model
+// feature 16 t + 4 g + i (g = lane / 16) belongs to it.  All reads of the map are issued
+// before any is compared.
+template <int DT>
+__device__ __forceinline__ uint64_t column_bits(const int4* fdesc, int D, int col, int g) {
+  int fc[DT][4];
+#pragma unroll
+  for (int t = 0; t < DT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fc[t][i] = fdesc[min(16 * t + 4 * g + i, D - 1)].x;
+  uint64_t b = 0;
+#pragma unroll
+  for (int t = 0; t < DT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (16 * t + 4 * g + i < D && fc[t][i] == col) b |= 1ull << (4 * t + i);
+  return b;
+}
+
+// Raw-column view of a mask held in the lane layout (lane = row rl, features 16 t + 4 g + i):
+// out[row][c] = sum of the row's mask over the features of raw column c, for all C
+// columns, as FP32 MFMA products with the 0/1 membership matrix S[c][f] = (column of f == c).
+// For 16 columns at a time the B operand of MFMA (t, i) is the lane's own value m[t][i]
+// (k slot g holds feature 16 t + 4 g + i of row rl) and the A operand is the membership
+// of that feature in column 16 ct + rl, taken from a bit mask (bits0 for the first 16
+// columns, kept for the whole kernel); the products are exact and the sums are FP32.
+// The result lands as out[row rl][16 ct + 4 g + j] and is written to the wave's LDS
+// staging area as [16][C] rows, ready for stage_out.
+template <int DT>
+__device__ __forceinline__ void reduce_columns(const float (&m)[DT][4], uint64_t bits0, const int4* fdesc, int D,
+                                               int C, float* st, int lane) {
+  const int g = lane >> 4;
+  const int rl = lane & 15;
+  for (int ct = 0; 16 * ct < C; ++ct) {
+    uint64_t bits = bits0;
+    if (ct > 0) {
+      // columns past the first 16 (wide raw layouts only): one map read at a time, to keep
+      // registers free in the middle of a step
+      bits = 0;
+#pragma nounroll
+      for (int k = 0; k < 4 * DT; ++k) {
+        const int f = 16 * (k >> 2) + 4 * g + (k & 3);
+        if (f < D && fdesc[f].x == 16 * ct + rl) bits |= 1ull << k;
+      }
+    }
+    f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};   // two independent chains
+#pragma unroll
+    for (int t = 0; t < DT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float a = (bits >> (4 * t + i)) & 1 ? 1.f : 0.f;
+        if ((i & 1) == 0)
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, m[t][i], acc0, 0, 0, 0);
+        else
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, m[t][i], acc1, 0, 0, 0);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * ct + 4 * g + j;
+      if (c < C) st[rl * C + c] = acc0[j] + acc1[j];
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
-template <int PREC, int DT, int NT, int KA0, int R, int W>
+template <int PREC, int DT, int NT, int KA0, int R, int W, bool RAW>
 __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   constexpr Plan PL = make_plan(PREC, DT, NT, KA0);
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
@@ -349,6 +413,28 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   // the final map, staged in LDS behind the mask staging areas (visible after the first barrier)
   float* wfin_s = reinterpret_cast<float*>(smem + 2 * PL.buf) + (size_t)W * 16 * R * D;
   for (int e = threadIdx.x; e < A.n_out * n_d; e += 64 * W) wfin_s[e] = A.wfin[e];
+  // raw rows: the embedding map, staged behind the final map (the prologue needs it, so the
+  // workgroup synchronises once more)
+  int* meta_s = reinterpret_cast<int*>(wfin_s + ((A.n_out * n_d + 3) & ~3));   // 16-byte aligned
+  // and the embedding tables after it when they fit (tab_lds), else they are read from L2
+  float* tab_s = reinterpret_cast<float*>(meta_s + 4 * D);
+  if constexpr (RAW) {
+    // this wave's raw rows go straight into its LDS staging area (global_load_lds_dword:
+    // lane l of an instruction writes base + 4 l), while the workgroup copies the maps
+    {
+      const float* src = A.X + wrow0 * A.C;
+      const int n = live_rows * A.C;
+      for (int j = 0; 64 * j < n; ++j)
+        if (64 * j + lane < n)
+          __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 64 * j + lane),
+                                           (void __attribute__((address_space(3)))*)(stage + 64 * j), 4, 0, 0);
+    }
+    for (int e = threadIdx.x; e < 4 * D; e += 64 * W) meta_s[e] = A.emb_meta[e];
+    if (A.tab_lds)
+      for (int e = threadIdx.x; e < A.tab_len; e += 64 * W) tab_s[e] = A.emb_tables[e];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
   bool live[R];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) live[rb] = 16 * rb + rl < live_rows;
@@ -368,8 +454,35 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   ws.begin();     // first chunk -> buffer 0
 
   // ---- input batch norm (folded to a per-column affine map) ----
+  // Raw rows are embedded first.  Model feature f is described by fdesc[f] = (raw column
+  // c, its number of levels (0: continuous), index of the feature's entry in level 0's
+  // table row, table row width): a continuous column passes through, a level l of a
+  // categorical column contributes tables[z + l * w], and a value that is not a level in
+  // [0, card) contributes 0.
   float x[R][DT][4];
   const bool vec4 = (D & 3) == 0;
+  const int C = A.C;
+  const int4* fdesc = reinterpret_cast<const int4*>(meta_s);
+  float raw[RAW ? R : 1][RAW ? DT : 1][4];
+  uint64_t col_bits0 = 0;     // raw rows: membership of this lane's features in column rl
+  if constexpr (RAW) {
+    // every feature is gathered from LDS: the raw rows (staged above), the maps, the tables
+    col_bits0 = column_bits<DT>(fdesc, D, rl, g);
+    const float* tab = A.tab_lds ? tab_s : A.emb_tables;
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+      for (int t = 0; t < DT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int4 d = fdesc[feat_ok(t, i) ? 16 * t + 4 * g + i : 0];
+          const float q = stage[(16 * rb + rl) * C + d.x];
+          const bool level = q >= 0.f && q < (float)d.y && q == floorf(q);   // false for card 0
+          const float tv = tab[level ? d.z + (int)q * d.w : 0];
+          const float e = d.y == 0 ? q : (level ? tv : 0.f);
+          raw[rb][t][i] = live[rb] && feat_ok(t, i) ? e : 0.f;
+        }
+  }
 #pragma unroll
   for (int t = 0; t < DT; ++t) {
     const f4 sc = *reinterpret_cast<const f4*>(A.in_affine + 16 * t + 4 * g);
@@ -378,7 +491,10 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     for (int rb = 0; rb < R; ++rb) {
       float v[4] = {0.f, 0.f, 0.f, 0.f};
       const float* xr = A.X + (wrow0 + 16 * rb + rl) * D + 16 * t + 4 * g;
-      if (live[rb]) {
+      if constexpr (RAW) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = raw[rb][t][i];
+      } else if (live[rb]) {
         if (vec4) {
           if (feat_ok(t, 0)) {
             const f4 q = *reinterpret_cast<const f4*>(xr);
@@ -421,7 +537,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
   }
 
-  const int64_t step_stride = B * (int64_t)D;
+  const int64_t step_stride = B * (int64_t)(RAW ? C : D);
   for (int s = 1; s <= A.n_steps; ++s) {
     // ---- attentive transformer: z = P * (a W_att'^T + b_att') ----
     {
@@ -552,17 +668,24 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     // ---- step mask out (through LDS, coalesced) first, so that the stores drain while
     // the prior update and the masked input are computed ----
     if (A.masks_step != nullptr) {
+      if constexpr (RAW) {
 #pragma unroll
-      for (int rb = 0; rb < R; ++rb) {
-        float* sr = stage + (16 * rb + rl) * D + 4 * g;
+        for (int rb = 0; rb < R; ++rb) reduce_columns<DT>(M[rb], col_bits0, fdesc, D, C, stage + 16 * rb * C, lane);
+        lds_wave_sync();
+        stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * C, live_rows * C, lane);
+      } else {
 #pragma unroll
-        for (int t = 0; t < DT; ++t)
+        for (int rb = 0; rb < R; ++rb) {
+          float* sr = stage + (16 * rb + rl) * D + 4 * g;
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
+          for (int t = 0; t < DT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
+        }
+        lds_wave_sync();
+        stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
       }
-      lds_wave_sync();
-      stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
     }
     BOp<PREC, DT, R> u;
 #pragma unroll
@@ -624,15 +747,23 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       for (int i = 0; i < 4; ++i) den += agg[rb][t][i];
     den = row_sum(den);
     const float inv = den > 0.f ? 1.0f / den : 0.f;
-    float* sr = stage + (16 * rb + rl) * D + 4 * g;
+    if constexpr (RAW) {
 #pragma unroll
-    for (int t = 0; t < DT; ++t)
+      for (int t = 0; t < DT; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (feat_ok(t, i)) sr[16 * t + i] = agg[rb][t][i] * inv;
+        for (int i = 0; i < 4; ++i) agg[rb][t][i] *= inv;
+      reduce_columns<DT>(agg[rb], col_bits0, fdesc, D, C, stage + 16 * rb * C, lane);
+    } else {
+      float* sr = stage + (16 * rb + rl) * D + 4 * g;
+#pragma unroll
+      for (int t = 0; t < DT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (feat_ok(t, i)) sr[16 * t + i] = agg[rb][t][i] * inv;
+    }
   }
   lds_wave_sync();
-  stage_out(stage, A.masks_agg + wrow0 * D, live_rows * D, lane);
+  stage_out(stage, (RAW ? A.masks_agg + wrow0 * C : A.masks_agg + wrow0 * D), live_rows * (RAW ? C : D), lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -641,6 +772,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 // fixed per shape so that a row's arithmetic never depends on the batch size.
 struct KernelEntry {
   int prec, DT, NT, KA0, R, W;
+  bool raw;                  // embeds raw rows and writes masks per raw column
   void (*fn)(FwdArgs);
   Plan plan;
 };
@@ -651,8 +783,9 @@ struct KernelEntry {
 #ifndef TABNET_ADULT_W
 #define TABNET_ADULT_W 8
 #endif
-#define TABNET_SHAPE(P, DT, NT, KA0, R, W) \
-  {P, DT, NT, KA0, R, W, tabnet_forward_kernel<P, DT, NT, KA0, R, W>, make_plan(P, DT, NT, KA0)},
+#define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                          \
+  {P, DT, NT, KA0, R, W, false, tabnet_forward_kernel<P, DT, NT, KA0, R, W, false>, make_plan(P, DT, NT, KA0)}, \
+      {P, DT, NT, KA0, R, W, true, tabnet_forward_kernel<P, DT, NT, KA0, R, W, true>, make_plan(P, DT, NT, KA0)},
 #define TABNET_SHAPES(P)          \
   TABNET_SHAPE(P, 1, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 2, 1, 0, 1, 4)  \
@@ -664,26 +797,34 @@ struct KernelEntry {
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)};
 
-const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0) {
+const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
   for (const auto& e : kKernels)
-    if (e.prec == prec && e.DT == DT && e.NT == NT && e.KA0 == KA0) return &e;
+    if (e.prec == prec && e.DT == DT && e.NT == NT && e.KA0 == KA0 && e.raw == raw) return &e;
   return nullptr;
 }
 
-size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d) {
-  return 2 * (size_t)k->plan.buf + ((size_t)k->W * 16 * k->R * D + (size_t)n_out * n_d) * sizeof(float);
+// LDS of one workgroup: the two weight buffers, the per-wave mask staging areas, the
+// final map and, for the raw-row kernels, the feature descriptors (4 D ints, 16-byte
+// aligned) and the tables when they are staged.
+size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len) {
+  (void)C;
+  const size_t wf = k->raw ? ((size_t)n_out * n_d + 3) / 4 * 4 : (size_t)n_out * n_d;
+  return 2 * (size_t)k->plan.buf + ((size_t)k->W * 16 * k->R * D + wf) * sizeof(float) +
+         (k->raw ? 4 * (size_t)D * sizeof(int) + (size_t)tab_lds_len * sizeof(float) : 0);
 }
 
-hipError_t prepare_kernel(const KernelEntry* k, int D, int n_out, int n_d) {
+// The attribute is a cap, not a reservation: it is set to the whole LDS of a workgroup so
+// that models of different widths sharing a kernel never lower each other's cap.
+hipError_t prepare_kernel(const KernelEntry* k) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k->fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)kernel_lds_bytes(k, D, n_out, n_d));
+                             (int)kMaxLdsBytes);
 }
 
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream) {
   const int64_t rows_per_block = 16LL * k->R * k->W;
   const int64_t blocks = (a.B + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W), kernel_lds_bytes(k, a.D, a.n_out, a.n_d),
-                     stream, a);
+  hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W),
+                     kernel_lds_bytes(k, a.D, a.n_out, a.n_d, a.C, a.tab_lds ? a.tab_len : 0), stream, a);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ namespace tabnet {
 constexpr int kMaxFtLayers = 96;   // n_shared + (n_steps + 1) * n_indep
 constexpr int kMaxSteps = 32;
 constexpr int kFrag = 1024;        // bytes of one A fragment
+constexpr int kMaxLdsBytes = 160 * 1024;   // LDS of one workgroup on gfx950
 constexpr int kChunkTarget = 40960;
 
 struct ChunkRec {
@@ -109,6 +110,13 @@ struct FwdArgs {
   const int64_t* B_dev;       // if set: live row count in device memory, <= B
   int D, n_d, n_a, n_steps, n_sh, n_ind, n_out, n_chunks;
   float gamma;
+  // Raw rows (the RAW kernels): X is [B, C] raw columns, embedded on the fly, and both
+  // masks are written per raw column ([B, C] and [S, B, C]).
+  const int* emb_meta;        // [D][4]: raw column, levels (0: continuous), table offset, width
+  const float* emb_tables;    // the categorical columns' tables, concatenated
+  int C;
+  int tab_len;                // floats in emb_tables
+  int tab_lds;                // 1: the kernel copies the tables into LDS
 };
 
 }  // namespace tabnet

@@ -72,6 +72,10 @@ def lib() -> ctypes.CDLL:
     L.tabnet_get_precision.restype = i32
     L.tabnet_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.tabnet_forward.restype = i32
+    L.tabnet_set_embeddings.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    L.tabnet_set_embeddings.restype = i32
+    L.tabnet_forward_raw.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.tabnet_forward_raw.restype = i32
     L.tabnet_free.argtypes = [vp]
     L.tabnet_free.restype = None
     L.tabnet_last_error.argtypes = []
@@ -174,6 +178,41 @@ class Model:
                                    masks_agg.data_ptr(),
                                    None if masks_step is None else masks_step.data_ptr(),
                                    _stream_ptr(stream)))
+
+    def set_embeddings(self, cards, dims, tables) -> None:
+        """tabnet_set_embeddings: cards / dims per raw column (int32), tables the categorical
+        columns' [card, dim] tables concatenated (float32)."""
+        import numpy as np
+        cards = np.ascontiguousarray(cards, dtype=np.int32)
+        dims = np.ascontiguousarray(dims, dtype=np.int32)
+        tables = np.ascontiguousarray(tables, dtype=np.float32)
+        if cards.shape != dims.shape or cards.ndim != 1:
+            raise ValueError("cards and dims must be 1-D arrays of equal length")
+        check(lib().tabnet_set_embeddings(self._h, int(cards.size), cards.ctypes.data, dims.ctypes.data,
+                                          tables.ctypes.data if tables.size else None))
+        self.n_cols = int(cards.size)
+
+    def forward_raw_into(self, X_raw, logits, masks_agg_cols, masks_step_cols=None, stream=None) -> None:
+        """tabnet_forward_raw on caller-provided device tensors (float32, contiguous)."""
+        check(lib().tabnet_forward_raw(self._h, X_raw.data_ptr(), int(X_raw.shape[0]), logits.data_ptr(),
+                                       masks_agg_cols.data_ptr(),
+                                       None if masks_step_cols is None else masks_step_cols.data_ptr(),
+                                       _stream_ptr(stream)))
+
+    def forward_raw(self, X_raw, with_steps: bool = True, stream=None) -> Tuple:
+        """Returns (logits[B, n_out], masks_agg[B, C], masks_step[S, B, C] or None)."""
+        import torch
+        C = getattr(self, "n_cols", 0)
+        if X_raw.dtype != torch.float32 or not X_raw.is_contiguous() or X_raw.dim() != 2 or X_raw.shape[1] != C:
+            raise ValueError(f"X_raw must be a contiguous float32 [B, {C}] tensor (after set_embeddings)")
+        c = self.config
+        B = int(X_raw.shape[0])
+        dev = X_raw.device
+        lo = torch.empty((B, c.n_out), dtype=torch.float32, device=dev)
+        ag = torch.empty((B, C), dtype=torch.float32, device=dev)
+        ms = torch.empty((c.n_steps, B, C), dtype=torch.float32, device=dev) if with_steps else None
+        self.forward_raw_into(X_raw, lo, ag, ms, stream)
+        return lo, ag, ms
 
     def outputs(self, B: int, with_steps: bool = True):
         import torch

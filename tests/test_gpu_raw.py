@@ -1,0 +1,163 @@
+"""GPU parity of the raw-row forward (categorical embedding gathered in the kernel, masks
+per raw column) with the FP64 oracle (oracle/embed.py) and with tabnet_forward on the
+embedded rows.
+
+Gates.  The logits must equal tabnet_forward's on the embedded rows bit for bit (the kernel
+sees the same FP32 features), and each raw column's mask the FP32 sum of that forward's
+feature masks (|d| <= 1e-6: a sum of at most 16 values below 1).  Against the FP64 oracle
+the FP32 gates of the feature-level tests apply, the mask gate times the widest column
+(16 features): HR-shaped logits 1e-5 relative and masks 1e-6, Adult-shaped 1e-4 and
+16 x 1e-5; BF16 logits 2e-2, aggregate-mask L1 1e-2, step-mask L1 2e-2."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import embed as oe  # noqa: E402
+from paper_2510_19689_amd import synth, tabnet as tb  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"adult108": "adult", "hr35": "hr"}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+
+
+def model(name, prec, tmp_path):
+    params = synth.make_params(synth.WORKLOADS[name]["cfg"], synth.WEIGHT_SEED[name])
+    path = str(tmp_path / f"{name}.tnw")
+    synth.write_weights(params, path)
+    return params, tb.Model(path, prec)
+
+
+def raw_rows(name, B, seed=None):
+    return synth.make_raw_inputs(KINDS[name], B, synth.DATA_SEED[name] if seed is None else seed)
+
+
+def to_np(*ts):
+    torch.cuda.synchronize()
+    return [None if t is None else t.cpu().numpy() for t in ts]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("name", ["adult108", "hr35"])
+@pytest.mark.parametrize("B", [1, 63, 65, 1000])
+def test_raw_equals_embedded_forward(name, prec, B, tmp_path):
+    _say(f"case raw vs embedded {name} {prec} B={B}")
+    params, m = model(name, prec, tmp_path)
+    with m:
+        X_raw, cards, dims, tables = raw_rows(name, B)
+        X = synth.make_inputs(KINDS[name], B, synth.DATA_SEED[name])
+        m.set_embeddings(cards, dims, tables)
+        lo_r, ag_r, ms_r = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+        lo, ag, ms = to_np(*m.forward(torch.from_numpy(X).cuda()))
+    np.testing.assert_array_equal(lo_r, lo)
+    np.testing.assert_allclose(ag_r, oe.reduce_columns(ag, dims), rtol=0, atol=1e-6)
+    np.testing.assert_allclose(ms_r, oe.reduce_columns(ms, dims), rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 2000)])
+def test_raw_fp32_matches_oracle(name, B, tmp_path):
+    _say(f"case raw fp32 vs oracle {name} B={B}")
+    params, m = model(name, "fp32", tmp_path)
+    X_raw, cards, dims, tables = raw_rows(name, B)
+    with m:
+        m.set_embeddings(cards, dims, tables)
+        lo, ag, ms = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+    rlo, rag, rms = oe.forward_raw(params, X_raw, cards, dims, tables)
+    rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+    cfg = synth.WORKLOADS[name]["cfg"]
+    lt, mt = (1e-5, 1e-6 * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)) if name == "hr35" else (1e-4, 16e-5)
+    _say(name, "logit_rel", rel, "agg", np.abs(ag - rag).max(), "step", np.abs(ms - rms).max())
+    assert rel <= lt
+    assert np.abs(ag - rag).max() <= mt and np.abs(ms - rms).max() <= mt
+    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=1e-5)
+
+
+def test_raw_bf16_matches_oracle(tmp_path):
+    _say("case raw bf16 vs oracle adult108")
+    params, m = model("adult108", "bf16", tmp_path)
+    X_raw, cards, dims, tables = raw_rows("adult108", 3000)
+    with m:
+        m.set_embeddings(cards, dims, tables)
+        lo, ag, ms = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+    rlo, rag, rms = oe.forward_raw(params, X_raw, cards, dims, tables)
+    assert np.abs(lo - rlo).max() <= 2e-2
+    assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.999
+    assert np.abs(ag - rag).sum(-1).max() <= 1e-2 and np.abs(ms - rms).sum(-1).max() <= 2e-2
+
+
+def test_invalid_levels_embed_to_zero(tmp_path):
+    _say("case raw invalid levels")
+    params, m = model("adult108", "fp32", tmp_path)
+    X_raw, cards, dims, tables = raw_rows("adult108", 64)
+    cat_cols = np.nonzero(cards)[0]
+    bad = [-1.0, 1e9, 2.5, np.nan, np.inf, -0.5, float(cards[cat_cols[0]])]
+    for k, v in enumerate(bad):
+        X_raw[k, cat_cols[k % len(cat_cols)]] = v
+    X_raw[10, cat_cols[0]] = float(cards[cat_cols[0]] - 1)     # the last valid level
+    with m:
+        m.set_embeddings(cards, dims, tables)
+        lo, ag, ms = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+    rlo, rag, rms = oe.forward_raw(params, X_raw, cards, dims, tables)
+    assert np.isfinite(lo).all()
+    rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+    assert rel <= 1e-4 and np.abs(ms - rms).max() <= 16e-5
+
+
+def test_optional_steps_empty_batch_and_row_independence(tmp_path):
+    _say("case raw optional steps / B=0 / row independence")
+    params, m = model("adult108", "bf16", tmp_path)
+    X_raw, cards, dims, tables = raw_rows("adult108", 700)
+    with m:
+        m.set_embeddings(cards, dims, tables)
+        Xd = torch.from_numpy(X_raw).cuda()
+        lo, ag, ms = m.forward_raw(Xd)
+        lo2, ag2, none = m.forward_raw(Xd, with_steps=False)
+        assert none is None
+        sub = m.forward_raw(Xd[123:456].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(lo, lo2) and torch.equal(ag, ag2)
+        assert torch.equal(sub[0], lo[123:456]) and torch.equal(sub[1], ag[123:456])
+        assert torch.equal(sub[2], ms[:, 123:456])
+        empty = torch.zeros((0, 14), dtype=torch.float32, device="cuda")
+        r = m.forward_raw(empty)
+        torch.cuda.synchronize()
+        assert r[0].shape == (0, 2)
+
+
+def test_embedding_spec_errors_and_replacement(tmp_path):
+    _say("case raw spec errors")
+    params, m = model("hr35", "fp32", tmp_path)
+    X_raw, cards, dims, tables = raw_rows("hr35", 100)
+    with m:
+        with pytest.raises(tb.TabNetError) as e:      # no embedding yet
+            m.forward_raw_into(torch.zeros((4, 35), device="cuda"), torch.zeros((4, 2), device="cuda"),
+                               torch.zeros((4, 35), device="cuda"))
+        assert e.value.status == tb.E_INVALID
+        for c, d in [(cards, dims[:-1]), (cards, np.where(np.arange(35) == 0, 2, dims)),
+                     (np.where(np.arange(35) == 30, -1, cards), dims)]:
+            n = min(len(c), len(d))
+            with pytest.raises((tb.TabNetError, ValueError)):
+                m.set_embeddings(c[:n] if len(c) != len(d) else c, d, tables)
+        # widths that do not add up to D
+        with pytest.raises(tb.TabNetError):
+            m.set_embeddings(cards[:-1], dims[:-1], tables[:-int(cards[-1])])
+        # an all-continuous spec is the plain forward, and a later spec replaces it
+        X = synth.make_inputs("hr", 100, synth.DATA_SEED["hr35"])
+        m.set_embeddings(np.zeros(35), np.ones(35), np.zeros(0))
+        a = to_np(*m.forward_raw(torch.from_numpy(X).cuda()))
+        b = to_np(*m.forward(torch.from_numpy(X).cuda()))
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u, v)
+        m.set_embeddings(cards, dims, tables)
+        c = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+        np.testing.assert_array_equal(c[0], b[0])
