@@ -33,8 +33,10 @@ tabnet_status tabnet_hook_parse(const void* buf, size_t len, tabnet_config* cfg)
 tabnet_status tabnet_hook_fold(const void* buf, size_t len, int layer, double* Wf, double* bf,
                                int* rows, int* cols);
 
-/* Packed sizes of the model for a precision: bytes of the packed GEMM units (fragments
- * and shifts) and the number of weight-stream chunks the kernel consumes per forward. */
+/* Packed sizes of the model for a precision, in the chunk layout of the compiled kernel
+ * for its shape: bytes of the packed GEMM units (fragments and shifts) and the number of
+ * weight-stream chunks the kernel consumes per forward.  TABNET_E_UNSUPPORTED if no
+ * kernel covers the shape. */
 tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precision,
                                        int64_t* wts_bytes, int64_t* n_chunks);
 

@@ -14,6 +14,7 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw);
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
 hipError_t prepare_kernel(const KernelEntry* k);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
+const Plan* kernel_plan(const KernelEntry* k);
 }  // namespace tabnet
 
 struct tabnet_handle {

@@ -4,6 +4,7 @@
 #include <string>
 #include <vector>
 
+#include "tabnet_handle.hpp"
 #include "tabnet_pack.hpp"
 
 using namespace tabnet;
@@ -52,8 +53,12 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   std::string err;
   tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
   if (st != TABNET_OK) return st;
+  if (precision < TABNET_FP32 || precision > TABNET_FP8_E4M3) return TABNET_E_INVALID;
+  const Shape sh = shape_of(m.cfg);
+  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);
+  if (!k) return TABNET_E_UNSUPPORTED;
   Packed pk;
-  pack_model(m, precision, &pk);
+  pack_model(m, precision, *kernel_plan(k), &pk);
   *wts_bytes = (int64_t)pk.wts.size();
   *n_chunks = (int64_t)pk.chunks.size();
   return TABNET_OK;

@@ -187,6 +187,7 @@ __device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC
 #endif
 template <int W, int BUF>
 struct WeightStream {
+  static constexpr int kW = W;
   static constexpr int T = 64 * W;
   static constexpr int NSTG = (BUF / 16 + T - 1) / T;
   unsigned char* lds;            // 2 * BUF bytes
@@ -303,7 +304,7 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
 template <int PREC, int DT, int NT, int KA0, int R, class WS>
 __device__ __forceinline__ void ft_pass(WS& ws, int L, const BOp<PREC, DT, R>& u,
                                         float (&h)[R][NT][4], int lane) {
-  constexpr Plan P = make_plan(PREC, DT, NT, KA0);
+  constexpr Plan P = make_plan(PREC, DT, NT, KA0, chunk_target(DT, R, WS::kW));
   glu_layer<PREC, DT, NT, R, P.first.unit, P.first.upc, P.first.nchunks>(ws, u, h, true, lane);
   for (int l = 1; l < L; ++l) {
     BOp<PREC, NT, R> bh;
@@ -395,7 +396,7 @@ __device__ __forceinline__ void reduce_columns(const float (&m)[DT][4], uint64_t
 // ------------------------------------------------------------------------------------
 template <int PREC, int DT, int NT, int KA0, int R, int W, bool RAW>
 __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
-  constexpr Plan PL = make_plan(PREC, DT, NT, KA0);
+  constexpr Plan PL = make_plan(PREC, DT, NT, KA0, chunk_target(DT, R, W));
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
@@ -783,9 +784,14 @@ struct KernelEntry {
 #ifndef TABNET_ADULT_W
 #define TABNET_ADULT_W 8
 #endif
-#define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                          \
-  {P, DT, NT, KA0, R, W, false, tabnet_forward_kernel<P, DT, NT, KA0, R, W, false>, make_plan(P, DT, NT, KA0)}, \
-      {P, DT, NT, KA0, R, W, true, tabnet_forward_kernel<P, DT, NT, KA0, R, W, true>, make_plan(P, DT, NT, KA0)},
+#ifndef TABNET_WIDE_W
+#define TABNET_WIDE_W 4
+#endif
+#define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                                 \
+  {P, DT, NT, KA0, R, W, false, tabnet_forward_kernel<P, DT, NT, KA0, R, W, false>,                      \
+   make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},                                                   \
+      {P, DT, NT, KA0, R, W, true, tabnet_forward_kernel<P, DT, NT, KA0, R, W, true>,                    \
+       make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},
 #define TABNET_SHAPES(P)          \
   TABNET_SHAPE(P, 1, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 2, 1, 0, 1, 4)  \
@@ -793,7 +799,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 4, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 2, 1, 1, 4)  \
   TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
-  TABNET_SHAPE(P, 13, 8, 4, 1, 4)
+  TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)};
 

@@ -68,14 +68,23 @@ struct GemmPlan {
 constexpr int kblocks(int prec, int KT) { return prec == 0 ? KT : (KT + 1) / 2; }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Units per chunk: balanced chunks of at most kChunkTarget bytes (one unit if a single
-// unit is larger).
-constexpr GemmPlan gemm_plan(int unit, int nunits) {
-  const int nch0 = cdiv(unit * nunits, kChunkTarget);
+// Units per chunk: balanced chunks of at most `target` bytes (one unit if a single unit
+// is larger).
+constexpr GemmPlan gemm_plan(int unit, int nunits, int target) {
+  const int nch0 = cdiv(unit * nunits, target);
   int upc = cdiv(nunits, nch0 < 1 ? 1 : nch0);
-  const int cap = kChunkTarget / unit < 1 ? 1 : kChunkTarget / unit;
+  const int cap = target / unit < 1 ? 1 : target / unit;
   if (upc > cap) upc = cap;
   return GemmPlan{unit, nunits, upc, cdiv(nunits, upc)};
+}
+
+// Bytes of one LDS weight buffer for a workgroup of W waves of R 16-row blocks: at most
+// kChunkTarget, and small enough that the two buffers fit beside the per-wave mask
+// staging areas (W * 16 R rows of up to 16 DT features) with 4 KiB left for the final
+// map and the raw-row maps.
+constexpr int chunk_target(int DT, int R, int W) {
+  const int room = (kMaxLdsBytes - W * 16 * R * 16 * DT * 4 - 4096) / 2 / 1024 * 1024;
+  return room < kChunkTarget ? (room < 8192 ? 8192 : room) : kChunkTarget;
 }
 
 struct Plan {
@@ -88,11 +97,11 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 // prec: 0 FP32, 1 BF16, 2 E4M3 weights (BF16 fragments holding the E4M3 codes, plus one
 // FP32 scale per output channel after the shifts).  DT = ceil(D/16), NT = ceil(N/16),
 // KA0 = floor(n_d/16).
-constexpr Plan make_plan(int prec, int DT, int NT, int KA0) {
+constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const int sc = prec == 2 ? 2 : 1;   // shifts, or shifts + scales
-  const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128 * sc, NT);
-  const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128 * sc, NT);
-  const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64 * sc, DT);
+  const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128 * sc, NT, target);
+  const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128 * sc, NT, target);
+  const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64 * sc, DT, target);
   const int buf = imax(first.upc * first.unit, imax(mid.upc * mid.unit, att.upc * att.unit));
   return Plan{first, mid, att, buf};
 }

@@ -309,13 +309,11 @@ void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int ro
 
 }  // namespace
 
-void pack_model(const ModelRaw& m, int precision, Packed* out) {
+void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out) {
   const tabnet_config& c = m.cfg;
   const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
-  const int kprec = precision == TABNET_FP32 ? 0 : (precision == TABNET_BF16 ? 1 : 2);
   const bool fp8 = precision == TABNET_FP8_E4M3;
-  const Plan plan = make_plan(kprec, sh.DT, sh.NT, sh.KA0);
   *out = Packed();
   // input BN as a per-column affine map
   out->in_affine.assign(32 * sh.DT, 0.f);

@@ -59,6 +59,7 @@ struct Packed {
   std::vector<int64_t> ft_off;      // per unique feature-transformer layer
   std::vector<int64_t> att_off;     // per step
 };
-void pack_model(const ModelRaw& m, int precision, Packed* out);
+// Packs the model for `precision` in the chunk layout of `plan` (the kernel's plan).
+void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out);
 
 }  // namespace tabnet

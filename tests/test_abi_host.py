@@ -119,12 +119,15 @@ def test_packed_sizes(L):
     [value fragments][gate fragments][32 shifts], an attentive layer DT units of
     [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32) or per pair
     of K tiles (BF16, an odd last tile padded); every GEMM starts 256-byte aligned.
-    The chunk count is the number of weight-stream pieces of at most 40 KiB (balanced,
-    one unit if a unit is larger) over pass 0, then per step attentive + pass."""
+    The chunk count is the number of weight-stream pieces of at most T bytes (balanced,
+    one unit if a unit is larger) over pass 0, then per step attentive + pass, where T is
+    40 KiB or less: the two LDS buffers must fit beside the staging areas of the
+    workgroup's waves (8 waves of 16 rows for the Adult-shaped kernel, 4 for the others)
+    with 4 KiB to spare, in whole KiB."""
     def cdiv(a, b):
         return -(-a // b)
 
-    def chunks(unit, n, target=40960):
+    def chunks(unit, n, target):
         upc = cdiv(n, cdiv(unit * n, target))
         upc = min(upc, max(1, target // unit))
         return cdiv(n, upc)
@@ -134,6 +137,8 @@ def test_packed_sizes(L):
         p = synth.make_params(cfg, 1)
         raw = synth.to_bytes(p)
         DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
+        W = 8 if DT == 7 else 4
+        target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
         for prec in (0, 1, 2):
@@ -142,9 +147,10 @@ def test_packed_sizes(L):
             glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 * ex for k in set(ks)}
             att_unit = kb(NT - KA0) * 1024 + 64 * ex
             exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
-            first, mid = chunks(2 * kb(DT) * 1024 + 128 * ex, NT), chunks(2 * kb(NT) * 1024 + 128 * ex, NT)
+            first = chunks(2 * kb(DT) * 1024 + 128 * ex, NT, target)
+            mid = chunks(2 * kb(NT) * 1024 + 128 * ex, NT, target)
             nl = cfg.n_shared + cfg.n_indep
-            exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT)
+            exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT, target)
             wb, nch = ctypes.c_int64(), ctypes.c_int64()
             assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == 0
             assert wb.value == exp, (name, prec, wb.value, exp)
