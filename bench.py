@@ -179,31 +179,35 @@ def _ring_alloc(spans, head: int, need: int, size: int):
     return head if head + need <= tail else None      # wrapped: free run is [head, tail)
 
 
-def serve_bench(model, Xpool, rates, warm_s: float, dur_s: float, step_masks: bool = False):
-    """Open-loop Poisson load against the continuous-batching server (one model).
+def serve_bench(models, Xpools, rates, warm_s: float, dur_s: float, step_masks: bool = False,
+                max_rows: int = 4096, mix_seed=None):
+    """Open-loop Poisson load against the continuous-batching server.
 
-    Request sizes are log-uniform over 1..4096 rows; arrivals and sizes come from the
-    seeded request stream.  Latency is measured by the library from each request's
-    scheduled arrival to the completion of its copy-out, so a late submission counts
-    against the server (no coordinated omission)."""
+    Request sizes are log-uniform over 1..max_rows; arrivals and sizes come from the
+    seeded request stream.  With several models each request goes to one of them, drawn
+    uniformly from a seeded generator (mix_seed).  Latency is measured by the library
+    from each request's scheduled arrival to the completion of its copy-out, so a late
+    submission counts against the server (no coordinated omission)."""
     import collections
     import threading
 
     import numpy as np
     from paper_2510_19689_amd import synth, tabnet
 
-    cfg = model.config
-    per_row = cfg.n_out + cfg.D + (cfg.n_steps * cfg.D if step_masks else 0)
+    cfgs = [m.config for m in models]
+    per_row = [c.n_out + c.D + (c.n_steps * c.D if step_masks else 0) for c in cfgs]
     RING = 1 << 26                      # floats of output space in flight (256 MiB)
     out = []
     for lam in rates:
-        t_arr, rows = synth.request_stream(lam, warm_s + dur_s, seed=synth.REQUEST_SEED)
+        t_arr, rows = synth.request_stream(lam, warm_s + dur_s, seed=synth.REQUEST_SEED, max_rows=max_rows)
+        pick = (np.random.default_rng(mix_seed).integers(0, len(models), size=t_arr.size)
+                if len(models) > 1 else np.zeros(t_arr.size, np.int64))
         ring = np.empty(RING, np.float32)
         spans = collections.deque()      # (start, end, req_id) in submission order
         lock = threading.Condition()
         head = [0]
         done_sub = [False]
-        with tabnet.Server([model], max_rows_per_launch=65536, slots=3, with_step_masks=step_masks) as srv:
+        with tabnet.Server(models, max_rows_per_launch=65536, slots=3, with_step_masks=step_masks) as srv:
             def waiter():
                 while True:
                     with lock:
@@ -223,21 +227,24 @@ def serve_bench(model, Xpool, rates, warm_s: float, dur_s: float, step_masks: bo
             rows_meas = 0
             for i, (ta, r) in enumerate(zip(t_arr, rows)):
                 r = int(r)
+                mi = int(pick[i])
+                c = cfgs[mi]
                 if i == measured_from:
                     srv.reset_stats()
-                need = r * per_row
+                need = r * per_row[mi]
                 with lock:
                     while (base := _ring_alloc(spans, head[0], need, RING)) is None:
                         lock.wait()
-                lo = ring[base:base + r * cfg.n_out].reshape(r, cfg.n_out)
-                ag = ring[base + r * cfg.n_out:base + r * (cfg.n_out + cfg.D)].reshape(r, cfg.D)
-                ms = (ring[base + r * (cfg.n_out + cfg.D):base + need].reshape(cfg.n_steps, r, cfg.D)
+                lo = ring[base:base + r * c.n_out].reshape(r, c.n_out)
+                ag = ring[base + r * c.n_out:base + r * (c.n_out + c.D)].reshape(r, c.D)
+                ms = (ring[base + r * (c.n_out + c.D):base + need].reshape(c.n_steps, r, c.D)
                       if step_masks else None)
-                off = (i * 7919) % (Xpool.shape[0] - r)
+                pool = Xpools[mi]
+                off = (i * 7919) % (pool.shape[0] - r)
                 target = start + int(ta * 1e9)
                 while srv.now_ns() < target:
                     pass
-                rid = srv.submit(0, Xpool[off:off + r], lo, ag, ms, arrival_ns=target)
+                rid = srv.submit(mi, pool[off:off + r], lo, ag, ms, arrival_ns=target)
                 if i >= measured_from:
                     rows_meas += r
                 with lock:
@@ -253,9 +260,9 @@ def serve_bench(model, Xpool, rates, warm_s: float, dur_s: float, step_masks: bo
                     "rows_per_s": st["rows_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
                     "p999_ms": st["p999_us"] / 1e3, "mean_rows_per_launch": st["mean_rows_per_launch"],
                     "launches": int(st["launches"])})
-        print(f"[bench] serve {lam} req/s: p50 {st['p50_us']/1e3:.3f} ms p99 {st['p99_us']/1e3:.3f} ms "
-              f"{st['rows_per_s']/1e6:.2f} M rows/s, {st['mean_rows_per_launch']:.0f} rows/launch",
-              file=sys.stderr, flush=True)
+        print(f"[bench] serve{' mix' if len(models) > 1 else ''} {lam} req/s: p50 {st['p50_us']/1e3:.3f} ms "
+              f"p99 {st['p99_us']/1e3:.3f} ms {st['rows_per_s']/1e6:.2f} M rows/s, "
+              f"{st['mean_rows_per_launch']:.0f} rows/launch", file=sys.stderr, flush=True)
     return out
 
 
@@ -270,6 +277,9 @@ def main():
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
                     help="request rates (req/s) of the serving leg; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-mix-rates", default="2000,5000,10000",
+                    help="request rates of a mixed load over the three compiled model shapes "
+                         "(HR-, Adult- and wide-shaped models, requests of 1..8192 rows); empty to skip")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of TabNet, time a plain device-to-device copy of this many "
                          "bytes (the reference for scaling HBM byte counters)")
@@ -341,7 +351,26 @@ def main():
         if args.serve_rates:
             rates = [int(r) for r in args.serve_rates.split(",") if r]
             with tabnet.Model(path, "bf16") as m:
-                serving = serve_bench(m, Xh, rates, warm_s=0.5, dur_s=args.serve_seconds)
+                serving = serve_bench([m], [Xh], rates, warm_s=0.5, dur_s=args.serve_seconds)
+        serving_mix = None
+        if args.serve_mix_rates:
+            rates = [int(r) for r in args.serve_mix_rates.split(",") if r]
+            names = ["hr35", "adult108", "wide200"]
+            models, pools = [], []
+            for nm in names:
+                p_nm = os.path.join(d, f"{nm}.tnw")
+                synth.write_weights(synth.make_params(synth.WORKLOADS[nm]["cfg"], synth.WEIGHT_SEED[nm]), p_nm)
+                models.append(tabnet.Model(p_nm, "bf16"))
+                pools.append(synth.make_inputs(synth.WORKLOADS[nm]["data"], 20000, synth.DATA_SEED[nm]))
+            try:
+                serving_mix = {"models": names, "precision": "bf16", "masks": "logits + masks_agg",
+                               "request_rows": "log-uniform 1..8192", "model_choice": "uniform, seeded",
+                               "arrivals": "Poisson, open loop",
+                               "points": serve_bench(models, pools, rates, warm_s=0.5, dur_s=args.serve_seconds,
+                                                     max_rows=8192, mix_seed=4000)}
+            finally:
+                for m in models:
+                    m.close()
     t_bf16, wall_bf16 = res["bf16"]
     per_launch = t_bf16 / args.steps
     value = rows * args.steps / t_bf16
@@ -382,6 +411,7 @@ def main():
         out["raw_rows"] = {"what": "BF16 forward on raw rows: embedding gathered in the kernel, masks per raw column",
                            "columns": C, "rows_per_s": rows / t_raw, "us_per_forward": t_raw * 1e6,
                            "algorithmic_bytes_per_row": rb, "GB_s": rb * rows / t_raw / 1e9}
+    if "mask_stats" in res:
         t_ms = res["mask_stats"]
         gbs = rows * cfg.D * 4 / t_ms / 1e9
         out["mask_stats"] = {"what": "per-feature mean and variance of masks_agg", "rows": rows, "D": cfg.D,
@@ -390,6 +420,8 @@ def main():
         out["serving"] = {"model": name, "precision": "bf16", "masks": "logits + masks_agg",
                           "request_rows": "log-uniform 1..4096", "arrivals": "Poisson, open loop",
                           "points": serving}
+    if serving_mix is not None:
+        out["serving_mix"] = serving_mix
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, Xh)
     print(json.dumps(out), flush=True)
