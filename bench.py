@@ -93,6 +93,49 @@ def time_forward(model, X, outs, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def forward_detail(model, X, outs, n: int = 200, per_graph: int = 20):
+    """Per-launch spread and two variants of the same BF16 forward: p10/p50/p90 of the
+    interval between events recorded around each of n back-to-back launches; the time per
+    launch without step masks; and the time per launch when per_graph launches are
+    captured in one HIP graph and replayed (no per-launch host work)."""
+    import numpy as np
+    import torch
+    lo, ag, ms = outs
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record(stream)
+    for i in range(n):
+        model.forward_into(X, lo, ag, ms)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    dts = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(n)])
+    t_nomask, _ = time_forward(model, X, (lo, ag, None), n, 10)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        model.forward_into(X, lo, ag, ms)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(per_graph):
+            model.forward_into(X, lo, ag, ms)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, n // per_graph)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_graph = e0.elapsed_time(e1) / 1e3 / (reps * per_graph)
+    return {"p10_us": float(np.percentile(dts, 10)), "p50_us": float(np.percentile(dts, 50)),
+            "p90_us": float(np.percentile(dts, 90)), "no_step_masks_us": t_nomask / n * 1e6,
+            "graph_replay_us": t_graph * 1e6}
+
+
 def time_forward_raw(model, X_raw, outs, steps: int, warmup: int) -> float:
     """Seconds per tabnet_forward_raw launch (HIP events on the launch stream)."""
     import torch
@@ -328,6 +371,11 @@ def main():
                 print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
                       f"{rows * args.steps / t / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
                 if prec == "bf16":
+                    res["detail"] = forward_detail(m, X, outs)
+                    dd = res["detail"]
+                    print(f"[bench] bf16 per launch p10/p50/p90 {dd['p10_us']:.1f}/{dd['p50_us']:.1f}/"
+                          f"{dd['p90_us']:.1f} us; without step masks {dd['no_step_masks_us']:.1f} us; "
+                          f"graph replay {dd['graph_replay_us']:.1f} us", file=sys.stderr, flush=True)
                     t_ms = time_mask_stats(outs[1], args.steps, args.warmup)
                     res["mask_stats"] = t_ms
                     print(f"[bench] mask_stats of masks_agg: {t_ms * 1e6:.2f} us, "
@@ -405,6 +453,8 @@ def main():
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
     out["wall_s_bf16"] = wall_bf16
+    if "detail" in res:
+        out["bf16_forward_detail"] = res["detail"]
     if "raw" in res:
         t_raw, C = res["raw"]
         rb = 4 * (C + cfg.n_out + C + cfg.n_steps * C)

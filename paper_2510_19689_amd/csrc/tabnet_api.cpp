@@ -29,8 +29,10 @@ tabnet_status hip_fail(tabnet_handle* h, hipError_t e, const char* what) {
 void release(tabnet_handle* h) {
   if (h->d_emb_meta) (void)hipFree(h->d_emb_meta);
   if (h->d_emb_tables) (void)hipFree(h->d_emb_tables);
+  if (h->d_emb_colbits) (void)hipFree(h->d_emb_colbits);
   h->d_emb_meta = nullptr;
   h->d_emb_tables = nullptr;
+  h->d_emb_colbits = nullptr;
   if (h->d_wts) (void)hipFree(h->d_wts);
   if (h->d_chunks) (void)hipFree(h->d_chunks);
   if (h->d_affine) (void)hipFree(h->d_affine);
@@ -180,6 +182,20 @@ tabnet_status tabnet_set_embeddings(tabnet_handle* h, int32_t n_cols, const int3
     if (base > 0x7fffffffLL) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: tables too large");
   }
   if (at != D) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: the widths must add up to D");
+  // membership masks of the per-column mask reduction: for column tile ct and lane l
+  // (g = l / 16, r = l % 16), bit 4 t + i is set when feature 16 t + 4 g + i belongs to
+  // raw column 16 ct + r
+  const int DT = h->shape.DT;
+  if (DT > 16) return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: D above 256");
+  const int n_ct = (n_cols + 15) / 16;
+  std::vector<uint64_t> colbits((size_t)n_ct * 64, 0);
+  for (int ct = 0; ct < n_ct; ++ct)
+    for (int l = 0; l < 64; ++l)
+      for (int t = 0; t < DT; ++t)
+        for (int i = 0; i < 4; ++i) {
+          const int f = 16 * t + 4 * (l / 16) + i;
+          if (f < D && meta[4 * (size_t)f] == 16 * ct + l % 16) colbits[(size_t)ct * 64 + l] |= 1ull << (4 * t + i);
+        }
   if (base > 0 && !tables) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: NULL tables");
   const KernelEntry* k = find_kernel(h->precision, h->shape.DT, h->shape.NT, h->shape.KA0, true);
   if (!k) return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: no compiled raw-row kernel for this shape");
@@ -196,13 +212,16 @@ tabnet_status tabnet_set_embeddings(tabnet_handle* h, int32_t n_cols, const int3
     if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
     if (h->d_emb_meta) (void)hipFree(h->d_emb_meta);
     if (h->d_emb_tables) (void)hipFree(h->d_emb_tables);
+    if (h->d_emb_colbits) (void)hipFree(h->d_emb_colbits);
     h->d_emb_meta = nullptr;
     h->d_emb_tables = nullptr;
+    h->d_emb_colbits = nullptr;
     h->emb_C = 0;
   }
   std::vector<float> tab(tables ? tables : nullptr, tables ? tables + base : nullptr);
   if ((st = upload(h, meta, &h->d_emb_meta, "embedding map")) != TABNET_OK ||
-      (st = upload(h, tab, &h->d_emb_tables, "embedding tables")) != TABNET_OK)
+      (st = upload(h, tab, &h->d_emb_tables, "embedding tables")) != TABNET_OK ||
+      (st = upload(h, colbits, &h->d_emb_colbits, "column masks")) != TABNET_OK)
     return st;
   h->kernel_raw = k;
   h->emb_C = n_cols;
@@ -266,6 +285,7 @@ FwdArgs forward_args(const tabnet_handle* h, const float* X, int64_t B, const in
   a.C = 0;
   a.tab_len = 0;
   a.tab_lds = 0;
+  a.colbits = nullptr;
   return a;
 }
 
@@ -282,6 +302,7 @@ hipError_t enqueue_forward_raw(const tabnet_handle* h, const float* X_raw, int64
   a.C = h->emb_C;
   a.tab_len = h->emb_tab_len;
   a.tab_lds = h->emb_tab_lds ? 1 : 0;
+  a.colbits = h->d_emb_colbits;
   return launch_forward(h->kernel_raw, a, stream);
 }
 

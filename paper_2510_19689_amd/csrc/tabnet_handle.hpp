@@ -34,6 +34,7 @@ struct tabnet_handle {
   int* d_emb_meta = nullptr;
   float* d_emb_tables = nullptr;
   int emb_C = 0;
+  uint64_t* d_emb_colbits = nullptr;   // feature-to-column membership masks per lane
   int emb_tab_len = 0;           // floats in d_emb_tables
   bool emb_tab_lds = false;      // the tables fit in LDS beside everything else
 };

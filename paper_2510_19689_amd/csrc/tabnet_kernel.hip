@@ -329,51 +329,23 @@ __device__ __forceinline__ void stage_out(const float* st, float* dst, int n, in
   }
 }
 
-// Membership of the lane's features in raw column `col`: bit 4 t + i is set when model
-// feature 16 t + 4 g + i (g = lane / 16) belongs to it.  All reads of the map are issued
-// before any is compared.
-template <int DT>
-__device__ __forceinline__ uint64_t column_bits(const int4* fdesc, int D, int col, int g) {
-  int fc[DT][4];
-#pragma unroll
-  for (int t = 0; t < DT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fc[t][i] = fdesc[min(16 * t + 4 * g + i, D - 1)].x;
-  uint64_t b = 0;
-#pragma unroll
-  for (int t = 0; t < DT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (16 * t + 4 * g + i < D && fc[t][i] == col) b |= 1ull << (4 * t + i);
-  return b;
-}
-
 // Raw-column view of a mask held in the lane layout (lane = row rl, features 16 t + 4 g + i):
 // out[row][c] = sum of the row's mask over the features of raw column c, for all C
 // columns, as FP32 MFMA products with the 0/1 membership matrix S[c][f] = (column of f == c).
 // For 16 columns at a time the B operand of MFMA (t, i) is the lane's own value m[t][i]
 // (k slot g holds feature 16 t + 4 g + i of row rl) and the A operand is the membership
-// of that feature in column 16 ct + rl, taken from a bit mask (bits0 for the first 16
-// columns, kept for the whole kernel); the products are exact and the sums are FP32.
+// of that feature in column 16 ct + rl: bit 4 t + i of colbits[64 ct + lane], a table
+// the host builds with the embedding.  The products are exact and the sums are FP32.
 // The result lands as out[row rl][16 ct + 4 g + j] and is written to the wave's LDS
 // staging area as [16][C] rows, ready for stage_out.
 template <int DT>
-__device__ __forceinline__ void reduce_columns(const float (&m)[DT][4], uint64_t bits0, const int4* fdesc, int D,
-                                               int C, float* st, int lane) {
+__device__ __forceinline__ void reduce_columns(const float (&m)[DT][4], const uint64_t* colbits, int C, float* st,
+                                               int lane) {
+  static_assert(DT <= 16, "membership masks hold 64 features per lane");
   const int g = lane >> 4;
   const int rl = lane & 15;
   for (int ct = 0; 16 * ct < C; ++ct) {
-    uint64_t bits = bits0;
-    if (ct > 0) {
-      // columns past the first 16 (wide raw layouts only): one map read at a time, to keep
-      // registers free in the middle of a step
-      bits = 0;
-#pragma nounroll
-      for (int k = 0; k < 4 * DT; ++k) {
-        const int f = 16 * (k >> 2) + 4 * g + (k & 3);
-        if (f < D && fdesc[f].x == 16 * ct + rl) bits |= 1ull << k;
-      }
-    }
+    const uint64_t bits = colbits[64 * ct + lane];
     f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};   // two independent chains
 #pragma unroll
     for (int t = 0; t < DT; ++t)
@@ -465,10 +437,8 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   const int C = A.C;
   const int4* fdesc = reinterpret_cast<const int4*>(meta_s);
   float raw[RAW ? R : 1][RAW ? DT : 1][4];
-  uint64_t col_bits0 = 0;     // raw rows: membership of this lane's features in column rl
   if constexpr (RAW) {
     // every feature is gathered from LDS: the raw rows (staged above), the maps, the tables
-    col_bits0 = column_bits<DT>(fdesc, D, rl, g);
     const float* tab = A.tab_lds ? tab_s : A.emb_tables;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
@@ -671,7 +641,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     if (A.masks_step != nullptr) {
       if constexpr (RAW) {
 #pragma unroll
-        for (int rb = 0; rb < R; ++rb) reduce_columns<DT>(M[rb], col_bits0, fdesc, D, C, stage + 16 * rb * C, lane);
+        for (int rb = 0; rb < R; ++rb) reduce_columns<DT>(M[rb], A.colbits, C, stage + 16 * rb * C, lane);
         lds_wave_sync();
         stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * C, live_rows * C, lane);
       } else {
@@ -753,7 +723,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       for (int t = 0; t < DT; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) agg[rb][t][i] *= inv;
-      reduce_columns<DT>(agg[rb], col_bits0, fdesc, D, C, stage + 16 * rb * C, lane);
+      reduce_columns<DT>(agg[rb], A.colbits, C, stage + 16 * rb * C, lane);
     } else {
       float* sr = stage + (16 * rb + rl) * D + 4 * g;
 #pragma unroll

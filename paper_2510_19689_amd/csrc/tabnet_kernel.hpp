@@ -126,6 +126,7 @@ struct FwdArgs {
   int C;
   int tab_len;                // floats in emb_tables
   int tab_lds;                // 1: the kernel copies the tables into LDS
+  const uint64_t* colbits;    // [ceil(C/16)][64]: per lane, its features' membership in column 16 ct + lane % 16
 };
 
 }  // namespace tabnet

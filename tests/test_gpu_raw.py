@@ -161,3 +161,17 @@ def test_embedding_spec_errors_and_replacement(tmp_path):
         m.set_embeddings(cards, dims, tables)
         c = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
         np.testing.assert_array_equal(c[0], b[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_all_continuous_wide_layout_is_plain_forward(prec, tmp_path):
+    # 108 raw columns: seven column tiles of the per-column reduction
+    _say(f"case raw all-continuous 108 columns {prec}")
+    params, m = model("adult108", prec, tmp_path)
+    X = synth.make_inputs("adult", 777, synth.DATA_SEED["adult108"])
+    with m:
+        m.set_embeddings(np.zeros(108), np.ones(108), np.zeros(0))
+        a = to_np(*m.forward_raw(torch.from_numpy(X).cuda()))
+        b = to_np(*m.forward(torch.from_numpy(X).cuda()))
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
