@@ -738,6 +738,442 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 }
 
 // ------------------------------------------------------------------------------------
+// Split-feature kernel for wide models.  One workgroup of W waves carries one block of 16
+// rows; wave w owns feature tiles [w TPW, (w + 1) TPW) (x, the prior, the aggregate and
+// the mask of those features stay in its registers) and output tile pairs
+// [w OPW, (w + 1) OPW) of every feature-transformer layer.  The waves meet in LDS:
+//   u_s  the masked input u = M * x, in the B-operand layout of the first layer's GEMM
+//        (each wave writes its tiles, every wave reads all of them);
+//   h_s  the hidden state h of every layer (FP32), written by the owners of its tiles;
+//   ex   per-row partial sums of the sparsemax passes and the aggregate's denominator;
+//   st   per-row start bounds of the sparsemax.
+// A layer's weights stream as K slices that hold every output pair, so all waves work on
+// every chunk; the attentive weights stream as chunks holding TPC feature tiles of every
+// wave.  Everything a row computes is in a fixed order, independent of the batch.
+template <int PREC, int DT, int NT, int W>
+struct WideGeom {
+  static constexpr int TPW = wide_tpw(DT, W);     // feature tiles per wave
+  static constexpr int DTP = TPW * W;             // padded feature tiles
+  static constexpr int OPW = NT / W;              // output tile pairs per wave
+  static constexpr int UKB = PREC == 0 ? DTP : DTP / 2;   // k-blocks of u
+  static constexpr int UBYTES = UKB * kFrag;
+};
+
+// B operand of k-block kb.  The buffer holds [k-block][64 lanes][16 bytes] in the MFMA
+// operand format, or (SRC_F32 with BF16 GEMMs) FP32 tiles [tile][64 lanes][4 floats] that
+// are packed here, tile 2 kb and 2 kb + 1 (a tile at or past KT reads as zero).
+template <int PREC, bool SRC_F32>
+__device__ __forceinline__ void load_kblock(const unsigned char* src, int kb, int KT, int lane, f4& f, s8& b) {
+  if constexpr (PREC == 0) {
+    f = *reinterpret_cast<const f4*>(src + ((size_t)kb * 64 + lane) * 16);
+  } else if constexpr (SRC_F32) {
+    const f4 a = *reinterpret_cast<const f4*>(src + ((size_t)(2 * kb) * 64 + lane) * 16);
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+    if (2 * kb + 1 < KT) c = *reinterpret_cast<const f4*>(src + ((size_t)(2 * kb + 1) * 64 + lane) * 16);
+    uint32_t q[4] = {pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]), pack_bf16x2(c[0], c[1]),
+                     pack_bf16x2(c[2], c[3])};
+    b = __builtin_bit_cast(s8, q);
+  } else {
+    b = *reinterpret_cast<const s8*>(src + ((size_t)kb * 64 + lane) * 16);
+  }
+}
+
+// One GLU layer of the split-feature kernel.  src: B operands of the layer input, KT
+// tiles of K; h: this wave's OPW output tiles (updated in place after the first layer);
+// the new h is published to h_s for all waves.
+template <int PREC, int KT, int NT, int W, bool SRC_F32, class WS>
+__device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src, unsigned char* h_s, int sk,
+                                               float (&h)[NT / W][4], bool first, int lane, int wave) {
+  constexpr int OPW = NT / W;
+  constexpr int KB = kblocks(PREC, KT);
+  const int g = lane >> 4;
+  f4 av[OPW], ag[OPW];
+#pragma unroll
+  for (int p = 0; p < OPW; ++p) {
+    av[p] = f4{0.f, 0.f, 0.f, 0.f};
+    ag[p] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int kb0 = 0; kb0 < KB; kb0 += sk) {
+    const int nkb = KB - kb0 < sk ? KB - kb0 : sk;
+    ws.begin();
+    const unsigned char* buf = ws.ptr();
+    for (int q = 0; q < nkb; ++q) {
+      f4 bf = {0.f, 0.f, 0.f, 0.f};
+      s8 bb = {};
+      load_kblock<PREC, SRC_F32>(src, kb0 + q, KT, lane, bf, bb);
+#pragma unroll
+      for (int p = 0; p < OPW; ++p) {
+        const int pr = wave * OPW + p;
+        const unsigned char* fv = buf + ((size_t)(pr * 2 + 0) * nkb + q) * kFrag + lane * 16;
+        const unsigned char* fg = buf + ((size_t)(pr * 2 + 1) * nkb + q) * kFrag + lane * 16;
+        if constexpr (PREC == 0) {
+          const f4 a = *reinterpret_cast<const f4*>(fv);
+          const f4 c = *reinterpret_cast<const f4*>(fg);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            av[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], bf[r], av[p], 0, 0, 0);
+            ag[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(c[r], bf[r], ag[p], 0, 0, 0);
+          }
+        } else {
+          av[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const s8*>(fv), bb, av[p], 0, 0, 0);
+          ag[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const s8*>(fg), bb, ag[p], 0, 0, 0);
+        }
+      }
+    }
+    if (kb0 + nkb == KB) {
+      // shifts of every pair follow the fragments of the layer's last slice
+      const float* sft = reinterpret_cast<const float*>(buf + (size_t)NT * 2 * nkb * kFrag);
+#pragma unroll
+      for (int p = 0; p < OPW; ++p) {
+        const int pr = wave * OPW + p;
+        const f4 sv = *reinterpret_cast<const f4*>(sft + pr * 32 + 4 * g);
+        const f4 sg = *reinterpret_cast<const f4*>(sft + pr * 32 + 16 + 4 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float v = av[p][i] + sv[i];
+          const float sgm = sigmoid_fast(ag[p][i] + sg[i]);
+          h[p][i] = first ? v * sgm : __builtin_fmaf(v, sgm, h[p][i]) * kSqrtHalf;
+        }
+      }
+    }
+    ws.end();
+  }
+  // publish this wave's tiles of h (the chunk barrier above ended every read of h_s)
+#pragma unroll
+  for (int p = 0; p < OPW; ++p)
+    *reinterpret_cast<f4*>(h_s + ((size_t)(wave * OPW + p) * 64 + lane) * 16) = f4{h[p][0], h[p][1], h[p][2], h[p][3]};
+  lds_block_sync();
+}
+
+// u = M * x of this wave's tiles into the B-operand layout of u_s.
+template <int PREC, int TPW>
+__device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[TPW][4], const float (&x)[TPW][4],
+                                          int wave, int lane) {
+  if constexpr (PREC == 0) {
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+      *reinterpret_cast<f4*>(u_s + ((size_t)(wave * TPW + t) * 64 + lane) * 16) =
+          f4{m[t][0] * x[t][0], m[t][1] * x[t][1], m[t][2] * x[t][2], m[t][3] * x[t][3]};
+  } else {
+#pragma unroll
+    for (int t = 0; t < TPW; t += 2) {
+      uint32_t q[4] = {pack_bf16x2(m[t][0] * x[t][0], m[t][1] * x[t][1]),
+                       pack_bf16x2(m[t][2] * x[t][2], m[t][3] * x[t][3]),
+                       pack_bf16x2(m[t + 1][0] * x[t + 1][0], m[t + 1][1] * x[t + 1][1]),
+                       pack_bf16x2(m[t + 1][2] * x[t + 1][2], m[t + 1][3] * x[t + 1][3])};
+      *reinterpret_cast<uint4*>(u_s + ((size_t)((wave * TPW + t) / 2) * 64 + lane) * 16) =
+          uint4{q[0], q[1], q[2], q[3]};
+    }
+  }
+}
+
+template <int PREC, int DT, int NT, int KA0, int W>
+__global__ void __launch_bounds__(64 * W) tabnet_wide_kernel(FwdArgs A) {
+  using G = WideGeom<PREC, DT, NT, W>;
+  constexpr int TPW = G::TPW, OPW = G::OPW;
+  constexpr int KTA = NT - KA0;
+  constexpr int KBA = kblocks(PREC, KTA);
+  constexpr int KD = KA0 + 1 < NT ? KA0 + 1 : NT;   // tiles that can hold decision channels
+  constexpr Plan PL = make_wide_plan(PREC, DT, NT, KA0, W);
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
+  if ((int64_t)blockIdx.x * 16 >= B) return;       // every wave of the workgroup alike
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int rl = lane & 15;
+  const int D = A.D, n_d = A.n_d;
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  const int live_rows = (int)(B - row0 > 16 ? 16 : B - row0);
+  const bool live = rl < live_rows;
+  const int64_t row = row0 + rl;
+
+  unsigned char* u_s = smem + 2 * PL.buf;
+  unsigned char* h_s = u_s + G::UBYTES;
+  float* ex = reinterpret_cast<float*>(h_s + NT * kFrag);   // [2][W][16][2]
+  float* st = ex + 2 * W * 16 * 2;                           // [W][16][4]
+  float* wfin_s = st + W * 16 * 4;
+  for (int e = threadIdx.x; e < A.n_out * n_d; e += 64 * W) wfin_s[e] = A.wfin[e];
+
+  WeightStream<W, PL.buf> ws;
+  ws.lds = smem;
+  ws.wts = A.wts;
+  ws.tab = A.chunks;
+  ws.n = A.n_chunks;
+  ws.idx = -1;
+  ws.cur = 1;
+  ws.begin();
+
+  // ---- input batch norm of this wave's features ----
+  float x[TPW][4];
+  auto fok = [&](int t, int i) { return 16 * (wave * TPW + t) + 4 * g + i < D; };
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int T = wave * TPW + t;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = 0.f, sc = 0.f, sh = 0.f;
+      if (T < DT) {
+        sc = A.in_affine[16 * T + 4 * g + i];
+        sh = A.in_affine[16 * DT + 16 * T + 4 * g + i];
+        if (live && fok(t, i)) v = A.X[row * D + 16 * T + 4 * g + i];
+      }
+      x[t][i] = v * sc + sh;
+    }
+  }
+  float P[TPW][4], agg[TPW][4], M[TPW][4], h[OPW][4], acc[KD][4];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      P[t][i] = 1.f;
+      agg[t][i] = 0.f;
+      M[t][i] = 1.f;                 // pass 0 reads u = x
+    }
+#pragma unroll
+  for (int p = 0; p < OPW; ++p)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[p][i] = 0.f;
+#pragma unroll
+  for (int t = 0; t < KD; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[t][i] = 0.f;
+  publish_u<PREC, TPW>(u_s, M, x, wave, lane);
+  ws.end();                          // first chunk in LDS, u_s visible to every wave
+  const int L = A.n_sh + A.n_ind;
+  auto ft_pass = [&]() {
+    glu_layer_wide<PREC, DT, NT, W, false>(ws, u_s, h_s, PL.sk, h, true, lane, wave);
+    for (int l = 1; l < L; ++l) glu_layer_wide<PREC, NT, NT, W, true>(ws, h_s, h_s, PL.sk, h, false, lane, wave);
+  };
+  ft_pass();
+
+  const int64_t step_stride = B * (int64_t)D;
+  for (int s = 1; s <= A.n_steps; ++s) {
+    // ---- attentive transformer on this wave's feature tiles ----
+    {
+      f4 bf[PREC == 0 ? KTA : 1];
+      s8 bb[PREC == 0 ? 1 : KBA];
+      if constexpr (PREC == 0) {
+#pragma unroll
+        for (int t = 0; t < KTA; ++t) bf[t] = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + t) * 64 + lane) * 16);
+      } else {
+#pragma unroll
+        for (int kb = 0; kb < KBA; ++kb) {
+          const f4 a = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + 2 * kb) * 64 + lane) * 16);
+          f4 c = {0.f, 0.f, 0.f, 0.f};
+          if (2 * kb + 1 < KTA) c = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + 2 * kb + 1) * 64 + lane) * 16);
+          uint32_t q[4] = {pack_bf16x2(a[0], a[1]), pack_bf16x2(a[2], a[3]), pack_bf16x2(c[0], c[1]),
+                           pack_bf16x2(c[2], c[3])};
+          if (2 * kb + 1 >= KTA) q[2] = q[3] = 0u;
+          bb[kb] = __builtin_bit_cast(s8, q);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < TPW / PL.tpc; ++j) {
+        ws.begin();
+        const unsigned char* buf = ws.ptr();
+#pragma unroll
+        for (int q = 0; q < PL.tpc; ++q) {
+          const int t = j * PL.tpc + q;      // compile-time after unrolling
+          const unsigned char* unit = buf + (size_t)(wave * PL.tpc + q) * PL.att_unit;
+          f4 z = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
+          if constexpr (PREC == 0) {
+#pragma unroll
+            for (int kt = 0; kt < KTA; ++kt) {
+              const f4 a = *reinterpret_cast<const f4*>(unit + kt * kFrag + lane * 16);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) z = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], bf[kt][r], z, 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int kb = 0; kb < KBA; ++kb)
+              z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const s8*>(unit + kb * kFrag + lane * 16),
+                                                         bb[kb], z, 0, 0, 0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) M[t][i] = fok(t, i) ? P[t][i] * z[i] : kNegBig;
+        }
+        ws.end();
+      }
+    }
+    // ---- sparsemax over the row, whose features are spread over the W waves ----
+    {
+      float a1 = kNegBig, a2 = kNegBig, b1 = kNegBig, b2 = kNegBig;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float w = M[t][i];
+          if (i & 1) {
+            b2 = __builtin_amdgcn_fmed3f(b1, b2, w);
+            b1 = fmaxf(b1, w);
+          } else {
+            a2 = __builtin_amdgcn_fmed3f(a1, a2, w);
+            a1 = fmaxf(a1, w);
+          }
+        }
+      float v[8];
+      top8_sorted(fmaxf(a1, b1), fmaxf(fminf(a1, b1), fmaxf(a2, b2)), v);
+      // best prefix bound of this wave's candidates (a lower bound of the row's threshold)
+      float c = 0.f, best = v[0] - 1.f, vl = v[0];
+      int kb = 1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        c += v[k];
+        const float bnd = (c - 1.f) * (1.0f / (float)(k + 1));
+        if (bnd > best) {
+          best = bnd;
+          kb = k + 1;
+          vl = v[k];
+        }
+      }
+      if (g == 0) {
+        st[(wave * 16 + rl) * 4 + 0] = best;
+        st[(wave * 16 + rl) * 4 + 1] = (float)kb;
+        st[(wave * 16 + rl) * 4 + 2] = vl;
+      }
+      lds_block_sync();
+      float tau = st[rl * 4 + 0];
+      int kbest = (int)st[rl * 4 + 1];
+      float vlast = st[rl * 4 + 2];
+      for (int w = 1; w < W; ++w) {
+        const float b = st[(w * 16 + rl) * 4 + 0];
+        if (b > tau) {
+          tau = b;
+          kbest = (int)st[(w * 16 + rl) * 4 + 1];
+          vlast = st[(w * 16 + rl) * 4 + 2];
+        }
+      }
+      int kprev = 0x7fffffff;
+      bool done = false;
+      for (int it = 0; it <= 16 * G::DTP + 1; ++it) {
+        float sp[4] = {0.f, 0.f, 0.f, 0.f};
+        int kp[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const bool in = M[t][i] > tau;
+            sp[i] += in ? M[t][i] : 0.f;
+            kp[i] += in ? 1 : 0;
+          }
+        const float smw = row_sum((sp[0] + sp[1]) + (sp[2] + sp[3]));
+        const int kw = row_sum((kp[0] + kp[1]) + (kp[2] + kp[3]));
+        float* e = ex + (size_t)(it & 1) * W * 16 * 2;
+        if (g == 0) {
+          e[(wave * 16 + rl) * 2 + 0] = smw;
+          e[(wave * 16 + rl) * 2 + 1] = (float)kw;
+        }
+        lds_block_sync();
+        float sm = 0.f;
+        int k = 0;
+        for (int w = 0; w < W; ++w) {
+          sm += e[(w * 16 + rl) * 2 + 0];
+          k += (int)e[(w * 16 + rl) * 2 + 1];
+        }
+        if (!done) {
+          if (k >= kprev) {
+            done = true;
+          } else {
+            tau = (sm - 1.f) / (float)k;
+            kprev = k;
+            if (it == 0 && k == kbest && vlast > tau) done = true;
+          }
+        }
+        if (!__any(!done)) break;
+      }
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) M[t][i] = fmaxf(M[t][i] - tau, 0.f);
+    }
+    // ---- step mask out: each lane writes its 4 consecutive features of each tile ----
+    if (A.masks_step != nullptr && live) {
+      float* dst = A.masks_step + (int64_t)(s - 1) * step_stride + row * D;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int f0 = 16 * (wave * TPW + t) + 4 * g;
+        if (f0 + 3 < D && (D & 3) == 0) {
+          __builtin_nontemporal_store(f4{M[t][0], M[t][1], M[t][2], M[t][3]}, reinterpret_cast<f4*>(dst + f0));
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (f0 + i < D) __builtin_nontemporal_store(M[t][i], dst + f0 + i);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) P[t][i] *= A.gamma - M[t][i];
+    publish_u<PREC, TPW>(u_s, M, x, wave, lane);
+    lds_block_sync();
+    ft_pass();
+    // ---- decision aggregation: every wave reads the decision half of h from h_s ----
+    float ep[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < KD; ++t) {
+      const f4 hv = *reinterpret_cast<const f4*>(h_s + ((size_t)t * 64 + lane) * 16);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float r = 16 * t + 4 * g + i < n_d ? fmaxf(hv[i], 0.f) : 0.f;
+        acc[t][i] += r;
+        ep[i] += r;
+      }
+    }
+    const float eta = row_sum((ep[0] + ep[1]) + (ep[2] + ep[3]));
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) agg[t][i] += eta * M[t][i];
+  }
+
+  // ---- outputs ----
+  if (wave == 0) {
+    for (int o = 0; o < A.n_out; ++o) {
+      const float* wf = wfin_s + o * n_d;
+      float part = 0.f;
+#pragma unroll
+      for (int t = 0; t < KD; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 16 * t + 4 * g + i;
+          if (c < n_d) part += acc[t][i] * wf[c];
+        }
+      part = row_sum(part);
+      if (live && g == (o & 3)) A.logits[row * A.n_out + o] = part;
+    }
+  }
+  float dp = 0.f;
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dp += agg[t][i];
+  dp = row_sum(dp);
+  if (g == 0) ex[wave * 16 + rl] = dp;
+  lds_block_sync();
+  float den = 0.f;
+  for (int w = 0; w < W; ++w) den += ex[w * 16 + rl];
+  const float inv = den > 0.f ? 1.0f / den : 0.f;
+  if (live) {
+    float* dst = A.masks_agg + row * D;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int f0 = 16 * (wave * TPW + t) + 4 * g;
+      if (f0 + 3 < D && (D & 3) == 0) {
+        __builtin_nontemporal_store(f4{agg[t][0] * inv, agg[t][1] * inv, agg[t][2] * inv, agg[t][3] * inv},
+                                    reinterpret_cast<f4*>(dst + f0));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (f0 + i < D) __builtin_nontemporal_store(agg[t][i] * inv, dst + f0 + i);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // Compiled shapes.  (DT, NT, KA0) = (ceil(D/16), ceil((n_d+n_a)/16), floor(n_d/16)); R is
 // the number of 16-row blocks per wavefront and W the wavefronts per workgroup, both
 // fixed per shape so that a row's arithmetic never depends on the batch size.
@@ -745,7 +1181,7 @@ struct KernelEntry {
   int prec, DT, NT, KA0, R, W;
   bool raw;                  // embeds raw rows and writes masks per raw column
   void (*fn)(FwdArgs);
-  Plan plan;
+  Plan plan;                 // plan.wide: split-feature kernel, 16 rows per workgroup
 };
 
 #ifndef TABNET_ADULT_R
@@ -762,6 +1198,9 @@ struct KernelEntry {
    make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},                                                   \
       {P, DT, NT, KA0, R, W, true, tabnet_forward_kernel<P, DT, NT, KA0, R, W, true>,                    \
        make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},
+// Split-feature kernels for models too wide for the register-resident layout.
+#define TABNET_WIDE_SHAPE(P, DT, NT, KA0, W) \
+  {P, DT, NT, KA0, 1, W, false, tabnet_wide_kernel<P, DT, NT, KA0, W>, make_wide_plan(P, DT, NT, KA0, W)},
 #define TABNET_SHAPES(P)          \
   TABNET_SHAPE(P, 1, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 2, 1, 0, 1, 4)  \
@@ -771,7 +1210,8 @@ struct KernelEntry {
   TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
   TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
-static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)};
+static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)
+                                       TABNET_WIDE_SHAPE(0, 32, 8, 4, 4) TABNET_WIDE_SHAPE(1, 32, 8, 4, 4)};
 
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
   for (const auto& e : kKernels)
@@ -784,6 +1224,13 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
 // aligned) and the tables when they are staged.
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len) {
   (void)C;
+  if (k->plan.wide) {
+    // weight buffers, u (B-operand layout), h (FP32), sparsemax exchange and start areas,
+    // the final map
+    const int dtp = wide_tpw(k->DT, k->W) * k->W;
+    const size_t ub = (size_t)(k->prec == 0 ? dtp : dtp / 2) * kFrag;
+    return 2 * (size_t)k->plan.buf + ub + (size_t)k->NT * kFrag + ((size_t)k->W * 16 * 8 + (size_t)n_out * n_d) * 4;
+  }
   const size_t wf = k->raw ? ((size_t)n_out * n_d + 3) / 4 * 4 : (size_t)n_out * n_d;
   return 2 * (size_t)k->plan.buf + ((size_t)k->W * 16 * k->R * D + wf) * sizeof(float) +
          (k->raw ? 4 * (size_t)D * sizeof(int) + (size_t)tab_lds_len * sizeof(float) : 0);
@@ -797,7 +1244,7 @@ hipError_t prepare_kernel(const KernelEntry* k) {
 }
 
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream) {
-  const int64_t rows_per_block = 16LL * k->R * k->W;
+  const int64_t rows_per_block = k->plan.wide ? 16 : 16LL * k->R * k->W;
   const int64_t blocks = (a.B + rows_per_block - 1) / rows_per_block;
   hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W),
                      kernel_lds_bytes(k, a.D, a.n_out, a.n_d, a.C, a.tab_lds ? a.tab_len : 0), stream, a);

@@ -90,6 +90,14 @@ constexpr int chunk_target(int DT, int R, int W) {
 struct Plan {
   GemmPlan first, mid, att;
   int buf;       // bytes of one LDS weight buffer
+  // Split-feature kernels (wide models): the features of one 16-row block are shared out
+  // over the W waves of a workgroup.  A feature-transformer layer streams K slices of sk
+  // k-blocks; a slice chunk holds, for every output tile pair, [value fragments][gate
+  // fragments] of those k-blocks, and the layer's last slice adds the shifts of all pairs
+  // ([pair][16 value | 16 gate] floats).  An attentive chunk holds, for every wave, tpc of
+  // its feature tiles as [fragments][16 shifts] units of att_unit bytes.
+  int wide = 0;
+  int W = 0, tpw = 0, sk = 0, tpc = 0, att_unit = 0;
 };
 
 constexpr int imax(int a, int b) { return a > b ? a : b; }
@@ -104,6 +112,35 @@ constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64 * sc, DT, target);
   const int buf = imax(first.upc * first.unit, imax(mid.upc * mid.unit, att.upc * att.unit));
   return Plan{first, mid, att, buf};
+}
+
+// Split-feature plan: wave w owns feature tiles [w tpw, (w + 1) tpw) of the padded row
+// (tpw even, so that BF16 tile pairs never straddle waves) and output tile pairs
+// [w NT / W, (w + 1) NT / W) of every feature-transformer layer.
+constexpr int wide_tpw(int DT, int W) { return (cdiv(DT, W) + 1) / 2 * 2; }
+constexpr int wide_slice_bytes(int prec, int NT, int nkb, bool last) {
+  return NT * 2 * nkb * kFrag + (last ? NT * 128 : 0);
+}
+constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
+  Plan p{};
+  p.wide = 1;
+  p.W = W;
+  p.tpw = wide_tpw(DT, W);
+  p.sk = NT >= 8 ? 1 : 8 / NT;                  // slice chunks of at most 16 KiB + shifts
+  p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64;
+  int tpc = p.tpw;
+  while (tpc > 1 && (W * tpc * p.att_unit > 16384 || p.tpw % tpc != 0)) --tpc;
+  p.tpc = tpc;
+  const int kbf = kblocks(prec, DT), kbm = kblocks(prec, NT);
+  int buf = W * tpc * p.att_unit;
+  buf = imax(buf, wide_slice_bytes(prec, NT, kbf < p.sk ? kbf : p.sk, true));
+  buf = imax(buf, wide_slice_bytes(prec, NT, kbm < p.sk ? kbm : p.sk, true));
+  p.buf = buf;
+  // GemmPlan fields describe the chunk counts per GEMM (units are not used)
+  p.first = GemmPlan{0, 0, 0, cdiv(kbf, p.sk)};
+  p.mid = GemmPlan{0, 0, 0, cdiv(kbm, p.sk)};
+  p.att = GemmPlan{0, 0, 0, p.tpw / tpc};
+  return p;
 }
 
 struct FwdArgs {

@@ -248,9 +248,11 @@ void emit(std::vector<unsigned char>* out, const void* p, size_t n) {
 // One A-operand fragment group: output tile rows row_of(i) (i = 0..15, -1 = zero row) of
 // the folded weights Wf [rows][cols], K over KT tiles with col_of(kin) mapping the
 // kernel's K index 16 t + 4 q + j to a column of Wf (-1 = zero).
+// Only k-blocks [kb_lo, kb_hi) are emitted (a k-block is one K tile in FP32, a pair of
+// K tiles in BF16); kb_hi < 0 means all of them.
 template <class RowOf, class ColOf>
 void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precision, RowOf row_of,
-                    ColOf col_of, std::vector<unsigned char>* wts) {
+                    ColOf col_of, std::vector<unsigned char>* wts, int kb_lo = 0, int kb_hi = -1) {
   auto wv = [&](int i, int kin) -> double {
     const int r = row_of(i);
     const int c = (kin < 16 * KT) ? col_of(kin) : -1;
@@ -258,7 +260,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
     return Wf[(size_t)r * cols + c];
   };
   if (precision == TABNET_FP32) {
-    for (int kt = 0; kt < KT; ++kt)
+    for (int kt = kb_lo; kt < (kb_hi < 0 ? KT : kb_hi); ++kt)
       for (int lane = 0; lane < 64; ++lane) {
         const int i = lane & 15, q = lane >> 4;
         float v[4];
@@ -267,7 +269,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
       }
   } else {
     const int KP = (KT + 1) / 2;   // an odd last tile is paired with a zero tile
-    for (int kb = 0; kb < KP; ++kb)
+    for (int kb = kb_lo; kb < (kb_hi < 0 ? KP : kb_hi); ++kb)
       for (int lane = 0; lane < 64; ++lane) {
         const int i = lane & 15, q = lane >> 4;
         uint16_t v[8];
@@ -307,6 +309,78 @@ void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int ro
   }
 }
 
+// Split-feature layout (see Plan): feature-transformer layers as K slices holding every
+// output pair, attentive layers as chunks holding tpc feature tiles of every wave.
+void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::vector<const LayerRaw*>& ft,
+               Packed* out) {
+  const tabnet_config& c = m.cfg;
+  const Shape sh = shape_of(c);
+  const int N = c.n_d + c.n_a;
+  std::vector<double> Wf, bf;
+  auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
+  const int kbn = precision == TABNET_FP32 ? 1 : 2;   // K tiles per k-block
+  std::vector<std::vector<ChunkRec>> ft_chunks, att_chunks;
+  for (const LayerRaw* L : ft) {
+    fold_layer(*L, c.bn_eps, &Wf, &bf);
+    const int KT = (L->cols + 15) / 16;
+    const int K = L->cols;
+    const int KB = (KT + kbn - 1) / kbn;
+    align();
+    out->ft_off.push_back((int64_t)out->wts.size());
+    std::vector<ChunkRec> chunks;
+    for (int kb0 = 0; kb0 < KB; kb0 += plan.sk) {
+      const int kb1 = std::min(KB, kb0 + plan.sk);
+      const int64_t at = (int64_t)out->wts.size();
+      for (int pr = 0; pr < sh.NT; ++pr)
+        for (int half = 0; half < 2; ++half)
+          emit_fragments(
+              Wf, L->cols, KT, precision,
+              [&](int i) { const int ch = 16 * pr + i; return ch < N ? half * N + ch : -1; },
+              [&](int kin) { return kin < K ? kin : -1; }, &out->wts, kb0, kb1);
+      if (kb1 == KB)
+        for (int pr = 0; pr < sh.NT; ++pr) {
+          const int nv = std::min(16, N - 16 * pr);
+          emit_vals(bf, nv, 16 * pr, 0.f, &out->wts);
+          emit_vals(bf, nv, N + 16 * pr, 0.f, &out->wts);
+        }
+      chunks.push_back(ChunkRec{at, (int32_t)((int64_t)out->wts.size() - at), 0});
+    }
+    ft_chunks.push_back(chunks);
+  }
+  const int KTA = sh.NT - sh.KA0;
+  for (const auto& L : m.att) {
+    fold_layer(L, c.bn_eps, &Wf, &bf);
+    align();
+    out->att_off.push_back((int64_t)out->wts.size());
+    std::vector<ChunkRec> chunks;
+    for (int j = 0; j < plan.tpw / plan.tpc; ++j) {
+      const int64_t at = (int64_t)out->wts.size();
+      for (int w = 0; w < plan.W; ++w)
+        for (int q = 0; q < plan.tpc; ++q) {
+          const int mt = w * plan.tpw + j * plan.tpc + q;   // feature tile (past DT: zeros)
+          emit_fragments(
+              Wf, L.cols, KTA, precision,
+              [&](int i) { const int d = 16 * mt + i; return d < c.D ? d : -1; },
+              [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
+              &out->wts);
+          emit_vals(bf, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 0.f, &out->wts);
+        }
+      chunks.push_back(ChunkRec{at, (int32_t)((int64_t)out->wts.size() - at), 0});
+    }
+    att_chunks.push_back(chunks);
+  }
+  align();
+  out->wfin.assign(m.w_fin, m.w_fin + (size_t)c.n_out * c.n_d);
+  const int L = c.n_shared + c.n_indep;
+  auto lid = [&](int s, int l) { return l < c.n_shared ? l : c.n_shared + s * c.n_indep + (l - c.n_shared); };
+  for (int s = 0; s <= c.n_steps; ++s) {
+    if (s > 0)
+      for (const ChunkRec& r : att_chunks[s - 1]) out->chunks.push_back(r);
+    for (int l = 0; l < L; ++l)
+      for (const ChunkRec& r : ft_chunks[lid(s, l)]) out->chunks.push_back(r);
+  }
+}
+
 }  // namespace
 
 void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out) {
@@ -328,6 +402,10 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
     for (const auto& L : pass) ft.push_back(&L);
   std::vector<double> Wf, bf, sc;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
+  if (plan.wide) {
+    pack_wide(m, precision, plan, ft, out);
+    return;
+  }
   // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);

@@ -73,10 +73,14 @@ WORKLOADS: Dict[str, dict] = {
     # Scale-up: 200 continuous N(0,1), 20 columns zeroed with probability 0.3.
     "wide200": dict(cfg=TabNetConfig(D=200, n_d=64, n_a=64, n_steps=7, n_shared=4, n_indep=2,
                                       n_out=3, gamma=1.3), rows=1048576, data="wide"),
+    # The widest resident model of the multi-model serving mix: 512 continuous N(0,1)
+    # features, 10 steps (n_shared = n_indep = 2 and 2 outputs are readings).
+    "wide512": dict(cfg=TabNetConfig(D=512, n_d=64, n_a=64, n_steps=10, n_shared=2, n_indep=2,
+                                      n_out=2, gamma=1.3), rows=65536, data="wide512"),
 }
-# Seeds: weights 1000 + k, data 2000 + k, request stream 3000 (k = 1, 2, 3 in the order above).
-WEIGHT_SEED = {"hr35": 1001, "adult108": 1002, "wide200": 1003}
-DATA_SEED = {"hr35": 2001, "adult108": 2002, "wide200": 2003}
+# Seeds: weights 1000 + k, data 2000 + k, request stream 3000 (k = 1, 2, 3, 5 in the order above).
+WEIGHT_SEED = {"hr35": 1001, "adult108": 1002, "wide200": 1003, "wide512": 1005}
+DATA_SEED = {"hr35": 2001, "adult108": 2002, "wide200": 2003, "wide512": 2005}
 REQUEST_SEED = 3000
 
 ADULT_EMBED_DIMS = (16, 16, 14, 14, 12, 10, 10, 10)
@@ -284,6 +288,8 @@ def make_inputs(kind: str, rows: int, seed: int) -> np.ndarray:
         sub[zero] = 0.0
         X[:, cols] = sub
         return X
+    if kind == "wide512":
+        return rng.standard_normal((rows, 512), dtype=np.float32)
     if kind == "normal":
         raise ValueError("use make_normal_inputs for plain Gaussian inputs")
     raise ValueError(f"unknown input family {kind!r}")

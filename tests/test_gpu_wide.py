@@ -1,0 +1,116 @@
+"""GPU parity of the split-feature kernel (models too wide for the register-resident
+layout: D = 512, 10 steps) with the FP64 oracle.
+
+Gates.  FP32: logits 1e-4 relative (as for the other wide models) and masks 1e-5 scaled
+by max(1, gamma^(S-1) / 2), the growth of the prior over the steps.  BF16: logits 2e-2
+and argmax 99.9 % against FP64; against an FP64 forward on the same bf16-rounded operands
+(the oracle's rounding option) logits 1e-3 and per-row mask L1 5e-3."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import tabnet as oracle  # noqa: E402
+from paper_2510_19689_amd import synth, tabnet as tb  # noqa: E402
+from paper_2510_19689_amd.synth import TabNetConfig  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+
+
+def load(cfg, seed, prec, tmp_path, tag="m"):
+    params = synth.make_params(cfg, seed)
+    path = str(tmp_path / f"{tag}.tnw")
+    synth.write_weights(params, path)
+    return params, tb.Model(path, prec)
+
+
+def run(m, X, with_steps=True):
+    lo, ag, ms = m.forward(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda(), with_steps)
+    torch.cuda.synchronize()
+    return lo.cpu().numpy(), ag.cpu().numpy(), None if ms is None else ms.cpu().numpy()
+
+
+WIDE = synth.WORKLOADS["wide512"]["cfg"]
+VARIANTS = {
+    "wide512": WIDE,
+    "D500_nout3": TabNetConfig(D=500, n_d=64, n_a=64, n_steps=4, n_shared=2, n_indep=2, n_out=3, gamma=1.5),
+    "D497_nd72": TabNetConfig(D=497, n_d=72, n_a=56, n_steps=3, n_shared=1, n_indep=3, n_out=2, gamma=1.2),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+@pytest.mark.parametrize("B", [1, 15, 17, 100])
+def test_fp32_matches_oracle(name, B, tmp_path):
+    cfg = VARIANTS[name]
+    _say(f"case wide fp32 {name} B={B}")
+    params, m = load(cfg, 1005, "fp32", tmp_path)
+    X = synth.make_normal_inputs(B, cfg.D, 2005 + B)
+    with m:
+        lo, ag, ms = run(m, X)
+    rlo, rag, rms = oracle.forward(params, X)
+    rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+    mt = 1e-5 * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)
+    _say(name, B, "logit_rel", rel, "agg", np.abs(ag - rag).max(), "step", np.abs(ms - rms).max())
+    assert rel <= 1e-4
+    assert np.abs(ag - rag).max() <= mt and np.abs(ms - rms).max() <= mt
+
+
+@pytest.mark.parametrize("B", [33, 300])
+def test_bf16_matches_oracle(B, tmp_path):
+    _say(f"case wide bf16 B={B}")
+    params, m = load(WIDE, 1005, "bf16", tmp_path)
+    X = synth.make_inputs("wide512", B, 2005)
+    with m:
+        lo, ag, ms = run(m, X)
+    rlo, rag, rms = oracle.forward(params, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="bf16", acts="bf16")
+    _say("bf16 vs fp64: logits", np.abs(lo - rlo).max(), "agg L1", np.abs(ag - rag).sum(-1).max(),
+         "step L1", np.abs(ms - rms).sum(-1).max())
+    _say("bf16 vs rounded fp64: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
+         "step L1", np.abs(ms - qms).sum(-1).max())
+    assert np.abs(lo - rlo).max() <= 2e-2
+    assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.999
+    assert np.abs(lo - qlo).max() <= 1e-3
+    assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_rows_independent_optional_masks_empty(prec, tmp_path):
+    _say(f"case wide rows independent {prec}")
+    params, m = load(WIDE, 1005, prec, tmp_path)
+    X = synth.make_inputs("wide512", 200, 2005)
+    with m:
+        full = run(m, X)
+        sub = run(m, X[37:121])
+        again = run(m, X)
+        nomask = run(m, X, with_steps=False)
+        empty = m.forward(torch.zeros((0, 512), dtype=torch.float32, device="cuda"))
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(sub[0], full[0][37:121])
+    np.testing.assert_array_equal(sub[1], full[1][37:121])
+    np.testing.assert_array_equal(sub[2], full[2][:, 37:121])
+    for u, v in zip(full, again):
+        np.testing.assert_array_equal(u, v)
+    np.testing.assert_array_equal(nomask[0], full[0])
+    np.testing.assert_array_equal(nomask[1], full[1])
+    assert nomask[2] is None and empty[0].shape == (0, 2)
+
+
+def test_fp8_wide_is_refused(tmp_path):
+    path = str(tmp_path / "w.tnw")
+    synth.write_weights(synth.make_params(WIDE, 1005), path)
+    with pytest.raises(tb.TabNetError) as e:
+        tb.Model(path, "fp8")
+    assert e.value.status == tb.E_UNSUPPORTED
