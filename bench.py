@@ -321,8 +321,8 @@ def main():
                     help="request rates (req/s) of the serving leg; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-mix-rates", default="2000,5000,10000",
-                    help="request rates of a mixed load over the three compiled model shapes "
-                         "(HR-, Adult- and wide-shaped models, requests of 1..8192 rows); empty to skip")
+                    help="request rates of a mixed load over four resident models (HR-, Adult-, "
+                         "200- and 512-feature models, requests of 1..8192 rows); empty to skip")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of TabNet, time a plain device-to-device copy of this many "
                          "bytes (the reference for scaling HBM byte counters)")
@@ -403,7 +403,7 @@ def main():
         serving_mix = None
         if args.serve_mix_rates:
             rates = [int(r) for r in args.serve_mix_rates.split(",") if r]
-            names = ["hr35", "adult108", "wide200"]
+            names = ["hr35", "adult108", "wide200", "wide512"]
             models, pools = [], []
             for nm in names:
                 p_nm = os.path.join(d, f"{nm}.tnw")

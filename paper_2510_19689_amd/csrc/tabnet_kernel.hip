@@ -867,8 +867,9 @@ __device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[T
   }
 }
 
+// Two waves per SIMD (two workgroups per CU): the register budget is 256 per lane in all.
 template <int PREC, int DT, int NT, int KA0, int W>
-__global__ void __launch_bounds__(64 * W) tabnet_wide_kernel(FwdArgs A) {
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) tabnet_wide_kernel(FwdArgs A) {
   using G = WideGeom<PREC, DT, NT, W>;
   constexpr int TPW = G::TPW, OPW = G::OPW;
   constexpr int KTA = NT - KA0;

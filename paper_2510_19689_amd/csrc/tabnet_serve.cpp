@@ -5,9 +5,10 @@
 //
 //   submit (any thread)  ->  pending queue (FIFO)
 //   scheduler thread     ->  admits pending requests in order while their bytes fit the
-//                            budget; packs admitted rows (a request may be split) into a
-//                            free slot's pinned input buffer; the executor enqueues
-//                            copy-in, the forward and copy-out on the slot's stream
+//                            budget; packs the admitted rows of the oldest request's model
+//                            (a request may be split) into a free slot's pinned input
+//                            buffer; the executor enqueues copy-in, the forward and
+//                            copy-out on the slot's stream
 //   completion thread    ->  takes slots in launch order, waits for their copy-out,
 //                            copies each slice to its request's buffers, completes
 //                            requests, returns bytes to the budget and the slot to the pool
@@ -120,18 +121,28 @@ struct ServerImpl {
         cv_sched.wait(lk);
         continue;
       }
+      // The launch serves the model of the oldest admitted request and takes, in arrival
+      // order, the rows of every admitted request of that model until it is full, so that
+      // a mixed stream still forms large per-model batches.
       Launch L;
       L.slot = free_slots.back();
       free_slots.pop_back();
       L.model = admitted.front()->model;
       L.rows = 0;
-      while (!admitted.empty() && L.rows < max_rows && admitted.front()->model == L.model) {
-        auto r = admitted.front();
+      for (auto it = admitted.begin(); it != admitted.end() && L.rows < max_rows;) {
+        auto r = *it;
+        if (r->model != L.model) {
+          ++it;
+          continue;
+        }
         const int64_t take = std::min(r->rows - r->rows_launched, max_rows - L.rows);
         L.segs.push_back(Segment{r, r->rows_launched, take, L.rows});
         r->rows_launched += take;
         L.rows += take;
-        if (r->rows_launched == r->rows) admitted.pop_front();
+        if (r->rows_launched == r->rows)
+          it = admitted.erase(it);
+        else
+          ++it;
       }
       lk.unlock();
       // gather the rows into the slot's input buffer and enqueue the launch

@@ -212,3 +212,22 @@ def test_mask_stats_errors():
         assert tb.lib().tabnet_serve_mask_stats(s._s, 0, None, buf.ctypes.data, None) == tb.E_INVALID
     with pytest.raises(tb.TabNetError):
         tb.Server(fake_configs=[c], mask_stats_window=-1)
+
+
+def test_mixed_models_batch_per_model():
+    # while the only slot is busy, alternating requests of two models queue up; later
+    # launches gather all queued requests of one model instead of one request each
+    cs = [cfg(D=5, n_out=2, S=1), cfg(D=9, n_out=3, S=1)]
+    rng = np.random.default_rng(8)
+    with tb.Server(fake_configs=cs, slots=1, max_rows_per_launch=4096, fake_delay_us=100000) as s:
+        work = []
+        for k in range(20):
+            m = k % 2
+            r = make_req(rng, int(rng.integers(1, 50)), cs[m], steps=False)
+            work.append((m, r, s.submit(m, *r)))
+        for m, r, i in work:
+            assert s.wait(i) == tb.OK
+            check(r, cs[m])
+        st = s.stats()
+        assert st["completed"] == 20
+        assert st["launches"] <= 4, st["launches"]   # first request, then at most one per model per wave
