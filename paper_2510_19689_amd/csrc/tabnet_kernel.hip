@@ -867,37 +867,43 @@ __device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[T
   }
 }
 
-// Two waves per SIMD (two workgroups per CU): the register budget is 256 per lane in all.
-template <int PREC, int DT, int NT, int KA0, int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) tabnet_wide_kernel(FwdArgs A) {
+// A workgroup holds RG such groups of W waves (RG blocks of 16 rows) that share every
+// weight chunk, so the weights stream once per 16 RG rows.  Two waves per SIMD: the
+// register budget is 256 per lane in all.
+template <int PREC, int DT, int NT, int KA0, int W, int RG>
+__global__ void __launch_bounds__(64 * W * RG) __attribute__((amdgpu_waves_per_eu(2)))
+tabnet_wide_kernel(FwdArgs A) {
   using G = WideGeom<PREC, DT, NT, W>;
   constexpr int TPW = G::TPW, OPW = G::OPW;
   constexpr int KTA = NT - KA0;
   constexpr int KBA = kblocks(PREC, KTA);
   constexpr int KD = KA0 + 1 < NT ? KA0 + 1 : NT;   // tiles that can hold decision channels
   constexpr Plan PL = make_wide_plan(PREC, DT, NT, KA0, W);
+  constexpr int GROUP_LDS = G::UBYTES + NT * kFrag + W * 16 * 8 * 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
-  if ((int64_t)blockIdx.x * 16 >= B) return;       // every wave of the workgroup alike
+  if ((int64_t)blockIdx.x * 16 * RG >= B) return;  // every wave of the workgroup alike
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int rg = (threadIdx.x >> 6) / W;           // row group
+  const int wave = (threadIdx.x >> 6) % W;         // position in the feature split
   const int g = lane >> 4;
   const int rl = lane & 15;
   const int D = A.D, n_d = A.n_d;
-  const int64_t row0 = (int64_t)blockIdx.x * 16;
-  const int live_rows = (int)(B - row0 > 16 ? 16 : B - row0);
+  const int64_t row0 = ((int64_t)blockIdx.x * RG + rg) * 16;
+  const int live_rows = (int)(B - row0 < 0 ? 0 : (B - row0 > 16 ? 16 : B - row0));
   const bool live = rl < live_rows;
   const int64_t row = row0 + rl;
 
-  unsigned char* u_s = smem + 2 * PL.buf;
+  unsigned char* u_s = smem + 2 * PL.buf + (size_t)rg * GROUP_LDS;
   unsigned char* h_s = u_s + G::UBYTES;
   float* ex = reinterpret_cast<float*>(h_s + NT * kFrag);   // [2][W][16][2]
   float* st = ex + 2 * W * 16 * 2;                           // [W][16][4]
-  float* wfin_s = st + W * 16 * 4;
-  for (int e = threadIdx.x; e < A.n_out * n_d; e += 64 * W) wfin_s[e] = A.wfin[e];
+  float* wfin_s = reinterpret_cast<float*>(smem + 2 * PL.buf + (size_t)RG * GROUP_LDS);
+  int* open_s = reinterpret_cast<int*>(wfin_s + A.n_out * n_d);   // [2][RG]: rows still open
+  for (int e = threadIdx.x; e < A.n_out * n_d; e += 64 * W * RG) wfin_s[e] = A.wfin[e];
 
-  WeightStream<W, PL.buf> ws;
+  WeightStream<W * RG, PL.buf> ws;
   ws.lds = smem;
   ws.wts = A.wts;
   ws.tab = A.chunks;
@@ -1048,6 +1054,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))
       }
       int kprev = 0x7fffffff;
       bool done = false;
+      bool open = true;               // some row of this group is still open (wave-uniform)
       for (int it = 0; it <= 16 * G::DTP + 1; ++it) {
         float sp[4] = {0.f, 0.f, 0.f, 0.f};
         int kp[4] = {0, 0, 0, 0};
@@ -1066,7 +1073,12 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))
           e[(wave * 16 + rl) * 2 + 0] = smw;
           e[(wave * 16 + rl) * 2 + 1] = (float)kw;
         }
+        if (wave == 0 && lane == 0) open_s[(it & 1) * RG + rg] = open ? 1 : 0;
         lds_block_sync();
+        // leave together once no group had an open row after the previous pass
+        int any_group = 0;
+        for (int q = 0; q < RG; ++q) any_group |= open_s[(it & 1) * RG + q];
+        if (!any_group) break;
         float sm = 0.f;
         int k = 0;
         for (int w = 0; w < W; ++w) {
@@ -1082,7 +1094,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))
             if (it == 0 && k == kbest && vlast > tau) done = true;
           }
         }
-        if (!__any(!done)) break;
+        open = __any(!done);
       }
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
@@ -1194,14 +1206,20 @@ struct KernelEntry {
 #ifndef TABNET_WIDE_W
 #define TABNET_WIDE_W 4
 #endif
+#ifndef TABNET_WIDE_RG
+#define TABNET_WIDE_RG 2
+#endif
 #define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                                 \
   {P, DT, NT, KA0, R, W, false, tabnet_forward_kernel<P, DT, NT, KA0, R, W, false>,                      \
    make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},                                                   \
       {P, DT, NT, KA0, R, W, true, tabnet_forward_kernel<P, DT, NT, KA0, R, W, true>,                    \
        make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},
 // Split-feature kernels for models too wide for the register-resident layout.
-#define TABNET_WIDE_SHAPE(P, DT, NT, KA0, W) \
-  {P, DT, NT, KA0, 1, W, false, tabnet_wide_kernel<P, DT, NT, KA0, W>, make_wide_plan(P, DT, NT, KA0, W)},
+// (W waves share out the features of 16 rows; RG such groups per workgroup: R = RG and
+// the entry's W counts all W RG waves.)
+#define TABNET_WIDE_SHAPE(P, DT, NT, KA0, W, RG)                                                         \
+  {P, DT, NT, KA0, RG, W * RG, false, tabnet_wide_kernel<P, DT, NT, KA0, W, RG>,                         \
+   make_wide_plan(P, DT, NT, KA0, W)},
 #define TABNET_SHAPES(P)          \
   TABNET_SHAPE(P, 1, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 2, 1, 0, 1, 4)  \
@@ -1212,7 +1230,8 @@ struct KernelEntry {
   TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)
-                                       TABNET_WIDE_SHAPE(0, 32, 8, 4, 4) TABNET_WIDE_SHAPE(1, 32, 8, 4, 4)};
+                                       TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
+                                           TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
 
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
   for (const auto& e : kKernels)
@@ -1226,11 +1245,13 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len) {
   (void)C;
   if (k->plan.wide) {
-    // weight buffers, u (B-operand layout), h (FP32), sparsemax exchange and start areas,
-    // the final map
-    const int dtp = wide_tpw(k->DT, k->W) * k->W;
+    // weight buffers; per row group u (B-operand layout), h (FP32), the sparsemax exchange
+    // and start areas; the final map and the open-row flags
+    const int wf = k->plan.W;
+    const int dtp = wide_tpw(k->DT, wf) * wf;
     const size_t ub = (size_t)(k->prec == 0 ? dtp : dtp / 2) * kFrag;
-    return 2 * (size_t)k->plan.buf + ub + (size_t)k->NT * kFrag + ((size_t)k->W * 16 * 8 + (size_t)n_out * n_d) * 4;
+    const size_t group = ub + (size_t)k->NT * kFrag + (size_t)wf * 16 * 8 * 4;
+    return 2 * (size_t)k->plan.buf + (size_t)k->R * group + (size_t)n_out * n_d * 4 + 2 * (size_t)k->R * 4;
   }
   const size_t wf = k->raw ? ((size_t)n_out * n_d + 3) / 4 * 4 : (size_t)n_out * n_d;
   return 2 * (size_t)k->plan.buf + ((size_t)k->W * 16 * k->R * D + wf) * sizeof(float) +
@@ -1245,7 +1266,7 @@ hipError_t prepare_kernel(const KernelEntry* k) {
 }
 
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream) {
-  const int64_t rows_per_block = k->plan.wide ? 16 : 16LL * k->R * k->W;
+  const int64_t rows_per_block = k->plan.wide ? 16LL * k->R : 16LL * k->R * k->W;
   const int64_t blocks = (a.B + rows_per_block - 1) / rows_per_block;
   hipLaunchKernelGGL(k->fn, dim3((unsigned)blocks), dim3(64 * k->W),
                      kernel_lds_bytes(k, a.D, a.n_out, a.n_d, a.C, a.tab_lds ? a.tab_len : 0), stream, a);

@@ -114,6 +114,10 @@ constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   return Plan{first, mid, att, buf};
 }
 
+// Fragment bytes of one K slice of the split-feature kernel, in KiB (plus the shifts).
+#ifndef TABNET_WIDE_SLICE_KIB
+#define TABNET_WIDE_SLICE_KIB 32
+#endif
 // Split-feature plan: wave w owns feature tiles [w tpw, (w + 1) tpw) of the padded row
 // (tpw even, so that BF16 tile pairs never straddle waves) and output tile pairs
 // [w NT / W, (w + 1) NT / W) of every feature-transformer layer.
@@ -126,10 +130,11 @@ constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   p.wide = 1;
   p.W = W;
   p.tpw = wide_tpw(DT, W);
-  p.sk = NT >= 8 ? 1 : 8 / NT;                  // slice chunks of at most 16 KiB + shifts
+  constexpr int kib = TABNET_WIDE_SLICE_KIB;
+  p.sk = kib / (2 * NT) < 1 ? 1 : kib / (2 * NT);   // k-blocks per slice
   p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64;
   int tpc = p.tpw;
-  while (tpc > 1 && (W * tpc * p.att_unit > 16384 || p.tpw % tpc != 0)) --tpc;
+  while (tpc > 1 && (W * tpc * p.att_unit > kib * 1024 + NT * 128 || p.tpw % tpc != 0)) --tpc;
   p.tpc = tpc;
   const int kbf = kblocks(prec, DT), kbm = kblocks(prec, NT);
   int buf = W * tpc * p.att_unit;
