@@ -34,11 +34,14 @@ Every such reading of a point the paper leaves open is listed with the design no
 
 Optional operand rounding.  ``weights``/``acts`` select how the GEMM operands are
 rounded before the (exact, float64) products, to mirror a reduced-precision path:
-weights in {None, "bf16", "e4m3"} act on the BN-folded weight W' = diag(s) W with
-s = gamma / sqrt(var + eps) (E4M3 with one scale per output channel, max|W'_n|/448);
-acts in {None, "bf16", "e4m3"} act on each GEMM input (E4M3 with one scale per row,
-max|u_r|/448).  The folded shift beta - s * mean is never rounded.  With both None the
-computation is the definition above, unchanged.
+weights in {None, "bf16", "e4m3", "int8"} act on the BN-folded weight W' = diag(s) W
+with s = gamma / sqrt(var + eps) (E4M3 with one scale per output channel,
+max|W'_n|/448; INT8 with one scale per output channel, max|W'_n|/127); acts in
+{None, "bf16", "e4m3", "int8"} act on each GEMM input (one scale per row, max|u_r|/448
+or max|u_r|/127).  The GEMM input of the attentive transformer is the attention half
+a = h[:, n_d:] alone, so its row scale is taken over those channels.  The folded shift
+beta - s * mean is never rounded.  With both None the computation is the definition
+above, unchanged.
 """
 from __future__ import annotations
 
@@ -46,7 +49,7 @@ import math
 
 import numpy as np
 
-from .rounding import round_bf16, round_e4m3, E4M3_MAX
+from .rounding import round_bf16, round_e4m3, round_int8_rows, E4M3_MAX
 from .sparsemax import sparsemax
 
 SQRT_HALF = math.sqrt(0.5)
@@ -82,6 +85,8 @@ def _round_acts(u: np.ndarray, mode):
         amax = np.max(np.abs(u), axis=1, keepdims=True)
         scale = np.where(amax > 0, amax / E4M3_MAX, 1.0)
         return round_e4m3(u / scale) * scale
+    if mode == "int8":
+        return round_int8_rows(u)
     raise ValueError(mode)
 
 
@@ -98,6 +103,8 @@ def _fc_bn(u: np.ndarray, W, bn: dict, eps: float, weights=None, acts=None) -> n
         amax = np.max(np.abs(Wf), axis=1, keepdims=True)
         sc = np.where(amax > 0, amax / E4M3_MAX, 1.0)
         Wf = round_e4m3(Wf / sc) * sc
+    elif weights == "int8":
+        Wf = round_int8_rows(Wf)
     elif weights is not None:
         raise ValueError(weights)
     return _round_acts(u, acts) @ Wf.T + shift

@@ -223,6 +223,30 @@ def test_unrounded_options_are_identity():
         np.testing.assert_array_equal(u, v)
 
 
+def test_int8_forward_invariants_and_attention_half_scale(monkeypatch):
+    """The INT8 forward keeps the mask invariants, stays near the exact forward, and
+    quantises the attentive GEMM's input over the attention half only: a decision channel
+    of h, however large, must not change the attentive scores."""
+    p, X = synth.workload("hr35", rows=64)
+    lo, ag, ms = tabnet.forward(p, X, weights="int8", acts="int8")
+    elo, eag, ems = tabnet.forward(p, X)
+    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(ag.sum(-1), 1.0, atol=1e-12)
+    assert (ms >= 0).all() and np.abs(lo - elo).max() < 0.1
+    seen = []
+    real = tabnet._round_acts
+
+    def spy(u, mode):
+        seen.append(u.shape[1])
+        return real(u, mode)
+    monkeypatch.setattr(tabnet, "_round_acts", spy)
+    tabnet.forward(p, X[:2], weights="int8", acts="int8")
+    cfg = p["config"]
+    # per step: the attentive input has n_a columns; FT inputs have D or N columns
+    assert seen.count(cfg.n_a) == cfg.n_steps
+    assert set(seen) <= {cfg.n_a, cfg.D, cfg.n_d + cfg.n_a}
+
+
 def test_folded_form_equals_bn_form():
     """BN(u W^T) = u (diag(s) W)^T + (beta - s mean): the folded form the rounding
     option uses reduces to the plain definition when nothing is rounded."""
