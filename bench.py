@@ -317,6 +317,9 @@ def main():
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--quant", default="fp8,int8",
+                    help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights; int8: "
+                         "INT8 weights and GEMM inputs); empty to skip")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
                     help="request rates (req/s) of the serving leg; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -363,8 +366,16 @@ def main():
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, f"{name}.tnw")
         synth.write_weights(params, path)
-        for prec in (["bf16"] if args.skip_fp32 else ["bf16", "fp32"]):
-            with tabnet.Model(path, prec) as m:
+        precs = ["bf16"] + ([] if args.skip_fp32 else ["fp32"]) + [p for p in args.quant.split(",") if p]
+        for prec in precs:
+            try:
+                m = tabnet.Model(path, prec)
+            except tabnet.TabNetError as err:
+                if err.status != tabnet.E_UNSUPPORTED or prec in ("bf16", "fp32"):
+                    raise
+                print(f"[bench] {prec}: no kernel for this shape", file=sys.stderr, flush=True)
+                continue
+            with m:
                 outs = m.outputs(rows, with_steps=True)
                 t, wall = time_forward(m, X, outs, args.steps, args.warmup)
                 res[prec] = (t, wall)
@@ -452,6 +463,16 @@ def main():
         out["fp32_rows_per_s"] = rows * args.steps / t32
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
+    quant = {}
+    for prec, what in (("fp8", "E4M3 weights (one scale per output channel), BF16 GEMM inputs"),
+                       ("int8", "INT8 weights (one scale per output channel) and GEMM inputs (one step "
+                                "per row), INT32 products")):
+        if prec in res:
+            tq = res[prec][0]
+            quant[prec] = {"what": what, "us_per_forward": tq / args.steps * 1e6,
+                           "rows_per_s": rows * args.steps / tq, "over_bf16": t_bf16 / tq}
+    if quant:
+        out["quantised"] = quant
     out["wall_s_bf16"] = wall_bf16
     if "detail" in res:
         out["bf16_forward_detail"] = res["detail"]

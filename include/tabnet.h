@@ -45,7 +45,8 @@ typedef enum {
 typedef enum {
     TABNET_FP32 = 0,      /* FP32 MFMA GEMMs, FP32 everything                            */
     TABNET_BF16 = 1,      /* BF16 GEMM operands (RNE), FP32 accumulate and epilogues      */
-    TABNET_FP8_E4M3 = 2   /* E4M3 weights with one scale per output channel; see below   */
+    TABNET_FP8_E4M3 = 2,  /* E4M3 weights with one scale per output channel; see below   */
+    TABNET_INT8 = 3       /* INT8 weights and GEMM inputs, INT32 products; see below      */
 } tabnet_precision;
 
 /* Model hyper-parameters as stored in the weight file.  N = n_d + n_a. */
@@ -85,6 +86,18 @@ typedef struct tabnet_handle tabnet_handle;
  * sigma_n = max_k |W'_nk| / 448, and feeds the GEMMs BF16 activations (the weights are
  * widened to BF16 exactly on the way into the matrix cores); accumulation, the GLU and
  * residual epilogues, the prior, sparsemax and aggregation stay in FP32.
+ *
+ * TABNET_INT8 is the paper's FP32-to-INT8 quantisation (Sec. VI-D) in symmetric form:
+ * each GEMM weight row is stored as integer codes in [-127, 127] with one FP32 scale
+ * sigma_n = max_k |W'_nk| / 127, and each GEMM input row (the masked features, the
+ * hidden state, or its attention half for the attentive transformer) is coded the same
+ * way on the fly, with its own step max_k |u_k| / 127 and ties rounded to even.  The
+ * products are exact INT32 sums on the integer matrix cores, dequantised by
+ * sigma_n * step before the folded shift is added; everything else stays in FP32.
+ * A row that holds a non-finite value gets unspecified outputs (other rows are not
+ * affected).  INT8 has entries for the register-resident kernel shapes only: a model
+ * served by the split-feature kernel (the 512-feature shape) is TABNET_E_UNSUPPORTED in
+ * INT8.
  */
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out);
 

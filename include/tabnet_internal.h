@@ -22,6 +22,11 @@ uint16_t tabnet_hook_bf16_bits(double x);
 /* float8 E4M3FN bits of x, round to nearest even, saturating at +-448. */
 uint8_t tabnet_hook_e4m3_bits(double x);
 
+/* The load-time INT8 coding of a weight matrix W [rows][cols] (row-major, caller-owned):
+ * per row, scale = max_k |W_k| / 127 (1 for a zero row) into scales[row], and W_k
+ * replaced in place by round(W_k / scale) (ties to even), as TABNET_INT8 packs it. */
+void tabnet_hook_int8_rows(double* W, int rows, int cols, double* scales);
+
 /* Parse and validate a TNW1 image held in memory (buffer of `len` bytes, caller-owned).
  * On success fills *cfg.  Returns the status tabnet_load would return for that file. */
 tabnet_status tabnet_hook_parse(const void* buf, size_t len, tabnet_config* cfg);

@@ -76,7 +76,7 @@ const char* tabnet_last_error(void) { return g_err.c_str(); }
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out) {
   if (out == nullptr || path == nullptr) return fail(TABNET_E_INVALID, "tabnet_load: NULL argument");
   *out = nullptr;
-  if (precision < TABNET_FP32 || precision > TABNET_FP8_E4M3)
+  if (precision < TABNET_FP32 || precision > TABNET_INT8)
     return fail(TABNET_E_INVALID, "tabnet_load: unknown precision");
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(TABNET_E_IO, std::string("tabnet_load: cannot open ") + path);
@@ -90,8 +90,7 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   tabnet_status st = parse_model(img.data(), img.size(), &m, &err);
   if (st != TABNET_OK) return fail(st, "tabnet_load: " + err);
   const Shape sh = shape_of(m.cfg);
-  const int kprec = precision == TABNET_FP32 ? 0 : (precision == TABNET_BF16 ? 1 : 2);
-  const KernelEntry* k = find_kernel(kprec, sh.DT, sh.NT, sh.KA0, false);
+  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);   // kernel prec = tabnet_precision
   if (!k) {
     char msg[256];
     std::snprintf(msg, sizeof msg,

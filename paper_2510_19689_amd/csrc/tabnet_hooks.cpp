@@ -14,6 +14,14 @@ extern "C" {
 uint16_t tabnet_hook_bf16_bits(double x) { return bf16_bits_rne(x); }
 uint8_t tabnet_hook_e4m3_bits(double x) { return e4m3_bits_rne(x); }
 
+void tabnet_hook_int8_rows(double* W, int rows, int cols, double* scales) {
+  if (!W || !scales || rows < 1 || cols < 1) return;
+  std::vector<double> w(W, W + (size_t)rows * cols), b(rows, 0.0), s;
+  quantize_rows_int8(&w, &b, rows, cols, rows, &s);
+  for (size_t i = 0; i < w.size(); ++i) W[i] = w[i];
+  for (int r = 0; r < rows; ++r) scales[r] = s[r];
+}
+
 tabnet_status tabnet_hook_parse(const void* buf, size_t len, tabnet_config* cfg) {
   if (!buf || !cfg) return TABNET_E_INVALID;
   ModelRaw m;
@@ -53,7 +61,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   std::string err;
   tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
   if (st != TABNET_OK) return st;
-  if (precision < TABNET_FP32 || precision > TABNET_FP8_E4M3) return TABNET_E_INVALID;
+  if (precision < TABNET_FP32 || precision > TABNET_INT8) return TABNET_E_INVALID;
   const Shape sh = shape_of(m.cfg);
   const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);
   if (!k) return TABNET_E_UNSUPPORTED;

@@ -7,6 +7,7 @@ namespace tabnet {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kSqrtHalf = 0.70710678118654752f;
@@ -141,6 +142,85 @@ struct BOp<1, KT, R> {        // BF16: two packed dwords per tile
 template <int KT, int R>
 struct BOp<2, KT, R> : BOp<1, KT, R> {};   // E4M3 weights: BF16 activations
 
+// INT8: symmetric codes with one step per row, s = max_k |u_k| / 127, c_k = round(u_k / s)
+// (ties to even), four codes of a tile in one dword (feature 16 t + 4 g + i in byte i).
+// The row maximum is the lane's own maximum and two cross-lane exchanges.  A code is
+// formed by one FMA: u * (127 / max) + 1.5 * 2^23 rounds the exact product to an integer
+// (ties to even) held in the low mantissa bits, whose low byte is the two's-complement
+// code, since |u * 127 / max| <= 127.5 keeps the sum inside [2^23, 2^24).
+template <int KT, int R>
+struct BOp<3, KT, R> {
+  uint32_t v[R][KT];
+  float s[R];                 // the row's step (0 for an all-zero row)
+  template <class F>
+  __device__ __forceinline__ void build(F src) {
+    constexpr float kRound = 12582912.0f;   // 1.5 * 2^23
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+      float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i & 1) m1 = fmaxf(m1, fabsf(src(rb, t, i)));
+          else m0 = fmaxf(m0, fabsf(src(rb, t, i)));
+        }
+      const float amax = row_max(fmaxf(m0, m1));
+      s[rb] = amax * (1.0f / 127.0f);
+      const float inv = amax > 0.f ? 127.0f / amax : 0.f;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        uint32_t c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = __float_as_uint(__builtin_fmaf(src(rb, t, i), inv, kRound));
+        // v_perm_b32: byte k of the result is byte sel_k of {src0 (bytes 4-7), src1 (bytes 0-3)}
+        const uint32_t lo = __builtin_amdgcn_perm(c[1], c[0], 0x0c0c0400u);
+        const uint32_t hi = __builtin_amdgcn_perm(c[3], c[2], 0x0c0c0400u);
+        v[rb][t] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+      }
+    }
+  }
+};
+
+// Fill a GEMM's B operand from src(rb, t, i), the input of row block rb at the lane's
+// feature 16 t + 4 g + i.
+template <int PREC, int KT, int R, class F>
+__device__ __forceinline__ void build_b(BOp<PREC, KT, R>& b, F src) {
+  if constexpr (PREC == 3) {
+    b.build(src);
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const float v[4] = {src(rb, t, 0), src(rb, t, 1), src(rb, t, 2), src(rb, t, 3)};
+        b.set(rb, t, v);
+      }
+  }
+}
+
+// INT8: acc[rb] += Wq(one output tile, all K) * codes[rb], exactly in INT32 (K <= 2^14
+// keeps |acc| < 127 * 127 * 2^14 < 2^31); four K tiles per 16x16x64 MFMA.
+template <int KT, int R>
+__device__ __forceinline__ void mma_tile_i8(const unsigned char* fr, const BOp<3, KT, R>& b, i4 (&acc)[R],
+                                            int lane) {
+  constexpr int KQ = kblocks(3, KT);
+#pragma unroll
+  for (int kb = 0; kb < KQ; ++kb) {
+    const i4 a = *reinterpret_cast<const i4*>(fr + kb * kFrag + lane * 16);
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+      uint32_t q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = 4 * kb + j;
+        q[j] = t < KT ? b.v[rb][t < KT ? t : 0] : 0u;
+      }
+      acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, __builtin_bit_cast(i4, q), acc[rb], 0, 0, 0);
+    }
+  }
+}
+
 // acc[rb] += W'(one output tile, all K) * B[rb]; `fr` points at the tile's fragments
 // in LDS (kblocks(PREC, KT) fragments of 1 KiB).
 template <int PREC, int KT, int R>
@@ -268,6 +348,26 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
         const unsigned char* unit = buf + u * UNIT;
         const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 16 * g);
         const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 64 + 16 * g);
+        if constexpr (PREC == 3) {
+          // integer products, dequantised by (channel scale) x (row step); the gate's shift
+          // and scale carry the factor -log2(e) of the sigmoid's exponent
+          i4 qv[R], qg[R];
+#pragma unroll
+          for (int rb = 0; rb < R; ++rb) { qv[rb] = i4{0, 0, 0, 0}; qg[rb] = i4{0, 0, 0, 0}; }
+          mma_tile_i8<KT, R>(unit, b, qv, lane);
+          mma_tile_i8<KT, R>(unit + KB * kFrag, b, qg, lane);
+          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 128 + 16 * g);
+          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 192 + 16 * g);
+#pragma unroll
+          for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float v = __builtin_fmaf((float)qv[rb][i], sv[i] * b.s[rb], bv[i]);
+              const float e = __builtin_fmaf((float)qg[rb][i], sgt[i] * b.s[rb], bg[i]);
+              const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(e));
+              h[rb][mt][i] = first ? v * sg : __builtin_fmaf(v, sg, h[rb][mt][i]) * kSqrtHalf;
+            }
+        } else {
         f4 av[R], ag[R];
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
@@ -294,6 +394,7 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
               h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
             }
         }
+        }
       }
     }
     ws.end();
@@ -308,10 +409,7 @@ __device__ __forceinline__ void ft_pass(WS& ws, int L, const BOp<PREC, DT, R>& u
   glu_layer<PREC, DT, NT, R, P.first.unit, P.first.upc, P.first.nchunks>(ws, u, h, true, lane);
   for (int l = 1; l < L; ++l) {
     BOp<PREC, NT, R> bh;
-#pragma unroll
-    for (int rb = 0; rb < R; ++rb)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) bh.set(rb, t, h[rb][t]);
+    build_b(bh, [&](int rb, int t, int i) { return h[rb][t][i]; });
     glu_layer<PREC, NT, NT, R, P.mid.unit, P.mid.upc, P.mid.nchunks>(ws, bh, h, false, lane);
   }
 }
@@ -501,10 +599,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   // ---- pass 0: only its attention half is used ----
   {
     BOp<PREC, DT, R> u;
-#pragma unroll
-    for (int rb = 0; rb < R; ++rb)
-#pragma unroll
-      for (int t = 0; t < DT; ++t) u.set(rb, t, x[rb][t]);
+    build_b(u, [&](int rb, int t, int i) { return x[rb][t][i]; });
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
   }
 
@@ -513,10 +608,13 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     // ---- attentive transformer: z = P * (a W_att'^T + b_att') ----
     {
       BOp<PREC, KTA, R> ba;
-#pragma unroll
-      for (int rb = 0; rb < R; ++rb)
-#pragma unroll
-        for (int t = 0; t < KTA; ++t) ba.set(rb, t, h[rb][KA0 + t]);
+      // the attention half a = h[n_d, N): INT8 takes its row step over those channels only
+      // (the weights of the other channels in these tiles are zero)
+      const int n_att_end = n_d + A.n_a;
+      build_b(ba, [&](int rb, int t, int i) {
+        const int ch = 16 * (KA0 + t) + 4 * g + i;
+        return PREC != 3 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
+      });
       constexpr int KBA = kblocks(PREC, KTA);
 #pragma unroll
       for (int c = 0; c < PL.att.nchunks; ++c) {
@@ -528,6 +626,20 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           if (mt < DT) {
             const unsigned char* unit = buf + u * PL.att.unit;
             const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
+            if constexpr (PREC == 3) {
+              i4 qa[R];
+#pragma unroll
+              for (int rb = 0; rb < R; ++rb) qa[rb] = i4{0, 0, 0, 0};
+              mma_tile_i8<KTA, R>(unit, ba, qa, lane);
+              const f4 scl = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
+#pragma unroll
+              for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const float hz = __builtin_fmaf((float)qa[rb][i], scl[i] * ba.s[rb], bv[i]);
+                  M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
+                }
+            } else {
             f4 za[R];
 #pragma unroll
             for (int rb = 0; rb < R; ++rb) za[rb] = bv;
@@ -541,6 +653,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
                 const float hz = PREC == 2 ? za[rb][i] * scl[i] : za[rb][i];
                 M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
               }
+            }
           }
         }
         ws.end();
@@ -660,18 +773,12 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     }
     BOp<PREC, DT, R> u;
 #pragma unroll
-    for (int rb = 0; rb < R; ++rb) {
+    for (int rb = 0; rb < R; ++rb)
 #pragma unroll
-      for (int t = 0; t < DT; ++t) {
-        float uu[4];
+      for (int t = 0; t < DT; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          P[rb][t][i] *= A.gamma - M[rb][t][i];
-          uu[i] = M[rb][t][i] * x[rb][t][i];
-        }
-        u.set(rb, t, uu);
-      }
-    }
+        for (int i = 0; i < 4; ++i) P[rb][t][i] *= A.gamma - M[rb][t][i];
+    build_b(u, [&](int rb, int t, int i) { return M[rb][t][i] * x[rb][t][i]; });
     // ---- feature transformer pass s, decision aggregation ----
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
 #pragma unroll
@@ -1229,7 +1336,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
   TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
-static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2)
+static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
 

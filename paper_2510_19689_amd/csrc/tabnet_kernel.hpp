@@ -35,12 +35,16 @@
 // Packed layout of one GEMM (each starts 256-byte aligned), as a sequence of units:
 //   GLU layer, unit mt = 0..NT-1:  [value-tile fragments][gate-tile fragments]
 //                                  [16 value shifts][16 gate shifts]
-//                                  (E4M3: then [16 value scales][16 gate scales])
-//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (E4M3: then [16 scales])
+//                                  (E4M3, INT8: then [16 value scales][16 gate scales])
+//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (E4M3, INT8: then [16 scales])
 // A fragment is 64 lanes x 16 bytes: FP32 one per 16-wide K tile (a lane's float4 feeds
 // four 16x16x4 MFMAs), BF16 one per pair of K tiles (8 bf16 per lane, one 16x16x32 MFMA;
-// an odd last tile is paired with zeros).  Shifts are in C-layout order: slot 4 q + i
-// of tile mt is output feature 16 mt + 4 q + i.
+// an odd last tile is paired with zeros), INT8 one per four K tiles (16 codes per lane,
+// one 16x16x64 integer MFMA; missing tiles are zeros).  Shifts are in C-layout order:
+// slot 4 q + i of tile mt is output feature 16 mt + 4 q + i.  In INT8 the gate half's
+// shifts and scales are stored multiplied by -log2(e), the factor of the sigmoid's
+// exponent, and the shifts are not divided by the scales (the integer products are
+// dequantised before the shift is added).
 #pragma once
 #include <stdint.h>
 
@@ -65,7 +69,11 @@ struct GemmPlan {
   int nchunks;
 };
 
-constexpr int kblocks(int prec, int KT) { return prec == 0 ? KT : (KT + 1) / 2; }
+// K tiles per k-block: 1 (FP32), 2 (BF16 and E4M3 weights), 4 (INT8)
+constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 3 ? 4 : 2); }
+constexpr int kblocks(int prec, int KT) {
+  return (KT + ktiles_per_block(prec) - 1) / ktiles_per_block(prec);
+}
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Units per chunk: balanced chunks of at most `target` bytes (one unit if a single unit
@@ -103,10 +111,11 @@ struct Plan {
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 // prec: 0 FP32, 1 BF16, 2 E4M3 weights (BF16 fragments holding the E4M3 codes, plus one
-// FP32 scale per output channel after the shifts).  DT = ceil(D/16), NT = ceil(N/16),
-// KA0 = floor(n_d/16).
+// FP32 scale per output channel after the shifts), 3 INT8 weights and activations (INT8
+// fragments, one FP32 scale per output channel after the shifts).  DT = ceil(D/16),
+// NT = ceil(N/16), KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
-  const int sc = prec == 2 ? 2 : 1;   // shifts, or shifts + scales
+  const int sc = prec >= 2 ? 2 : 1;   // shifts, or shifts + scales
   const GemmPlan first = gemm_plan(2 * kblocks(prec, DT) * kFrag + 128 * sc, NT, target);
   const GemmPlan mid = gemm_plan(2 * kblocks(prec, NT) * kFrag + 128 * sc, NT, target);
   const GemmPlan att = gemm_plan(kblocks(prec, NT - KA0) * kFrag + 64 * sc, DT, target);

@@ -229,6 +229,28 @@ double e4m3_value(uint8_t b) {
   return s ? -v : v;
 }
 
+// Symmetric INT8 with one scale per output row: s_n = max_k |W'_nk| / 127 (1 for a zero
+// row), Wf <- round(W' / s_n) (ties to even), the codes in [-127, 127].  The shift is kept
+// as it is: the kernel adds it after dequantising the integer products.  Rows
+// [neg_lo, rows) (the gate half of a GLU layer) get their shift and scale multiplied by
+// -log2(e), the factor of the sigmoid's exponent.
+void quantize_rows_int8(std::vector<double>* Wf, std::vector<double>* bf, int rows, int cols, int neg_lo,
+                        std::vector<double>* scale) {
+  const double kNegLog2e = -1.4426950408889634;
+  scale->assign(rows, 1.0);
+  for (int r = 0; r < rows; ++r) {
+    double amax = 0;
+    for (int k = 0; k < cols; ++k) amax = std::fmax(amax, std::fabs((*Wf)[(size_t)r * cols + k]));
+    const double s = amax > 0 ? amax / 127.0 : 1.0;
+    for (int k = 0; k < cols; ++k) {
+      double& w = (*Wf)[(size_t)r * cols + k];
+      w = std::nearbyint(w / s);
+    }
+    (*scale)[r] = r >= neg_lo ? s * kNegLog2e : s;
+    if (r >= neg_lo) (*bf)[r] *= kNegLog2e;
+  }
+}
+
 // ---------------------------------------------------------------- packing
 Shape shape_of(const tabnet_config& c) {
   Shape s;
@@ -249,7 +271,8 @@ void emit(std::vector<unsigned char>* out, const void* p, size_t n) {
 // the folded weights Wf [rows][cols], K over KT tiles with col_of(kin) mapping the
 // kernel's K index 16 t + 4 q + j to a column of Wf (-1 = zero).
 // Only k-blocks [kb_lo, kb_hi) are emitted (a k-block is one K tile in FP32, a pair of
-// K tiles in BF16); kb_hi < 0 means all of them.
+// K tiles in BF16, four K tiles in INT8); kb_hi < 0 means all of them.  In INT8, Wf holds
+// the integer codes.
 template <class RowOf, class ColOf>
 void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precision, RowOf row_of,
                     ColOf col_of, std::vector<unsigned char>* wts, int kb_lo = 0, int kb_hi = -1) {
@@ -265,6 +288,18 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         const int i = lane & 15, q = lane >> 4;
         float v[4];
         for (int r = 0; r < 4; ++r) v[r] = (float)wv(i, 16 * kt + 4 * q + r);
+        emit(wts, v, sizeof v);
+      }
+  } else if (precision == TABNET_INT8) {
+    const int KQ = (KT + 3) / 4;   // missing tiles of the last block are zeros
+    for (int kb = kb_lo; kb < (kb_hi < 0 ? KQ : kb_hi); ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, q = lane >> 4;
+        int8_t v[16];
+        for (int j = 0; j < 16; ++j) {
+          const int t = 4 * kb + j / 4;
+          v[j] = (int8_t)std::lrint(t < KT ? wv(i, 16 * t + 4 * q + (j & 3)) : 0.0);
+        }
         emit(wts, v, sizeof v);
       }
   } else {
@@ -388,6 +423,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
   const bool fp8 = precision == TABNET_FP8_E4M3;
+  const bool i8 = precision == TABNET_INT8;
   *out = Packed();
   // input BN as a per-column affine map
   out->in_affine.assign(32 * sh.DT, 0.f);
@@ -410,6 +446,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
     if (fp8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, &sc);
+    if (i8) quantize_rows_int8(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
     const int KT = (L->cols + 15) / 16;   // the first layer of a pass reads D features, the others N
     const int K = L->cols;
     align();
@@ -424,7 +461,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
       const int nv = std::min(16, N - 16 * mt);
       emit_vals(bf, nv, 16 * mt, 0.f, &out->wts);
       emit_vals(bf, nv, N + 16 * mt, 0.f, &out->wts);
-      if (fp8) {
+      if (fp8 || i8) {
         emit_vals(sc, nv, 16 * mt, 1.f, &out->wts);
         emit_vals(sc, nv, N + 16 * mt, 1.f, &out->wts);
       }
@@ -435,6 +472,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
     if (fp8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, &sc);
+    if (i8) quantize_rows_int8(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
     const int KTA = sh.NT - sh.KA0;
     align();
     out->att_off.push_back((int64_t)out->wts.size());
@@ -445,7 +483,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
           [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
           &out->wts);
       emit_vals(bf, std::min(16, c.D - 16 * mt), 16 * mt, 0.f, &out->wts);
-      if (fp8) emit_vals(sc, std::min(16, c.D - 16 * mt), 16 * mt, 1.f, &out->wts);
+      if (fp8 || i8) emit_vals(sc, std::min(16, c.D - 16 * mt), 16 * mt, 1.f, &out->wts);
     }
   }
   align();

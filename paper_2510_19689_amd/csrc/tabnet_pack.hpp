@@ -44,6 +44,12 @@ uint8_t e4m3_bits_rne(double x);
 double bf16_value(uint16_t bits);
 double e4m3_value(uint8_t bits);
 
+// Symmetric INT8 coding of each row of Wf [rows][cols] in place (codes as doubles), one
+// scale per row into *scale; rows from neg_lo on (a GLU layer's gates) get their shift in
+// *bf and their scale multiplied by -log2(e).
+void quantize_rows_int8(std::vector<double>* Wf, std::vector<double>* bf, int rows, int cols, int neg_lo,
+                        std::vector<double>* scale);
+
 // Kernel shape: tiles of 16 features.
 struct Shape {
   int DT, NT, KA0;

@@ -114,11 +114,37 @@ def test_rounding_hooks_match_torch(L):
     assert L.tabnet_hook_e4m3_bits(1000.0) == 0x7E and L.tabnet_hook_e4m3_bits(-1000.0) == 0xFE
 
 
+def test_int8_weight_coding_matches_oracle(L):
+    """The packer's INT8 coding of folded weights is the oracle's, code for code."""
+    from oracle.rounding import quantise_int8_rows
+    cfg = synth.WORKLOADS["adult108"]["cfg"]
+    raw = synth.to_bytes(synth.make_params(cfg, 3))
+    rows, cols = ctypes.c_int(), ctypes.c_int()
+    for layer in (0, 2, 5, 18):          # shared, step-specific, attentive (the last layer)
+        assert L.tabnet_hook_fold(raw, len(raw), layer, None, None, ctypes.byref(rows), ctypes.byref(cols)) == 0
+        Wf = np.zeros((rows.value, cols.value))
+        bf = np.zeros(rows.value)
+        assert L.tabnet_hook_fold(raw, len(raw), layer, Wf.ctypes.data_as(ctypes.c_void_p),
+                                  bf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rows), ctypes.byref(cols)) == 0
+        codes, scale = quantise_int8_rows(Wf)
+        W = Wf.copy()
+        sc = np.zeros(rows.value)
+        L.tabnet_hook_int8_rows(W.ctypes.data_as(ctypes.c_void_p), rows.value, cols.value,
+                                sc.ctypes.data_as(ctypes.c_void_p))
+        np.testing.assert_array_equal(W, codes.astype(np.float64))
+        np.testing.assert_array_equal(sc, scale[:, 0])
+    z = np.zeros((2, 3))
+    sc = np.zeros(2)
+    L.tabnet_hook_int8_rows(z.ctypes.data_as(ctypes.c_void_p), 2, 3, sc.ctypes.data_as(ctypes.c_void_p))
+    assert (z == 0).all() and (sc == 1.0).all()
+
+
 def test_packed_sizes(L):
     """Packed bytes follow the documented unit layout: a GLU layer is NT units of
     [value fragments][gate fragments][32 shifts], an attentive layer DT units of
-    [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32) or per pair
-    of K tiles (BF16, an odd last tile padded); every GEMM starts 256-byte aligned.
+    [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32), per pair
+    of K tiles (BF16, an odd last tile padded) or per four K tiles (INT8); E4M3 and INT8
+    units add one scale per output; every GEMM starts 256-byte aligned.
     The chunk count is the number of weight-stream pieces of at most T bytes (balanced,
     one unit if a unit is larger) over pass 0, then per step attentive + pass, where T is
     40 KiB or less: the two LDS buffers must fit beside the staging areas of the
@@ -141,9 +167,10 @@ def test_packed_sizes(L):
         target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in (0, 1, 2):
-            kb = (lambda KT: KT) if prec == 0 else (lambda KT: cdiv(KT, 2))
-            ex = 2 if prec == 2 else 1          # E4M3 units also carry one scale per output
+        for prec in (0, 1, 2, 3):
+            per = {0: 1, 1: 2, 2: 2, 3: 4}[prec]     # K tiles per fragment (INT8: four)
+            kb = (lambda KT, per=per: cdiv(KT, per))
+            ex = 2 if prec >= 2 else 1          # E4M3 and INT8 units also carry one scale per output
             glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 * ex for k in set(ks)}
             att_unit = kb(NT - KA0) * 1024 + 64 * ex
             exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
