@@ -1,8 +1,8 @@
 """Round-to-nearest-even onto the reduced-precision grids, written from the formats'
 definitions (test infrastructure; never on the product path).
 
-The paper names reduced precision ("quantization ... and kernel fusion") as the next
-step for its TabNet inference (Sec. VI-D).  The oracle can round GEMM operands the way
+The paper names reduced-precision arithmetic, beside kernel fusion, as a next step for
+its TabNet inference (Sec. VI-D).  The oracle can round GEMM operands the way
 a reduced-precision path defines them, so that a reduced-precision GPU result can be
 compared both with exact FP64 TabNet and with FP64 TabNet on the rounded operands.
 
@@ -16,6 +16,15 @@ compared both with exact FP64 TabNet and with FP64 TabNet on the rounded operand
                   s = max|v| / 127 (s = 1 for an all-zero vector): c = round(v / s), ties
                   to even, and v is read back as c * s.  The largest |v| maps to +-127
                   exactly, so no code needs clamping and -128 is never used.
+  MX block formats (OCP Microscaling v1.0): blocks of 32 elements share one power-of-two
+                  scale 2^X (an E8M0 byte) with X = floor(log2 max|v|) - emax_elem, and
+                  each element is v / 2^X rounded to nearest even in the element format,
+                  saturating at its largest normal.  Elements: E4M3 (MXFP8, emax 8, max
+                  448) and E2M1 (MXFP4, emax 2, grid 0, 0.5, 1, 1.5, 2, 3, 4, 6).  X is
+                  clamped to [-126, 127] (a block of zeros takes X = 0).  Which 32
+                  positions of a K axis form a block is given by mx_block_of: the matrix
+                  instruction that consumes these formats (128 K positions per operand
+                  row) groups them as stated there.
 """
 from __future__ import annotations
 
@@ -68,3 +77,60 @@ def round_int8_rows(x) -> np.ndarray:
     """x with every row replaced by its symmetric INT8 reading codes * scale (float64)."""
     codes, scale = quantise_int8_rows(x)
     return codes * scale
+
+
+# ---- OCP MX block formats ----
+E2M1_MAX = 6.0
+MX_ELEMENTS = {"mxfp8": (8, E4M3_MAX), "mxfp4": (2, E2M1_MAX)}   # emax of the element, largest normal
+
+
+def round_e2m1(x) -> np.ndarray:
+    """Nearest FP4 E2M1 value (ties to even), saturating at +-6, as float64.  E2M1 has
+    2 significant bits from 1 up (exponent bias 1) and a step of 0.5 below 1."""
+    x = np.asarray(x, dtype=np.float64)
+    normal = _round_sig(x, 2)
+    sub = np.rint(x * 2.0) / 2.0
+    out = np.where(np.abs(x) < 1.0, sub, normal)
+    return np.clip(out, -E2M1_MAX, E2M1_MAX)
+
+
+def _round_element(v, fmt):
+    return round_e4m3(v) if fmt == "mxfp8" else round_e2m1(v)
+
+
+def mx_block_of(p, fmt) -> np.ndarray:
+    """Block index of K position p.  Positions run in 16-wide tiles t = p // 16, each made
+    of four groups q = (p % 16) // 4; eight tiles (128 positions) form one operand row of
+    the matrix instruction, k-block kb = t // 8, which holds four blocks:
+      mxfp4: block q  (group q of all eight tiles),
+      mxfp8: block q // 2 + 2 * ((t % 8) // 4)  (groups 2 b', 2 b' + 1 of four tiles).
+    Returns kb * 4 + block."""
+    p = np.asarray(p)
+    t, q = p // 16, (p % 16) // 4
+    within = q if fmt == "mxfp4" else q // 2 + 2 * ((t % 8) // 4)
+    return (t // 8) * 4 + within
+
+
+def mx_scale_exponent(amax, fmt) -> np.ndarray:
+    """X = floor(log2 amax) - emax_elem, clamped to [-126, 127]; 0 where amax = 0."""
+    emax = MX_ELEMENTS[fmt][0]
+    amax = np.asarray(amax, dtype=np.float64)
+    _, e = np.frexp(amax)                 # amax = m 2^e, m in [0.5, 1): floor(log2 amax) = e - 1
+    X = np.clip(e - 1 - emax, -126, 127)
+    return np.where(amax > 0, X, 0)
+
+
+def round_mx_rows(x, fmt, offset: int = 0) -> np.ndarray:
+    """Every row of x [rows, K] in the MX format: column j sits at K position j + offset,
+    positions are grouped into blocks by mx_block_of, and each block of each row is
+    scaled by its own 2^X and rounded element-wise.  Returns the values read back."""
+    x = np.asarray(x, dtype=np.float64)
+    blk = mx_block_of(np.arange(x.shape[-1]) + offset, fmt)
+    out = np.empty_like(x)
+    for b in np.unique(blk):
+        cols = blk == b
+        v = x[..., cols]
+        X = mx_scale_exponent(np.max(np.abs(v), axis=-1, keepdims=True), fmt)
+        sc = np.ldexp(1.0, X)
+        out[..., cols] = _round_element(v / sc, fmt) * sc
+    return out

@@ -1,0 +1,178 @@
+"""Pins for the oracle's OCP MX block formats (MXFP8 = E4M3 elements, MXFP4 = E2M1
+elements, one power-of-two scale per block of 32; CPU only)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.rounding import (E2M1_MAX, mx_block_of, mx_scale_exponent, round_e2m1, round_e4m3,
+                             round_mx_rows)
+from oracle import tabnet as ot
+
+
+def e2m1_table():
+    """All 16 FP4 E2M1 codes decoded from the bit fields: sign, 2-bit exponent (bias 1),
+    1-bit mantissa; exponent 0 is subnormal (m / 2)."""
+    vals = []
+    for c in range(16):
+        s = -1.0 if c & 8 else 1.0
+        e, m = (c >> 1) & 3, c & 1
+        vals.append(s * (m / 2.0 if e == 0 else (1 + m / 2.0) * 2.0 ** (e - 1)))
+    return np.array(vals)
+
+
+def test_e2m1_grid_and_brute_force_rounding():
+    table = e2m1_table()
+    assert sorted(set(np.abs(table))) == [0, 0.5, 1, 1.5, 2, 3, 4, 6]
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.uniform(-8, 8, 5000), np.arange(-7, 7.01, 0.25), [0.0, 100.0, -100.0]])
+    got = round_e2m1(x)
+    for v, g in zip(x, got):
+        a = min(abs(v), E2M1_MAX)
+        d = np.abs(table[:8] - a)
+        best = np.flatnonzero(d == d.min())
+        code = best[0] if len(best) == 1 else [b for b in best if b % 2 == 0][0]   # ties: even code
+        assert g == np.copysign(table[code], v), (v, g, table[code])
+
+
+def slot_block(p, fmt):
+    """The block of K position p derived from the matrix instruction's operand layout (a
+    row of 128 K slots over 4 lane groups of 32 elements; blocks are 32 consecutive
+    slots).  The position's lane group is q = (p % 16) // 4 and its element within the
+    lane e = 4 * (t % 8) + p % 4 for tile t = p // 16.  MXFP4 lanes hold slots 32 q + e;
+    MXFP8 lanes hold slots 16 q + e for e < 16 and 64 + 16 q + (e - 16) for the rest."""
+    t, q = p // 16, (p % 16) // 4
+    e = 4 * (t % 8) + p % 4
+    if fmt == "mxfp4":
+        slot = 32 * q + e
+    else:
+        slot = 16 * q + e if e < 16 else 64 + 16 * q + (e - 16)
+    return (t // 8) * 4 + slot // 32
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_block_partition_matches_instruction_layout(fmt):
+    p = np.arange(512)
+    got = mx_block_of(p, fmt)
+    ref = np.array([slot_block(int(k), fmt) for k in p])
+    np.testing.assert_array_equal(got, ref)
+    assert (np.bincount(got) == 32).all()
+
+
+def test_scale_exponent_ocp_rule():
+    amax = np.array([1.0, 1.5, 2.0, 448.0, 500.0, 2.0 ** -20, 0.0, 3.0e38, 1e-40])
+    X8 = mx_scale_exponent(amax, "mxfp8")
+    X4 = mx_scale_exponent(amax, "mxfp4")
+    np.testing.assert_array_equal(X8[:6], [-8, -8, -7, 0, 0, -28])
+    np.testing.assert_array_equal(X4[:6], [-2, -2, -1, 6, 6, -22])
+    assert X8[6] == 0 and X4[6] == 0
+    assert X8[7] == 127 - 8 and X8[8] == -126     # clamped below
+    # the block maximum lands in [2^emax, 2^(emax + 1)) after scaling
+    for fmt, emax in (("mxfp8", 8), ("mxfp4", 2)):
+        a = np.abs(np.random.default_rng(2).normal(0, 5, 1000)) + 1e-3
+        r = a / np.ldexp(1.0, mx_scale_exponent(a, fmt))
+        assert ((r >= 2.0 ** emax) & (r < 2.0 ** (emax + 1))).all()
+
+
+def brute_mx(x, fmt, offset):
+    """Element by element: find the element's block members, their maximum, the exponent,
+    then round (pure Python loops over a small matrix)."""
+    rows, K = x.shape
+    out = np.zeros_like(x)
+    emax, vmax = (8, 448.0) if fmt == "mxfp8" else (2, 6.0)
+    for r in range(rows):
+        for j in range(K):
+            b = slot_block(j + offset, fmt)
+            members = [k for k in range(K) if slot_block(k + offset, fmt) == b]
+            m = max(abs(x[r, k]) for k in members)
+            if m == 0:
+                out[r, j] = 0.0
+                continue
+            X = int(np.floor(np.log2(m))) - emax
+            X = min(max(X, -126), 127)
+            v = x[r, j] / 2.0 ** X
+            v = float(round_e4m3(np.array([v]))[0] if fmt == "mxfp8" else round_e2m1(np.array([v]))[0])
+            out[r, j] = max(-vmax, min(vmax, v)) * 2.0 ** X
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("K,offset", [(35, 0), (108, 0), (24, 8), (64, 0)])
+def test_round_mx_rows_matches_brute_force(fmt, K, offset):
+    rng = np.random.default_rng(K + offset)
+    x = rng.normal(0, 1, (4, K)) * np.array([[1.0], [1e-3], [300.0], [1.0]])
+    x[3, :] = 0.0
+    x[3, min(5, K - 1)] = -2.5
+    np.testing.assert_array_equal(round_mx_rows(x, fmt, offset), brute_mx(x, fmt, offset))
+
+
+def test_mxfp8_elements_match_torch_e4m3_and_saturate():
+    rng = np.random.default_rng(3)
+    x = rng.normal(0, 1, (50, 128))
+    got = round_mx_rows(x, "mxfp8")
+    blk = mx_block_of(np.arange(128), "mxfp8")
+    for b in range(4):
+        cols = blk == b
+        X = mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), "mxfp8")
+        sc = np.ldexp(1.0, X)
+        # torch's E4M3 cast does not saturate: clamp to the largest normal first
+        ref = torch.tensor(np.clip(x[:, cols] / sc, -448, 448), dtype=torch.float32)
+        ref = ref.to(torch.float8_e4m3fn).to(torch.float64).numpy() * sc
+        np.testing.assert_array_equal(got[:, cols], ref)
+    # a block whose maximum scales into (448, 512) saturates at 448 * 2^X
+    y = np.zeros((1, 32))
+    y[0, 0], y[0, 1] = 500.0, 1.0
+    r = round_mx_rows(y, "mxfp8")
+    assert r[0, 0] == 448.0 and r[0, 1] == 1.0
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_mx_exact_on_grid_and_scale_equivariant(fmt):
+    rng = np.random.default_rng(4)
+    x = rng.normal(0, 1, (6, 100))
+    r = round_mx_rows(x, fmt)
+    np.testing.assert_array_equal(round_mx_rows(r, fmt), r)            # idempotent
+    np.testing.assert_array_equal(round_mx_rows(x * 2.0 ** 7, fmt), r * 2.0 ** 7)
+    np.testing.assert_array_equal(round_mx_rows(-x, fmt), -r)
+    # per element: within half a step of the grid at the block's scale (the step of the
+    # top binade [2^emax, 2^(emax+1)) bounds all), or saturated at the largest normal
+    blk = mx_block_of(np.arange(100), fmt)
+    vmax = 448.0 if fmt == "mxfp8" else E2M1_MAX
+    for b in np.unique(blk):
+        cols = blk == b
+        sc = np.ldexp(1.0, mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), fmt))
+        step = sc * (2.0 ** (8 - 3) if fmt == "mxfp8" else 2.0 ** (2 - 1))
+        err = np.abs(r[:, cols] - x[:, cols])
+        sat = (np.abs(x[:, cols]) > vmax * sc) & (np.abs(r[:, cols]) == vmax * sc)
+        assert ((err <= step / 2 * (1 + 1e-12)) | sat).all()
+
+
+def test_mx_gemm_option_uses_both_operands_and_attention_offset(monkeypatch):
+    """_fc_bn rounds the input rows and the weight rows with the same K positions; the
+    attentive GEMM's positions start at n_d mod 16."""
+    rng = np.random.default_rng(5)
+    u = rng.normal(0, 1, (7, 24))
+    W = rng.normal(0, 0.3, (5, 24))
+    eps = 2.0 ** -10
+    bn = {"gamma": np.ones(5), "beta": np.zeros(5), "mean": np.zeros(5), "var": np.full(5, 1 - eps)}
+    for fmt in ("mxfp8", "mxfp4"):
+        got = ot._fc_bn(u, W, bn, eps, weights=fmt, acts=fmt, k_offset=8)
+        ref = round_mx_rows(u, fmt, 8) @ round_mx_rows(W, fmt, 8).T
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+        # MXFP8 regroups these 24 columns under a shift of 4 positions (a shift of 8 keeps
+        # the groups; MXFP4 groups by 4-position group within 128, which a shift only
+        # relabels); columns of very different size make the grouping visible
+        v = u * np.where(np.arange(24) < 4, 100.0, 1.0)
+        same = np.array_equal(round_mx_rows(v, fmt, 4), round_mx_rows(v, fmt, 0))
+        assert same == (fmt == "mxfp4")
+    seen = []
+    real = ot._round_acts
+
+    def spy(u_, mode, k_offset=0):
+        seen.append((u_.shape[1], k_offset))
+        return real(u_, mode, k_offset)
+    monkeypatch.setattr(ot, "_round_acts", spy)
+    from paper_2510_19689_amd import synth
+    p, X = synth.workload("hr35", rows=3)
+    ot.forward(p, X, weights="mxfp8", acts="mxfp8")
+    cfg = p["config"]
+    assert (cfg.n_a, cfg.n_d % 16) in seen and all(o == 0 for k, o in seen if k != cfg.n_a)
