@@ -22,6 +22,12 @@ uint16_t tabnet_hook_bf16_bits(double x);
 /* float8 E4M3FN bits of x, round to nearest even, saturating at +-448. */
 uint8_t tabnet_hook_e4m3_bits(double x);
 
+/* FP4 E2M1 bits (sign in bit 3) of x, round to nearest even, saturating at +-6. */
+uint8_t tabnet_hook_e2m1_bits(double x);
+/* OCP MX shared exponent of a block with largest magnitude amax for an element format
+ * with largest exponent emax: floor(log2 amax) - emax, clamped to [-126, 127]; 0 for 0. */
+int tabnet_hook_mx_exponent(double amax, int emax);
+
 /* The load-time INT8 coding of a weight matrix W [rows][cols] (row-major, caller-owned):
  * per row, scale = max_k |W_k| / 127 (1 for a zero row) into scales[row], and W_k
  * replaced in place by round(W_k / scale) (ties to even), as TABNET_INT8 packs it. */

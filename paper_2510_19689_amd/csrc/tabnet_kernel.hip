@@ -8,6 +8,7 @@ namespace tabnet {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kSqrtHalf = 0.70710678118654752f;
@@ -182,11 +183,148 @@ struct BOp<3, KT, R> {
   }
 };
 
+// OCP MX shared exponent of a block whose largest magnitude is amax: floor(log2 amax)
+// minus the element format's emax, clamped to [-126, 127] (0 for a block of zeros).
+template <int EMAX>
+__device__ __forceinline__ int mx_exponent(float amax) {
+  const int X = __builtin_amdgcn_frexp_expf(amax) - 1 - EMAX;   // amax = m 2^e, m in [0.5, 1)
+  return amax > 0.f ? (X < -126 ? -126 : (X > 127 ? 127 : X)) : 0;
+}
+
+// MXFP8: per row block and k-block (eight K tiles), 32 E4M3 elements (element 4 tt + i =
+// feature 16 (8 kb + tt) + 4 g + i, four to a dword) and the E8M0 scale this lane
+// supplies to the instruction.  Tiles 0-3 of the k-block form, with the partner lane
+// group (g ^ 1), block g / 2; tiles 4-7 block 2 + g / 2.  The instruction reads block b's
+// scale from lane group b: groups 0 and 3 own the blocks they supply, group 1 supplies
+// block 1 (tiles 0-3 of groups 2 and 3) and group 2 block 2 (tiles 4-7 of groups 0 and
+// 1), each received from the lane 32 away.  Elements are v / 2^X, clamped to +-448 and
+// rounded to nearest even.
+template <int KT, int R>
+struct BOp<4, KT, R> {
+  static constexpr int KB = kblocks(4, KT);
+  uint32_t v[R][KB][8];
+  uint32_t sc[R][KB];
+  template <class F>
+  __device__ __forceinline__ void build(F src) {
+    const int g = ((int)threadIdx.x >> 4) & 3;
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        float a[2] = {0.f, 0.f};
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt)
+          if (8 * kb + tt < KT)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[tt >> 2] = fmaxf(a[tt >> 2], fabsf(src(rb, 8 * kb + tt, i)));
+        int X[2];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) X[hf] = mx_exponent<8>(pair16_max(a[hf]));
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt) {
+          const int t = 8 * kb + tt;
+          if (t < KT) {
+            const float scale = __builtin_amdgcn_ldexpf(1.0f, X[tt >> 2]);
+            const float lim = 448.0f * scale;
+            float c[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_fmed3f(src(rb, t, i), -lim, lim);
+            typedef short sh2 __attribute__((ext_vector_type(2)));
+            sh2 w = {0, 0};
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[0], c[1], scale, false);
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[2], c[3], scale, true);
+            v[rb][kb][tt] = __builtin_bit_cast(uint32_t, w);
+          } else {
+            v[rb][kb][tt] = 0u;
+          }
+        }
+        const int e0 = X[0] + 127, e1 = X[1] + 127;
+        const int send = g == 3 ? e0 : e1;
+        const auto r = __builtin_amdgcn_permlane32_swap((unsigned)send, (unsigned)send, false, false);
+        const int recv = (int)((threadIdx.x & 32) ? r[0] : r[1]);
+        sc[rb][kb] = (uint32_t)(g == 0 ? e0 : (g == 3 ? e1 : recv));
+      }
+  }
+};
+
+// MXFP4: per row block and k-block, 32 E2M1 elements (element 4 tt + i in nibble
+// 4 tt + i, eight to a dword) forming one block, the lane's own, with its E8M0 scale.
+// Elements are v / 2^X rounded to nearest even, saturating at +-6.
+template <int KT, int R>
+struct BOp<5, KT, R> {
+  static constexpr int KB = kblocks(5, KT);
+  uint32_t v[R][KB][4];
+  uint32_t sc[R][KB];
+  template <class F>
+  __device__ __forceinline__ void build(F src) {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt)
+          if (8 * kb + tt < KT)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (i & 1) m1 = fmaxf(m1, fabsf(src(rb, 8 * kb + tt, i)));
+              else m0 = fmaxf(m0, fabsf(src(rb, 8 * kb + tt, i)));
+            }
+        const int X = mx_exponent<2>(fmaxf(m0, m1));
+        const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          // byte 2 k + p of the dword holds elements 8 d + 4 k + 2 p (low nibble) and + 1,
+          // tile t = 8 kb + 2 d + k
+          const int t0 = 8 * kb + 2 * d, t1 = t0 + 1;
+          uint32_t w = 0u;
+          if (t0 < KT) {
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t0, 0), src(rb, t0, 1), scale, 0);
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t0, 2), src(rb, t0, 3), scale, 1);
+          }
+          if (t1 < KT) {
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t1, 0), src(rb, t1, 1), scale, 2);
+            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t1, 2), src(rb, t1, 3), scale, 3);
+          }
+          v[rb][kb][d] = w;
+        }
+        sc[rb][kb] = (uint32_t)(X + 127);
+      }
+  }
+};
+
+// acc[rb] += W(one output tile, all K) * B[rb] with both operands in an MX format: one
+// 16x16x128 scaled MFMA per k-block, the block scales applied inside the instruction.
+template <int PREC, int KT, int R>
+__device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<PREC, KT, R>& b, f4 (&acc)[R],
+                                            int lane) {
+  constexpr int KB = kblocks(PREC, KT);
+  constexpr int FMT = PREC == 4 ? 0 : 4;              // E4M3 or E2M1 elements
+  constexpr int EL = PREC == 4 ? 2 * kFrag : kFrag;   // element bytes per k-block
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const unsigned char* f = fr + kb * kbytes(PREC);
+    const i4 lo = *reinterpret_cast<const i4*>(f + lane * 16);
+    i4 hi = {0, 0, 0, 0};
+    if constexpr (PREC == 4) hi = *reinterpret_cast<const i4*>(f + kFrag + lane * 16);
+    const i8v a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    const int sa = *reinterpret_cast<const int*>(f + EL + lane * 4);
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+      i8v bb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bb[j] = (PREC == 4 || j < 4) ? (int)b.v[rb][kb][PREC == 4 ? j : (j & 3)] : 0;
+      acc[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bb, acc[rb], FMT, FMT, 0, sa, 0,
+                                                                 (int)b.sc[rb][kb]);
+    }
+  }
+}
+
 // Fill a GEMM's B operand from src(rb, t, i), the input of row block rb at the lane's
 // feature 16 t + 4 g + i.
 template <int PREC, int KT, int R, class F>
 __device__ __forceinline__ void build_b(BOp<PREC, KT, R>& b, F src) {
-  if constexpr (PREC == 3) {
+  if constexpr (PREC >= 3) {
     b.build(src);
   } else {
 #pragma unroll
@@ -226,7 +364,9 @@ __device__ __forceinline__ void mma_tile_i8(const unsigned char* fr, const BOp<3
 template <int PREC, int KT, int R>
 __device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC, KT, R>& b,
                                          f4 (&acc)[R], int lane) {
-  if constexpr (PREC == 0) {
+  if constexpr (PREC >= 4) {
+    mma_tile_mx<PREC, KT, R>(fr, b, acc, lane);
+  } else if constexpr (PREC == 0) {
 #pragma unroll
     for (int kt = 0; kt < KT; ++kt) {
       const f4 a = *reinterpret_cast<const f4*>(fr + kt * kFrag + lane * 16);
@@ -346,8 +486,8 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
       const int mt = c * UPC + u;
       if (mt < NT) {
         const unsigned char* unit = buf + u * UNIT;
-        const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 16 * g);
-        const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 64 + 16 * g);
+        const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 16 * g);
+        const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 64 + 16 * g);
         if constexpr (PREC == 3) {
           // integer products, dequantised by (channel scale) x (row step); the gate's shift
           // and scale carry the factor -log2(e) of the sigmoid's exponent
@@ -355,9 +495,9 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
 #pragma unroll
           for (int rb = 0; rb < R; ++rb) { qv[rb] = i4{0, 0, 0, 0}; qg[rb] = i4{0, 0, 0, 0}; }
           mma_tile_i8<KT, R>(unit, b, qv, lane);
-          mma_tile_i8<KT, R>(unit + KB * kFrag, b, qg, lane);
-          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 128 + 16 * g);
-          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 192 + 16 * g);
+          mma_tile_i8<KT, R>(unit + KB * kbytes(PREC), b, qg, lane);
+          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 128 + 16 * g);
+          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 192 + 16 * g);
 #pragma unroll
           for (int rb = 0; rb < R; ++rb)
 #pragma unroll
@@ -372,11 +512,11 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
         mma_tile<PREC, KT, R>(unit, b, av, lane);
-        mma_tile<PREC, KT, R>(unit + KB * kFrag, b, ag, lane);
+        mma_tile<PREC, KT, R>(unit + KB * kbytes(PREC), b, ag, lane);
         if constexpr (PREC == 2) {
           // per-channel dequantisation: the shifts were stored divided by the scale
-          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 128 + 16 * g);
-          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kFrag + 192 + 16 * g);
+          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 128 + 16 * g);
+          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 192 + 16 * g);
 #pragma unroll
           for (int rb = 0; rb < R; ++rb)
 #pragma unroll
@@ -608,12 +748,12 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     // ---- attentive transformer: z = P * (a W_att'^T + b_att') ----
     {
       BOp<PREC, KTA, R> ba;
-      // the attention half a = h[n_d, N): INT8 takes its row step over those channels only
-      // (the weights of the other channels in these tiles are zero)
+      // the attention half a = h[n_d, N): INT8 and MX take their scales over those channels
+      // only (the weights of the other channels in these tiles are zero)
       const int n_att_end = n_d + A.n_a;
       build_b(ba, [&](int rb, int t, int i) {
         const int ch = 16 * (KA0 + t) + 4 * g + i;
-        return PREC != 3 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
+        return PREC < 3 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
       });
       constexpr int KBA = kblocks(PREC, KTA);
 #pragma unroll
@@ -625,13 +765,13 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           const int mt = c * PL.att.upc + u;
           if (mt < DT) {
             const unsigned char* unit = buf + u * PL.att.unit;
-            const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
+            const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 16 * g);
             if constexpr (PREC == 3) {
               i4 qa[R];
 #pragma unroll
               for (int rb = 0; rb < R; ++rb) qa[rb] = i4{0, 0, 0, 0};
               mma_tile_i8<KTA, R>(unit, ba, qa, lane);
-              const f4 scl = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
+              const f4 scl = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 64 + 16 * g);
 #pragma unroll
               for (int rb = 0; rb < R; ++rb)
 #pragma unroll
@@ -645,7 +785,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
             for (int rb = 0; rb < R; ++rb) za[rb] = bv;
             mma_tile<PREC, KTA, R>(unit, ba, za, lane);
             f4 scl = {1.f, 1.f, 1.f, 1.f};
-            if constexpr (PREC == 2) scl = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
+            if constexpr (PREC == 2) scl = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 64 + 16 * g);
 #pragma unroll
             for (int rb = 0; rb < R; ++rb)
 #pragma unroll
@@ -1337,6 +1477,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
+                                       TABNET_SHAPES(4) TABNET_SHAPES(5)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
 

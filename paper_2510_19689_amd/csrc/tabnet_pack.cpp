@@ -251,6 +251,28 @@ void quantize_rows_int8(std::vector<double>* Wf, std::vector<double>* bf, int ro
   }
 }
 
+// FP4 E2M1 bits (sign in bit 3) of x, round to nearest even, saturating at +-6.  The grid
+// is 0, 0.5, 1, 1.5 (step 0.5), 2, 3 (step 1), 4, 6 (step 2); within each step range the
+// code is the rounded multiple plus an offset of the same parity, so ties to the even
+// multiple are ties to the even code.
+uint8_t e2m1_bits_rne(double x) {
+  const uint8_t sign = std::signbit(x) ? 8 : 0;
+  const double a = std::fabs(x);
+  if (std::isnan(x)) return 7;
+  int code;
+  if (a < 2.0) code = (int)std::nearbyint(2.0 * a);             // 0 .. 4 (4 = 2.0)
+  else if (a < 4.0) code = (int)std::nearbyint(a) + 2;          // 4 .. 6 (6 = 4.0)
+  else code = std::min(7, (int)std::nearbyint(a / 2.0) + 4);    // 6, 7, saturating
+  return sign | (uint8_t)code;
+}
+
+int mx_exponent(double amax, int emax) {
+  if (!(amax > 0)) return 0;
+  int e;
+  std::frexp(amax, &e);   // amax = m 2^e, m in [0.5, 1): floor(log2 amax) = e - 1
+  return std::max(-126, std::min(127, e - 1 - emax));
+}
+
 // ---------------------------------------------------------------- packing
 Shape shape_of(const tabnet_config& c) {
   Shape s;
@@ -290,6 +312,57 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         for (int r = 0; r < 4; ++r) v[r] = (float)wv(i, 16 * kt + 4 * q + r);
         emit(wts, v, sizeof v);
       }
+  } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP4) {
+    // Per k-block of eight K tiles: the E8M0 exponent of each of an output row's four
+    // blocks, then the elements lane by lane, then the scale each lane supplies (the
+    // instruction takes block b's scale from lane group b).
+    const bool f8 = precision == TABNET_MXFP8;
+    const int KB = (KT + 7) / 8;
+    auto block_of = [&](int tt, int q) { return f8 ? q / 2 + 2 * (tt / 4) : q; };
+    auto val = [&](int i, int kb, int tt, int q, int j) {
+      const int t = 8 * kb + tt;
+      return t < KT ? wv(i, 16 * t + 4 * q + j) : 0.0;
+    };
+    for (int kb = kb_lo; kb < (kb_hi < 0 ? KB : kb_hi); ++kb) {
+      int X[16][4];
+      for (int i = 0; i < 16; ++i) {
+        double amax[4] = {0, 0, 0, 0};
+        for (int tt = 0; tt < 8; ++tt)
+          for (int q = 0; q < 4; ++q)
+            for (int j = 0; j < 4; ++j) {
+              double& a = amax[block_of(tt, q)];
+              a = std::fmax(a, std::fabs(val(i, kb, tt, q, j)));
+            }
+        for (int b = 0; b < 4; ++b) X[i][b] = mx_exponent(amax[b], f8 ? 8 : 2);
+      }
+      if (f8) {
+        for (int half = 0; half < 2; ++half)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int i = lane & 15, q = lane >> 4;
+            uint8_t v[16];
+            for (int e = 16 * half; e < 16 * half + 16; ++e) {
+              const int tt = e / 4, j = e % 4;
+              v[e - 16 * half] = e4m3_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][block_of(tt, q)]));
+            }
+            emit(wts, v, sizeof v);
+          }
+      } else {
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane & 15, q = lane >> 4;
+          uint8_t v[16] = {};
+          for (int e = 0; e < 32; ++e) {
+            const int tt = e / 4, j = e % 4;
+            const uint8_t c = e2m1_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
+            v[e / 2] |= (uint8_t)(c << (4 * (e & 1)));
+          }
+          emit(wts, v, sizeof v);
+        }
+      }
+      for (int lane = 0; lane < 64; ++lane) {
+        const uint32_t sc = (uint32_t)(X[lane & 15][lane >> 4] + 127);
+        emit(wts, &sc, sizeof sc);
+      }
+    }
   } else if (precision == TABNET_INT8) {
     const int KQ = (KT + 3) / 4;   // missing tiles of the last block are zeros
     for (int kb = kb_lo; kb < (kb_hi < 0 ? KQ : kb_hi); ++kb)

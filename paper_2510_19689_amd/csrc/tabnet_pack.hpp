@@ -41,6 +41,10 @@ void fold_layer(const LayerRaw& L, double eps, std::vector<double>* Wf, std::vec
 // Round-to-nearest-even of a double onto bfloat16 / E4M3FN (saturating at 448), as bits.
 uint16_t bf16_bits_rne(double x);
 uint8_t e4m3_bits_rne(double x);
+// FP4 E2M1 bits of a double (round to nearest even, saturating at +-6), and the OCP MX
+// shared exponent floor(log2 amax) - emax clamped to [-126, 127] (0 for amax = 0).
+uint8_t e2m1_bits_rne(double x);
+int mx_exponent(double amax, int emax);
 double bf16_value(uint16_t bits);
 double e4m3_value(uint8_t bits);
 

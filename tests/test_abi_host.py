@@ -114,6 +114,20 @@ def test_rounding_hooks_match_torch(L):
     assert L.tabnet_hook_e4m3_bits(1000.0) == 0x7E and L.tabnet_hook_e4m3_bits(-1000.0) == 0xFE
 
 
+def test_mx_encoders_match_oracle(L):
+    """The packer's E2M1 encoder and MX exponent rule against the oracle's."""
+    from oracle.rounding import mx_scale_exponent, round_e2m1
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.uniform(-8, 8, 3000), np.arange(-7, 7.01, 0.25), [0.0, -0.0, 100.0, -1e-3]])
+    table = [(-1.0 if c & 8 else 1.0) * [0, 0.5, 1, 1.5, 2, 3, 4, 6][c & 7] for c in range(16)]
+    got = np.array([table[L.tabnet_hook_e2m1_bits(float(v))] for v in x])
+    np.testing.assert_array_equal(got, round_e2m1(x))
+    amax = np.concatenate([np.abs(rng.normal(0, 10, 2000)), [0.0, 1.0, 448.0, 2.0 ** -140, 3e38]])
+    for fmt, emax in (("mxfp8", 8), ("mxfp4", 2)):
+        got = np.array([L.tabnet_hook_mx_exponent(float(a), emax) for a in amax])
+        np.testing.assert_array_equal(got, mx_scale_exponent(amax, fmt))
+
+
 def test_int8_weight_coding_matches_oracle(L):
     """The packer's INT8 coding of folded weights is the oracle's, code for code."""
     from oracle.rounding import quantise_int8_rows
@@ -167,15 +181,16 @@ def test_packed_sizes(L):
         target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in (0, 1, 2, 3):
-            per = {0: 1, 1: 2, 2: 2, 3: 4}[prec]     # K tiles per fragment (INT8: four)
-            kb = (lambda KT, per=per: cdiv(KT, per))
-            ex = 2 if prec >= 2 else 1          # E4M3 and INT8 units also carry one scale per output
-            glu_unit = {k: 2 * kb(cdiv(k, 16)) * 1024 + 128 * ex for k in set(ks)}
-            att_unit = kb(NT - KA0) * 1024 + 64 * ex
+        for prec in (0, 1, 2, 3, 4, 5):
+            per = {0: 1, 1: 2, 2: 2, 3: 4, 4: 8, 5: 8}[prec]     # K tiles per k-block
+            kbb = {4: 2 * 1024 + 256, 5: 1024 + 256}.get(prec, 1024)   # MX: elements + 64 scale dwords
+            kbytes = (lambda KT, per=per, kbb=kbb: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
+            ex = 2 if prec in (2, 3) else 1     # E4M3 and INT8 units also carry one scale per output
+            glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}
+            att_unit = kbytes(NT - KA0) + 64 * ex
             exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
-            first = chunks(2 * kb(DT) * 1024 + 128 * ex, NT, target)
-            mid = chunks(2 * kb(NT) * 1024 + 128 * ex, NT, target)
+            first = chunks(2 * kbytes(DT) + 128 * ex, NT, target)
+            mid = chunks(2 * kbytes(NT) + 128 * ex, NT, target)
             nl = cfg.n_shared + cfg.n_indep
             exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT, target)
             wb, nch = ctypes.c_int64(), ctypes.c_int64()

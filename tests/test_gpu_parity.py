@@ -242,7 +242,11 @@ def test_fp8_weights_parity(tmp_path, name, B):
 
 
 def check_int8(got, params, X, tag):
-    """INT8 against FP64 on the same INT8 operands, row by row.
+    check_rows_on_rounded(got, params, X, "int8", tag, worst=(2.5e-2, 1e-2, 2e-3))
+
+
+def check_rows_on_rounded(got, params, X, fmt, tag, worst, typical=(0.9, 1e-5)):
+    """A quantised path against FP64 on the same quantised operands, row by row.
 
     The kernel forms its GEMM inputs in FP32; where such an input lands on the other side
     of a rounding boundary than its FP64 value, its code moves by one, which moves that
@@ -250,20 +254,24 @@ def check_int8(got, params, X, tag):
     rounding error, carried through the later layers and the sparsemax.  An FP32/FP64
     difference of ~1e-7 of a step makes such flips rare, so most rows agree to FP32
     rounding and a few rows move by a fraction of what INT8 itself moves them from FP64.
-    Gates: at least 90 % of rows within 1e-5 (step-mask L1) and 1e-5 (logits); every row
-    within 2.5e-2 (step L1), 1e-2 (aggregate L1) and 2e-3 (logits).  A wrong index, scale
-    or code in the kernel moves every row, not a few."""
+    Gates: a share `typical` = (fraction, bound) of rows within the bound (step-mask L1 and
+    logits), by default 90 % within 1e-5; every row within `worst` = (step L1, aggregate
+    L1, logits), for INT8 2.5e-2, 1e-2 and 2e-3.  A wrong index, scale or code in the
+    kernel moves every row by far more, not a few rows.  (MX formats: a flip is rarer,
+    since the FP32/FP64 difference must cross an element boundary of a grid 2^-3 (E4M3)
+    or 2^-1 (E2M1) wide relative to the value, but larger.)"""
     lo, ag, ms = got
-    rlo, rag, rms = oracle.forward(params, X, weights="int8", acts="int8")
+    rlo, rag, rms = oracle.forward(params, X, weights=fmt, acts=fmt)
     step = np.abs(ms - rms).sum(-1).max(0)
     agg = np.abs(ag - rag).sum(-1)
     logit = np.abs(lo - rlo).max(1)
     q = lambda v: [float(np.percentile(v, p)) for p in (50, 90, 99, 100)]
-    _say(tag, "vs int8-operand fp64 per row p50/p90/p99/max: step L1", q(step), "agg L1", q(agg), "logits", q(logit),
+    _say(tag, f"vs {fmt}-operand fp64 per row p50/p90/p99/max: step L1", q(step), "agg L1", q(agg), "logits", q(logit),
          "rows moved:", float((step > 1e-5).mean()))
     assert np.isfinite(lo).all() and np.isfinite(ag).all()
-    assert (step <= 1e-5).mean() >= 0.9 and (logit <= 1e-5).mean() >= 0.9
-    assert step.max() <= 2.5e-2 and agg.max() <= 1e-2 and logit.max() <= 2e-3
+    frac, bound = typical
+    assert (step <= bound).mean() >= frac and (logit <= bound).mean() >= frac
+    assert step.max() <= worst[0] and agg.max() <= worst[1] and logit.max() <= worst[2]
 
 
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
@@ -295,3 +303,55 @@ def test_int8_unsupported_shape_and_round_trip(tmp_path):
     params, X = synth.workload("hr35", rows=40)
     with load(params, tmp_path, "int8") as m:
         assert tb.lib().tabnet_get_precision(m._h) == tb.INT8
+
+
+# Against plain FP64 the MX formats' own error decides: the oracle on MX operands differs
+# from plain FP64 by up to (logits, aggregate L1, step L1) = (1.2e-2, 0.22, 0.31) in MXFP8
+# and (3.3e-2, 0.45, 0.86) in MXFP4 on these rows, with argmax unchanged; the gates leave
+# a quarter more.  Per row against the same MX operands: flips of an E2M1 element move a
+# value by up to a third, hence the wider worst-row bounds for MXFP4.  The E4M3 form of
+# the scaled MFMA does not sum its products exactly in FP32: on known operands it
+# differs from the exact dot product by up to 5.2e-6 of sum |a_k b_k| (the E2M1 form is
+# exact), so every MXFP8 GEMM output carries an error of that order and the typical
+# MXFP8 row moves by ~1e-5; its typical-row gate is the median row within 1e-4.
+MX_GATES = {"mxfp8": dict(fp64=(1.5e-2, 0.28, 0.4), worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4)),
+            "mxfp4": dict(fp64=(4.2e-2, 0.56, 1.08), worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5))}
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
+def test_mx_parity(tmp_path, name, B, fmt):
+    """OCP MX formats on both GEMM operands (E8M0 block scales applied by the scaled MFMA)."""
+    params, X = synth.workload(name, rows=B)
+    _say(f"case {fmt} {name} B={B}")
+    with load(params, tmp_path, fmt) as m:
+        got = run(m, X)
+    gates = MX_GATES[fmt]
+    check_rows_on_rounded(got, params, X, fmt, f"{fmt} {name}", worst=gates["worst"], typical=gates["typical"])
+    e = errs(got, oracle.forward(params, X))
+    _say(f"{fmt} {name} vs fp64", e)
+    lo_t, agg_t, step_t = gates["fp64"]
+    assert e["logit_abs"] <= lo_t and e["agg_l1"] <= agg_t and e["step_l1"] <= step_t, e
+    assert e["argmax"] >= 0.995, e
+    lo, ag, ms = got
+    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=2e-5)
+    np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
+
+
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
+    params, X = synth.workload("adult108", rows=300)
+    _say(f"case {fmt} row independence")
+    with load(params, tmp_path, fmt) as m:
+        full = run(m, X)
+        for lo_, hi_ in ((0, 1), (17, 83), (299, 300)):
+            part = run(m, X[lo_:hi_])
+            for u, v in zip(part[:2], full[:2]):
+                np.testing.assert_array_equal(u, v[lo_:hi_])
+            np.testing.assert_array_equal(part[2], full[2][:, lo_:hi_])
+    cfg = synth.WORKLOADS["wide512"]["cfg"]
+    path = str(tmp_path / "w.tnw")
+    synth.write_weights(synth.make_params(cfg, 3), path)
+    with pytest.raises(tb.TabNetError) as ei:
+        tb.Model(path, fmt)
+    assert ei.value.status == tb.E_UNSUPPORTED
