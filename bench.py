@@ -313,7 +313,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=2000,
+                    help="untimed launches first (~0.2 s at the default workload: the GPU reaches its "
+                         "steady clock within that)")
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")

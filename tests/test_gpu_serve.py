@@ -82,6 +82,38 @@ def test_mix_equals_alone(models, use_graph):
             assert np.abs(ag[:64] - rag).sum(-1).max() <= 1e-2
 
 
+@pytest.mark.parametrize("prec_a,prec_h", [("int8", "mxfp4"), ("mxfp8", "int8")])
+def test_mix_quantised_equals_alone(models, prec_a, prec_h):
+    """Quantised models (INT8, MX) served together: each request's outputs are those of the
+    model's own forward of that request alone, bit for bit (the row coding is per row)."""
+    _, path_a = models["adult108"]
+    _, path_h = models["hr35"]
+    _say(f"case serve quantised mix {prec_a} + {prec_h}")
+    with tb.Model(path_a, prec_a) as ma, tb.Model(path_h, prec_h) as mh:
+        cfgs = [ma.config, mh.config]
+        rng = np.random.default_rng(11)
+        pools = [synth.make_inputs("adult", 8000, 81), synth.make_inputs("hr", 3000, 82)]
+        reqs = []
+        with tb.Server([ma, mh], max_rows_per_launch=2048, slots=2, with_step_masks=True, use_graph=True) as s:
+            for k in range(40):
+                m = k % 2
+                rows = int(min(np.floor(np.exp(rng.uniform(0, np.log(3001)))), 3000))
+                off = int(rng.integers(0, pools[m].shape[0] - rows))
+                X = np.ascontiguousarray(pools[m][off:off + rows])
+                c = cfgs[m]
+                lo = np.full((rows, c.n_out), np.nan, np.float32)
+                ag = np.full((rows, c.D), np.nan, np.float32)
+                ms = np.full((c.n_steps, rows, c.D), np.nan, np.float32)
+                reqs.append((m, X, lo, ag, ms, s.submit(m, X, lo, ag, ms)))
+            for r in reqs:
+                assert s.wait(r[5]) == tb.OK
+        for m, X, lo, ag, ms, _ in reqs:
+            a_lo, a_ag, a_ms = alone(ma if m == 0 else mh, X)
+            np.testing.assert_array_equal(lo, a_lo)
+            np.testing.assert_array_equal(ag, a_ag)
+            np.testing.assert_array_equal(ms, a_ms)
+
+
 def test_serve_without_step_masks_and_tiny_requests(models):
     _, path_a = models["adult108"]
     _say("case serve tiny requests")
