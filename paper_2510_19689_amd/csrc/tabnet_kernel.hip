@@ -901,11 +901,19 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) {
           float* sr = stage + (16 * rb + rl) * D + 4 * g;
+          if (vec4) {
+            // D % 4 == 0: a lane's four features are 16-byte aligned and all real or all padding
 #pragma unroll
-          for (int t = 0; t < DT; ++t)
+            for (int t = 0; t < DT; ++t)
+              if (feat_ok(t, 0))
+                *reinterpret_cast<f4*>(sr + 16 * t) = f4{M[rb][t][0], M[rb][t][1], M[rb][t][2], M[rb][t][3]};
+          } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
+            for (int t = 0; t < DT; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (feat_ok(t, i)) sr[16 * t + i] = M[rb][t][i];
+          }
         }
         lds_wave_sync();
         stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * D, live_rows * D, lane);
@@ -973,11 +981,19 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       reduce_columns<DT>(agg[rb], A.colbits, C, stage + 16 * rb * C, lane);
     } else {
       float* sr = stage + (16 * rb + rl) * D + 4 * g;
+      if (vec4) {
 #pragma unroll
-      for (int t = 0; t < DT; ++t)
+        for (int t = 0; t < DT; ++t)
+          if (feat_ok(t, 0))
+            *reinterpret_cast<f4*>(sr + 16 * t) =
+                f4{agg[rb][t][0] * inv, agg[rb][t][1] * inv, agg[rb][t][2] * inv, agg[rb][t][3] * inv};
+      } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (feat_ok(t, i)) sr[16 * t + i] = agg[rb][t][i] * inv;
+        for (int t = 0; t < DT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (feat_ok(t, i)) sr[16 * t + i] = agg[rb][t][i] * inv;
+      }
     }
   }
   lds_wave_sync();
