@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--quant", default="fp8,int8,mxfp8,mxfp4",
-                    help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights; int8: "
+                    help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights and GEMM inputs; int8: "
                          "INT8 weights and GEMM inputs; mxfp8 / mxfp4: OCP MX on both GEMM operands); "
                          "empty to skip")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
@@ -467,7 +467,8 @@ def main():
         out["bf16_over_fp32"] = t32 / t_bf16
         out["fp32_mfma_frac"] = flops / (t32 / args.steps) / 1e12 / FP32_MFMA_PEAK_TFLOPS
     quant = {}
-    for prec, what in (("fp8", "E4M3 weights (one scale per output channel), BF16 GEMM inputs"),
+    for prec, what in (("fp8", "E4M3 weights (one scale per output channel) and GEMM inputs (one scale per "
+                                "row), FP8 MFMA"),
                        ("int8", "INT8 weights (one scale per output channel) and GEMM inputs (one step "
                                 "per row), INT32 products"),
                        ("mxfp8", "OCP MXFP8 (E4M3 elements, E8M0 scale per 32) on both GEMM operands, "

@@ -45,7 +45,7 @@ typedef enum {
 typedef enum {
     TABNET_FP32 = 0,      /* FP32 MFMA GEMMs, FP32 everything                            */
     TABNET_BF16 = 1,      /* BF16 GEMM operands (RNE), FP32 accumulate and epilogues      */
-    TABNET_FP8_E4M3 = 2,  /* E4M3 weights with one scale per output channel; see below   */
+    TABNET_FP8_E4M3 = 2,  /* E4M3 weights and GEMM inputs, one scale per row; see below  */
     TABNET_INT8 = 3,      /* INT8 weights and GEMM inputs, INT32 products; see below      */
     TABNET_MXFP8 = 4,     /* OCP MX: E4M3 elements in blocks of 32 with E8M0 scales       */
     TABNET_MXFP4 = 5      /* OCP MX: E2M1 elements in blocks of 32 with E8M0 scales       */
@@ -84,10 +84,12 @@ typedef struct tabnet_handle tabnet_handle;
  * fields out of range, e.g. n_d < 1 or gamma < 1), TABNET_E_UNSUPPORTED (no compiled
  * kernel covers D, n_d + n_a or n_out), TABNET_E_OOM, TABNET_E_HIP.
  *
- * TABNET_FP8_E4M3 stores each GEMM weight row as E4M3 values q with one FP32 scale
- * sigma_n = max_k |W'_nk| / 448, and feeds the GEMMs BF16 activations (the weights are
- * widened to BF16 exactly on the way into the matrix cores); accumulation, the GLU and
- * residual epilogues, the prior, sparsemax and aggregation stay in FP32.
+ * TABNET_FP8_E4M3 puts both operands of every GEMM in E4M3 with one FP32 scale per
+ * vector: each weight row as q = E4M3(W'_n / sigma_n) with sigma_n = max_k |W'_nk| / 448,
+ * and each GEMM input row (coded in the kernel) as E4M3(u / s_r) with s_r = max_k |u_k| / 448,
+ * both rounded to nearest even.  The FP8 matrix instruction sums the products in FP32,
+ * dequantised by sigma_n * s_r before the folded shift is added; the GLU and residual
+ * epilogues, the prior, sparsemax and aggregation stay in FP32.
  *
  * TABNET_INT8 is the paper's FP32-to-INT8 quantisation (Sec. VI-D) in symmetric form:
  * each GEMM weight row is stored as integer codes in [-127, 127] with one FP32 scale
@@ -97,9 +99,9 @@ typedef struct tabnet_handle tabnet_handle;
  * products are exact INT32 sums on the integer matrix cores, dequantised by
  * sigma_n * step before the folded shift is added; everything else stays in FP32.
  * A row that holds a non-finite value gets unspecified outputs (other rows are not
- * affected).  INT8 has entries for the register-resident kernel shapes only: a model
- * served by the split-feature kernel (the 512-feature shape) is TABNET_E_UNSUPPORTED in
- * INT8.
+ * affected).  E4M3 and INT8 have entries for the register-resident kernel shapes only: a
+ * model served by the split-feature kernel (the 512-feature shape) is TABNET_E_UNSUPPORTED
+ * in these formats.
  *
  * TABNET_MXFP8 / TABNET_MXFP4 put both operands of every GEMM in an OCP microscaling
  * format: along K, blocks of 32 values share one power-of-two scale 2^X (E8M0) with

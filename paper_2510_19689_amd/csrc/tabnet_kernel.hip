@@ -140,8 +140,38 @@ struct BOp<1, KT, R> {        // BF16: two packed dwords per tile
   }
 };
 
+// E4M3 (the FP8 path): one scale per row, s = max_k |u_k| / 448, elements u_k / s rounded
+// to nearest even in E4M3, four to a dword (feature 16 t + 4 g + i in byte i).  The
+// largest element maps to 448 (|u * 448 / max| <= 448 (1 + 2^-23) rounds to 448), so no
+// element leaves the E4M3 range.
 template <int KT, int R>
-struct BOp<2, KT, R> : BOp<1, KT, R> {};   // E4M3 weights: BF16 activations
+struct BOp<2, KT, R> {
+  uint32_t v[R][KT];
+  float s[R];
+  template <class F>
+  __device__ __forceinline__ void build(F src) {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) {
+      float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < KT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i & 1) m1 = fmaxf(m1, fabsf(src(rb, t, i)));
+          else m0 = fmaxf(m0, fabsf(src(rb, t, i)));
+        }
+      const float amax = row_max(fmaxf(m0, m1));
+      s[rb] = amax * (1.0f / 448.0f);
+      const float inv = amax > 0.f ? 448.0f / amax : 0.f;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(src(rb, t, 0) * inv, src(rb, t, 1) * inv, 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(src(rb, t, 2) * inv, src(rb, t, 3) * inv, w, true);
+        v[rb][t] = (uint32_t)w;
+      }
+    }
+  }
+};
 
 // INT8: symmetric codes with one step per row, s = max_k |u_k| / 127, c_k = round(u_k / s)
 // (ties to even), four codes of a tile in one dword (feature 16 t + 4 g + i in byte i).
@@ -324,7 +354,7 @@ __device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<P
 // feature 16 t + 4 g + i.
 template <int PREC, int KT, int R, class F>
 __device__ __forceinline__ void build_b(BOp<PREC, KT, R>& b, F src) {
-  if constexpr (PREC >= 3) {
+  if constexpr (PREC >= 2) {
     b.build(src);
   } else {
 #pragma unroll
@@ -394,6 +424,51 @@ __device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC
         acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[rb], 0, 0, 0);
       }
     }
+  }
+}
+
+// E4M3: acc[rb] += Wq(one output tile, all K) * codes[rb] in FP32; a 1 KiB fragment holds
+// four K tiles, as two 16x16x32 FP8 MFMAs (bytes 0-7 and 8-15 of each lane).
+template <int KT, int R>
+__device__ __forceinline__ void mma_tile_f8(const unsigned char* fr, const BOp<2, KT, R>& b, f4 (&acc)[R],
+                                            int lane) {
+  constexpr int KQ = kblocks(2, KT);
+#pragma unroll
+  for (int kb = 0; kb < KQ; ++kb) {
+    const i4 a = *reinterpret_cast<const i4*>(fr + kb * kFrag + lane * 16);
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      if (4 * kb + 2 * hf < KT) {
+        const long ah = (long)(((uint64_t)(uint32_t)a[2 * hf + 1] << 32) | (uint32_t)a[2 * hf]);
+#pragma unroll
+        for (int rb = 0; rb < R; ++rb) {
+          const int t0 = 4 * kb + 2 * hf, t1 = t0 + 1;
+          const uint32_t lo = b.v[rb][t0 < KT ? t0 : 0];
+          const uint32_t hi = t1 < KT ? b.v[rb][t1 < KT ? t1 : 0] : 0u;
+          const long bh = (long)(((uint64_t)hi << 32) | lo);
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ah, bh, acc[rb], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// Row-coded formats (E4M3, INT8): acc[rb] = Wq(one output tile) * codes[rb] as FP32, before
+// the dequantisation by (channel scale) x (row scale).
+template <int PREC, int KT, int R>
+__device__ __forceinline__ void mma_tile_coded(const unsigned char* fr, const BOp<PREC, KT, R>& b, f4 (&acc)[R],
+                                               int lane) {
+  if constexpr (PREC == 3) {
+    i4 q[R];
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) q[rb] = i4{0, 0, 0, 0};
+    mma_tile_i8<KT, R>(fr, b, q, lane);
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) acc[rb] = f4{(float)q[rb][0], (float)q[rb][1], (float)q[rb][2], (float)q[rb][3]};
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+    mma_tile_f8<KT, R>(fr, b, acc, lane);
   }
 }
 
@@ -488,22 +563,20 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
         const unsigned char* unit = buf + u * UNIT;
         const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 16 * g);
         const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 64 + 16 * g);
-        if constexpr (PREC == 3) {
-          // integer products, dequantised by (channel scale) x (row step); the gate's shift
+        if constexpr (PREC == 2 || PREC == 3) {
+          // products of codes, dequantised by (channel scale) x (row scale); the gate's shift
           // and scale carry the factor -log2(e) of the sigmoid's exponent
-          i4 qv[R], qg[R];
-#pragma unroll
-          for (int rb = 0; rb < R; ++rb) { qv[rb] = i4{0, 0, 0, 0}; qg[rb] = i4{0, 0, 0, 0}; }
-          mma_tile_i8<KT, R>(unit, b, qv, lane);
-          mma_tile_i8<KT, R>(unit + KB * kbytes(PREC), b, qg, lane);
+          f4 qv[R], qg[R];
+          mma_tile_coded<PREC, KT, R>(unit, b, qv, lane);
+          mma_tile_coded<PREC, KT, R>(unit + KB * kbytes(PREC), b, qg, lane);
           const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 128 + 16 * g);
           const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 192 + 16 * g);
 #pragma unroll
           for (int rb = 0; rb < R; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float v = __builtin_fmaf((float)qv[rb][i], sv[i] * b.s[rb], bv[i]);
-              const float e = __builtin_fmaf((float)qg[rb][i], sgt[i] * b.s[rb], bg[i]);
+              const float v = __builtin_fmaf(qv[rb][i], sv[i] * b.s[rb], bv[i]);
+              const float e = __builtin_fmaf(qg[rb][i], sgt[i] * b.s[rb], bg[i]);
               const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(e));
               h[rb][mt][i] = first ? v * sg : __builtin_fmaf(v, sg, h[rb][mt][i]) * kSqrtHalf;
             }
@@ -513,27 +586,13 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
         for (int rb = 0; rb < R; ++rb) { av[rb] = bv; ag[rb] = bg; }
         mma_tile<PREC, KT, R>(unit, b, av, lane);
         mma_tile<PREC, KT, R>(unit + KB * kbytes(PREC), b, ag, lane);
-        if constexpr (PREC == 2) {
-          // per-channel dequantisation: the shifts were stored divided by the scale
-          const f4 sv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 128 + 16 * g);
-          const f4 sgt = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 192 + 16 * g);
 #pragma unroll
-          for (int rb = 0; rb < R; ++rb)
+        for (int rb = 0; rb < R; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(ag[rb][i] * (-kLog2e * sgt[i])));
-              const float v = av[rb][i] * sv[i];
-              h[rb][mt][i] = first ? v * sg : __builtin_fmaf(v, sg, h[rb][mt][i]) * kSqrtHalf;
-            }
-        } else {
-#pragma unroll
-          for (int rb = 0; rb < R; ++rb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float sg = sigmoid_fast(ag[rb][i]);
-              h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
-            }
-        }
+          for (int i = 0; i < 4; ++i) {
+            const float sg = sigmoid_fast(ag[rb][i]);
+            h[rb][mt][i] = first ? av[rb][i] * sg : __builtin_fmaf(av[rb][i], sg, h[rb][mt][i]) * kSqrtHalf;
+          }
         }
       }
     }
@@ -748,12 +807,12 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
     // ---- attentive transformer: z = P * (a W_att'^T + b_att') ----
     {
       BOp<PREC, KTA, R> ba;
-      // the attention half a = h[n_d, N): INT8 and MX take their scales over those channels
-      // only (the weights of the other channels in these tiles are zero)
+      // the attention half a = h[n_d, N): the scaled formats (E4M3, INT8, MX) take their
+      // scales over those channels only (the weights of the other channels here are zero)
       const int n_att_end = n_d + A.n_a;
       build_b(ba, [&](int rb, int t, int i) {
         const int ch = 16 * (KA0 + t) + 4 * g + i;
-        return PREC < 3 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
+        return PREC < 2 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
       });
       constexpr int KBA = kblocks(PREC, KTA);
 #pragma unroll
@@ -766,17 +825,15 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           if (mt < DT) {
             const unsigned char* unit = buf + u * PL.att.unit;
             const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 16 * g);
-            if constexpr (PREC == 3) {
-              i4 qa[R];
-#pragma unroll
-              for (int rb = 0; rb < R; ++rb) qa[rb] = i4{0, 0, 0, 0};
-              mma_tile_i8<KTA, R>(unit, ba, qa, lane);
+            if constexpr (PREC == 2 || PREC == 3) {
+              f4 qa[R];
+              mma_tile_coded<PREC, KTA, R>(unit, ba, qa, lane);
               const f4 scl = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 64 + 16 * g);
 #pragma unroll
               for (int rb = 0; rb < R; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  const float hz = __builtin_fmaf((float)qa[rb][i], scl[i] * ba.s[rb], bv[i]);
+                  const float hz = __builtin_fmaf(qa[rb][i], scl[i] * ba.s[rb], bv[i]);
                   M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
                 }
             } else {
@@ -784,14 +841,11 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
             for (int rb = 0; rb < R; ++rb) za[rb] = bv;
             mma_tile<PREC, KTA, R>(unit, ba, za, lane);
-            f4 scl = {1.f, 1.f, 1.f, 1.f};
-            if constexpr (PREC == 2) scl = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 64 + 16 * g);
 #pragma unroll
             for (int rb = 0; rb < R; ++rb)
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const float hz = PREC == 2 ? za[rb][i] * scl[i] : za[rb][i];
-                M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
+                M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * za[rb][i] : kNegBig;
               }
             }
           }

@@ -39,12 +39,12 @@
 //   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (E4M3, INT8: then [16 scales])
 // A fragment is 64 lanes x 16 bytes: FP32 one per 16-wide K tile (a lane's float4 feeds
 // four 16x16x4 MFMAs), BF16 one per pair of K tiles (8 bf16 per lane, one 16x16x32 MFMA;
-// an odd last tile is paired with zeros), INT8 one per four K tiles (16 codes per lane,
-// one 16x16x64 integer MFMA; missing tiles are zeros).  Shifts are in C-layout order:
-// slot 4 q + i of tile mt is output feature 16 mt + 4 q + i.  In INT8 the gate half's
-// shifts and scales are stored multiplied by -log2(e), the factor of the sigmoid's
-// exponent, and the shifts are not divided by the scales (the integer products are
-// dequantised before the shift is added).
+// an odd last tile is paired with zeros), E4M3 and INT8 one per four K tiles (16 codes per
+// lane: two 16x16x32 FP8 MFMAs, or one 16x16x64 integer MFMA; missing tiles are zeros).
+// Shifts are in C-layout order: slot 4 q + i of tile mt is output feature 16 mt + 4 q + i.
+// In E4M3 and INT8 the gate half's shifts and scales are stored multiplied by -log2(e),
+// the factor of the sigmoid's exponent, and the shifts are not divided by the scales (the
+// products of codes are dequantised before the shift is added).
 // MX formats (OCP microscaling: blocks of 32 K positions share a power-of-two E8M0
 // scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA: MXFP8 packs per
 // k-block [64 lanes x 16 B: E4M3 elements 0-15][64 x 16 B: elements 16-31][64 x 4 B: the
@@ -80,8 +80,8 @@ struct GemmPlan {
   int nchunks;
 };
 
-// K tiles per k-block: 1 (FP32), 2 (BF16 and E4M3 weights), 4 (INT8), 8 (MXFP8, MXFP4)
-constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 3 ? 4 : (prec >= 4 ? 8 : 2)); }
+// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (MXFP8, MXFP4)
+constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 1 ? 2 : (prec <= 3 ? 4 : 8)); }
 constexpr int kblocks(int prec, int KT) {
   return (KT + ktiles_per_block(prec) - 1) / ktiles_per_block(prec);
 }
@@ -90,7 +90,7 @@ constexpr int kMxScaleBytes = 256;
 constexpr int kbytes(int prec) {
   return prec == 4 ? 2 * kFrag + kMxScaleBytes : (prec == 5 ? kFrag + kMxScaleBytes : kFrag);
 }
-// Per-output scales after the shifts (E4M3 weights, INT8)
+// Per-output scales after the shifts (E4M3, INT8)
 constexpr bool has_channel_scales(int prec) { return prec == 2 || prec == 3; }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -128,10 +128,9 @@ struct Plan {
 
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
-// prec: 0 FP32, 1 BF16, 2 E4M3 weights (BF16 fragments holding the E4M3 codes, plus one
-// FP32 scale per output channel after the shifts), 3 INT8 weights and activations (INT8
-// fragments, one FP32 scale per output channel after the shifts), 4 MXFP8 and 5 MXFP4
-// (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
+// prec: 0 FP32, 1 BF16, 2 E4M3 and 3 INT8 weights and activations (codes in the fragments,
+// one FP32 scale per output channel after the shifts, one scale per input row formed in
+// the kernel), 4 MXFP8 and 5 MXFP4 (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
 // KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const int sc = has_channel_scales(prec) ? 2 : 1;   // shifts, or shifts + scales

@@ -363,6 +363,19 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         emit(wts, &sc, sizeof sc);
       }
     }
+  } else if (precision == TABNET_FP8_E4M3) {
+    // Wf holds E4M3 values of W' / s_n; byte j of a lane is tile 4 kb + j / 4
+    const int KQ = (KT + 3) / 4;   // missing tiles of the last block are zeros
+    for (int kb = kb_lo; kb < (kb_hi < 0 ? KQ : kb_hi); ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, q = lane >> 4;
+        uint8_t v[16];
+        for (int j = 0; j < 16; ++j) {
+          const int t = 4 * kb + j / 4;
+          v[j] = e4m3_bits_rne(t < KT ? wv(i, 16 * t + 4 * q + (j & 3)) : 0.0);
+        }
+        emit(wts, v, sizeof v);
+      }
   } else if (precision == TABNET_INT8) {
     const int KQ = (KT + 3) / 4;   // missing tiles of the last block are zeros
     for (int kb = kb_lo; kb < (kb_hi < 0 ? KQ : kb_hi); ++kb)
@@ -400,20 +413,23 @@ void emit_vals(const std::vector<double>& bf, int rows_valid, int first_row, flo
 }
 
 // E4M3 with one scale per output row: s_n = max_k |W'_nk| / 448 (1 for a zero row),
-// Wf <- E4M3(W' / s_n) (exact in BF16), shift <- b' / s_n so that s_n (acc + shift) = y.
-void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int rows, int cols,
+// Wf <- E4M3(W' / s_n) (round to nearest even).  The shift is kept as it is: the kernel adds
+// it after dequantising the products.  Rows [neg_lo, rows) (the gate half of a GLU layer)
+// get their shift and scale multiplied by -log2(e), the factor of the sigmoid's exponent.
+void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int rows, int cols, int neg_lo,
                         std::vector<double>* scale) {
+  const double kNegLog2e = -1.4426950408889634;
   scale->assign(rows, 1.0);
   for (int r = 0; r < rows; ++r) {
     double amax = 0;
     for (int k = 0; k < cols; ++k) amax = std::fmax(amax, std::fabs((*Wf)[(size_t)r * cols + k]));
     const double s = amax > 0 ? amax / 448.0 : 1.0;
-    (*scale)[r] = s;
     for (int k = 0; k < cols; ++k) {
       double& w = (*Wf)[(size_t)r * cols + k];
       w = e4m3_value(e4m3_bits_rne(w / s));
     }
-    (*bf)[r] /= s;
+    (*scale)[r] = r >= neg_lo ? s * kNegLog2e : s;
+    if (r >= neg_lo) (*bf)[r] *= kNegLog2e;
   }
 }
 
@@ -518,7 +534,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
-    if (fp8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, &sc);
+    if (fp8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, N, &sc);     // rows [N, 2N): the gates
     if (i8) quantize_rows_int8(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
     const int KT = (L->cols + 15) / 16;   // the first layer of a pass reads D features, the others N
     const int K = L->cols;
@@ -544,7 +560,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   // attentive layers: unit mt = [fragments over the attention half of h][shifts]
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
-    if (fp8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, &sc);
+    if (fp8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
     if (i8) quantize_rows_int8(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
     const int KTA = sh.NT - sh.KA0;
     align();

@@ -182,7 +182,7 @@ def test_packed_sizes(L):
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
         for prec in (0, 1, 2, 3, 4, 5):
-            per = {0: 1, 1: 2, 2: 2, 3: 4, 4: 8, 5: 8}[prec]     # K tiles per k-block
+            per = {0: 1, 1: 2, 2: 4, 3: 4, 4: 8, 5: 8}[prec]     # K tiles per k-block
             kbb = {4: 2 * 1024 + 256, 5: 1024 + 256}.get(prec, 1024)   # MX: elements + 64 scale dwords
             kbytes = (lambda KT, per=per, kbb=kbb: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
             ex = 2 if prec in (2, 3) else 1     # E4M3 and INT8 units also carry one scale per output

@@ -223,22 +223,25 @@ def test_full_size_adult108_sampled(tmp_path, prec):
 
 
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
-def test_fp8_weights_parity(tmp_path, name, B):
-    """E4M3 weights with one scale per output channel, BF16 activations.
+def test_fp8_parity(tmp_path, name, B):
+    """E4M3 weights (one scale per output channel) and E4M3 GEMM inputs (one scale per row,
+    max |u| / 448), FP32 sums on the FP8 matrix cores.
 
-    Against FP64: logits |d| <= 2e-2 and argmax >= 99.9 %.  The masks move with the
-    weight rounding itself (an FP64 forward on the same E4M3 weights and BF16 activations
-    shows step-mask L1 up to 0.19 on these models, so no kernel can meet 1e-2 there); they
-    are gated at 0.25 (step) / 0.1 (aggregate) per row against FP64, and tightly against
-    FP64 on the same rounded operands, which isolates the kernel."""
+    Row by row against FP64 on the same E4M3 operands (check_rows_on_rounded); the FP8
+    instruction's sums, like the scaled one's, need not be exact FP32 sums, so the typical
+    row is gated at the median within 1e-4.  Against plain FP64 the format decides: the
+    oracle on E4M3 operands differs from plain FP64 by up to (logits, aggregate L1, step L1)
+    = (1.3e-2, 9.2e-2, 0.18) on these rows with argmax unchanged; the gates leave more."""
     params, X = synth.workload(name, rows=B)
     _say(f"case fp8 {name} B={B}")
     with load(params, tmp_path, "fp8") as m:
         got = run(m, X)
-    e = check_reduced(got, params, X, "e4m3", "bf16", f"fp8 {name}")
+    check_rows_on_rounded(got, params, X, "e4m3", f"fp8 {name}", worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4))
+    e = errs(got, oracle.forward(params, X))
+    _say(f"fp8 {name} vs fp64", e)
     assert e["logit_abs"] <= 2e-2, e
     assert e["argmax"] >= 0.999, e
-    assert e["agg_l1"] <= 0.1 and e["step_l1"] <= 0.25, e
+    assert e["agg_l1"] <= 0.12 and e["step_l1"] <= 0.25, e
 
 
 def check_int8(got, params, X, tag):

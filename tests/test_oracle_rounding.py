@@ -135,3 +135,20 @@ def test_int8_gemm_within_error_bound():
     bound = (su / 2) * np.abs(Wf).sum(1)[None, :] + np.abs(u).sum(1)[:, None] * (sw / 2).T + K * (su / 2) * (sw / 2).T
     assert (np.abs(got - exact) <= bound * (1 + 1e-9)).all()
     assert np.abs(got - exact).max() > 0          # the operands really were rounded
+
+
+def test_e4m3_row_scaled_inputs_match_torch():
+    """The oracle's E4M3 GEMM-input option (one scale per row, max |u| / 448) against
+    torch's E4M3 cast of u / s: the largest entry of each row lands on 448."""
+    from oracle import tabnet as ot
+    rng = np.random.default_rng(13)
+    u = rng.normal(0, 1, (64, 40)) * rng.uniform(1e-3, 1e3, (64, 1))
+    u[7] = 0.0
+    got = ot._round_acts(u, "e4m3")
+    amax = np.abs(u).max(1, keepdims=True)
+    sc = np.where(amax > 0, amax / 448.0, 1.0)
+    ref = torch.tensor(u / sc, dtype=torch.float64).to(torch.float8_e4m3fn).to(torch.float64).numpy() * sc
+    np.testing.assert_array_equal(got, ref)
+    nz = amax[:, 0] > 0
+    np.testing.assert_allclose(np.abs(got[nz]).max(1), amax[nz, 0], rtol=4e-16, atol=0)   # 448 (max / 448)
+    assert (got[7] == 0).all()
