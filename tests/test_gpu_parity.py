@@ -145,7 +145,7 @@ def test_bf16_parity(tmp_path, name, B):
     assert e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp4"])
 def test_optional_step_masks_and_empty_batch(tmp_path, prec):
     params, X = synth.workload("adult108", rows=777)
     _say(f"case masks_step NULL {prec}")
