@@ -20,7 +20,9 @@ compared both with exact FP64 TabNet and with FP64 TabNet on the rounded operand
                   scale 2^X (an E8M0 byte) with X = floor(log2 max|v|) - emax_elem, and
                   each element is v / 2^X rounded to nearest even in the element format,
                   saturating at its largest normal.  Elements: E4M3 (MXFP8, emax 8, max
-                  448) and E2M1 (MXFP4, emax 2, grid 0, 0.5, 1, 1.5, 2, 3, 4, 6).  X is
+                  448), E2M3 (MXFP6, emax 2, step 1/8 below 1, 3 stored mantissa bits
+                  from 1 up, max 7.5) and E2M1 (MXFP4, emax 2, grid 0, 0.5, 1, 1.5, 2,
+                  3, 4, 6).  X is
                   clamped to [-126, 127] (a block of zeros takes X = 0).  Which 32
                   positions of a K axis form a block is given by mx_block_of: the matrix
                   instruction that consumes these formats (128 K positions per operand
@@ -81,7 +83,18 @@ def round_int8_rows(x) -> np.ndarray:
 
 # ---- OCP MX block formats ----
 E2M1_MAX = 6.0
-MX_ELEMENTS = {"mxfp8": (8, E4M3_MAX), "mxfp4": (2, E2M1_MAX)}   # emax of the element, largest normal
+E2M3_MAX = 7.5
+MX_ELEMENTS = {"mxfp8": (8, E4M3_MAX), "mxfp6": (2, E2M3_MAX), "mxfp4": (2, E2M1_MAX)}   # emax, largest normal
+
+
+def round_e2m3(x) -> np.ndarray:
+    """Nearest FP6 E2M3 value (ties to even), saturating at +-7.5, as float64.  E2M3 has
+    4 significant bits from 1 up (exponent bias 1) and a step of 1/8 below 1."""
+    x = np.asarray(x, dtype=np.float64)
+    normal = _round_sig(x, 4)
+    sub = np.rint(x * 8.0) / 8.0
+    out = np.where(np.abs(x) < 1.0, sub, normal)
+    return np.clip(out, -E2M3_MAX, E2M3_MAX)
 
 
 def round_e2m1(x) -> np.ndarray:
@@ -95,19 +108,19 @@ def round_e2m1(x) -> np.ndarray:
 
 
 def _round_element(v, fmt):
-    return round_e4m3(v) if fmt == "mxfp8" else round_e2m1(v)
+    return {"mxfp8": round_e4m3, "mxfp6": round_e2m3, "mxfp4": round_e2m1}[fmt](v)
 
 
 def mx_block_of(p, fmt) -> np.ndarray:
     """Block index of K position p.  Positions run in 16-wide tiles t = p // 16, each made
     of four groups q = (p % 16) // 4; eight tiles (128 positions) form one operand row of
     the matrix instruction, k-block kb = t // 8, which holds four blocks:
-      mxfp4: block q  (group q of all eight tiles),
-      mxfp8: block q // 2 + 2 * ((t % 8) // 4)  (groups 2 b', 2 b' + 1 of four tiles).
+      mxfp4, mxfp6: block q  (group q of all eight tiles),
+      mxfp8:        block q // 2 + 2 * ((t % 8) // 4)  (groups 2 b', 2 b' + 1 of four tiles).
     Returns kb * 4 + block."""
     p = np.asarray(p)
     t, q = p // 16, (p % 16) // 4
-    within = q if fmt == "mxfp4" else q // 2 + 2 * ((t % 8) // 4)
+    within = q if fmt in ("mxfp4", "mxfp6") else q // 2 + 2 * ((t % 8) // 4)
     return (t // 8) * 4 + within
 
 

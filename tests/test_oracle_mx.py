@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.rounding import (E2M1_MAX, mx_block_of, mx_scale_exponent, round_e2m1, round_e4m3,
-                             round_mx_rows)
+from oracle.rounding import (E2M1_MAX, E2M3_MAX, mx_block_of, mx_scale_exponent, round_e2m1, round_e2m3,
+                             round_e4m3, round_mx_rows)
 from oracle import tabnet as ot
 
 
@@ -34,22 +34,48 @@ def test_e2m1_grid_and_brute_force_rounding():
         assert g == np.copysign(table[code], v), (v, g, table[code])
 
 
+def e2m3_table():
+    """All 32 FP6 E2M3 codes decoded from the bit fields: sign, 2-bit exponent (bias 1),
+    3-bit mantissa; exponent 0 is subnormal (m / 8)."""
+    vals = []
+    for c in range(32):
+        s = -1.0 if c & 32 else 1.0
+        e, m = (c >> 3) & 3, c & 7
+        vals.append(s * (m / 8.0 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 1)))
+    return np.array(vals)
+
+
+def test_e2m3_grid_and_brute_force_rounding():
+    table = e2m3_table()
+    assert max(table) == E2M3_MAX and len(set(np.abs(table))) == 32
+    rng = np.random.default_rng(6)
+    x = np.concatenate([rng.uniform(-9, 9, 5000), np.arange(-8, 8.01, 1 / 16), [0.0, 100.0, -100.0]])
+    got = round_e2m3(x)
+    pos = table[:32]
+    for v, g in zip(x, got):
+        a = min(abs(v), E2M3_MAX)
+        d = np.abs(pos - a)
+        best = np.flatnonzero(d == d.min())
+        code = best[0] if len(best) == 1 else [b for b in best if b % 2 == 0][0]   # ties: even code
+        assert g == np.copysign(pos[code], v), (v, g, pos[code])
+
+
 def slot_block(p, fmt):
     """The block of K position p derived from the matrix instruction's operand layout (a
     row of 128 K slots over 4 lane groups of 32 elements; blocks are 32 consecutive
     slots).  The position's lane group is q = (p % 16) // 4 and its element within the
-    lane e = 4 * (t % 8) + p % 4 for tile t = p // 16.  MXFP4 lanes hold slots 32 q + e;
+    lane e = 4 * (t % 8) + p % 4 for tile t = p // 16.  MXFP4 and MXFP6 lanes hold slots 32 q + e;
     MXFP8 lanes hold slots 16 q + e for e < 16 and 64 + 16 q + (e - 16) for the rest."""
     t, q = p // 16, (p % 16) // 4
     e = 4 * (t % 8) + p % 4
-    if fmt == "mxfp4":
+    if fmt in ("mxfp4", "mxfp6"):
         slot = 32 * q + e
     else:
         slot = 16 * q + e if e < 16 else 64 + 16 * q + (e - 16)
     return (t // 8) * 4 + slot // 32
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
 def test_block_partition_matches_instruction_layout(fmt):
     p = np.arange(512)
     got = mx_block_of(p, fmt)
@@ -78,7 +104,7 @@ def brute_mx(x, fmt, offset):
     then round (pure Python loops over a small matrix)."""
     rows, K = x.shape
     out = np.zeros_like(x)
-    emax, vmax = (8, 448.0) if fmt == "mxfp8" else (2, 6.0)
+    emax, vmax = {"mxfp8": (8, 448.0), "mxfp6": (2, 7.5), "mxfp4": (2, 6.0)}[fmt]
     for r in range(rows):
         for j in range(K):
             b = slot_block(j + offset, fmt)
@@ -90,12 +116,13 @@ def brute_mx(x, fmt, offset):
             X = int(np.floor(np.log2(m))) - emax
             X = min(max(X, -126), 127)
             v = x[r, j] / 2.0 ** X
-            v = float(round_e4m3(np.array([v]))[0] if fmt == "mxfp8" else round_e2m1(np.array([v]))[0])
+            rnd = {"mxfp8": round_e4m3, "mxfp6": round_e2m3, "mxfp4": round_e2m1}[fmt]
+            v = float(rnd(np.array([v]))[0])
             out[r, j] = max(-vmax, min(vmax, v)) * 2.0 ** X
     return out
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
 @pytest.mark.parametrize("K,offset", [(35, 0), (108, 0), (24, 8), (64, 0)])
 def test_round_mx_rows_matches_brute_force(fmt, K, offset):
     rng = np.random.default_rng(K + offset)
@@ -125,7 +152,7 @@ def test_mxfp8_elements_match_torch_e4m3_and_saturate():
     assert r[0, 0] == 448.0 and r[0, 1] == 1.0
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
 def test_mx_exact_on_grid_and_scale_equivariant(fmt):
     rng = np.random.default_rng(4)
     x = rng.normal(0, 1, (6, 100))
@@ -136,11 +163,11 @@ def test_mx_exact_on_grid_and_scale_equivariant(fmt):
     # per element: within half a step of the grid at the block's scale (the step of the
     # top binade [2^emax, 2^(emax+1)) bounds all), or saturated at the largest normal
     blk = mx_block_of(np.arange(100), fmt)
-    vmax = 448.0 if fmt == "mxfp8" else E2M1_MAX
+    vmax = {"mxfp8": 448.0, "mxfp6": E2M3_MAX, "mxfp4": E2M1_MAX}[fmt]
     for b in np.unique(blk):
         cols = blk == b
         sc = np.ldexp(1.0, mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), fmt))
-        step = sc * (2.0 ** (8 - 3) if fmt == "mxfp8" else 2.0 ** (2 - 1))
+        step = sc * {"mxfp8": 2.0 ** (8 - 3), "mxfp6": 2.0 ** (2 - 3), "mxfp4": 2.0 ** (2 - 1)}[fmt]
         err = np.abs(r[:, cols] - x[:, cols])
         sat = (np.abs(x[:, cols]) > vmax * sc) & (np.abs(r[:, cols]) == vmax * sc)
         assert ((err <= step / 2 * (1 + 1e-12)) | sat).all()
