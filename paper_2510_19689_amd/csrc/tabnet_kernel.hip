@@ -323,27 +323,80 @@ struct BOp<5, KT, R> {
   }
 };
 
+// MXFP6: per row block and k-block, 32 E2M3 elements forming one block, the lane's own
+// (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i in bits 6 e .. 6 e + 5 of six dwords),
+// with its E8M0 scale.  The conversion takes two vectors of 16 values and interleaves them
+// (element 2 j from the first, 2 j + 1 from the second), rounds v / 2^X to nearest even and
+// saturates at +-7.5.  It writes its result while it still reads its sources, so the
+// result must not share registers with them: the instruction is issued with an
+// early-clobber result operand (the builtin's register allocation allows the overlap).
+template <int KT, int R>
+struct BOp<6, KT, R> {
+  static constexpr int KB = kblocks(6, KT);
+  uint32_t v[R][KB][6];
+  uint32_t sc[R][KB];
+  template <class F>
+  __device__ __forceinline__ void build(F src) {
+    typedef float f16v __attribute__((ext_vector_type(16)));
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        f16v a, b;
+        float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int t = 8 * kb + tt, e = 4 * tt + i;
+            const float x = t < KT ? src(rb, t < KT ? t : 0, i) : 0.f;
+            if (e & 1) {
+              b[e >> 1] = x;
+              m1 = fmaxf(m1, fabsf(x));
+            } else {
+              a[e >> 1] = x;
+              m0 = fmaxf(m0, fabsf(x));
+            }
+          }
+        const int X = mx_exponent<2>(fmaxf(m0, m1));
+        const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+        typedef unsigned u6v __attribute__((ext_vector_type(6)));
+        u6v r;
+        // early-clobber result: the destination registers may not overlap a, b or scale
+        asm("v_cvt_scalef32_2xpk16_fp6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
+#pragma unroll
+        for (int d = 0; d < 6; ++d) v[rb][kb][d] = r[d];
+        sc[rb][kb] = (uint32_t)(X + 127);
+      }
+  }
+};
+
 // acc[rb] += W(one output tile, all K) * B[rb] with both operands in an MX format: one
 // 16x16x128 scaled MFMA per k-block, the block scales applied inside the instruction.
 template <int PREC, int KT, int R>
 __device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<PREC, KT, R>& b, f4 (&acc)[R],
                                             int lane) {
   constexpr int KB = kblocks(PREC, KT);
-  constexpr int FMT = PREC == 4 ? 0 : 4;              // E4M3 or E2M1 elements
-  constexpr int EL = PREC == 4 ? 2 * kFrag : kFrag;   // element bytes per k-block
+  constexpr int FMT = PREC == 4 ? 0 : (PREC == 6 ? 2 : 4);   // E4M3, E2M3 or E2M1 elements
+  constexpr int ND = PREC == 4 ? 8 : (PREC == 6 ? 6 : 4);    // operand dwords per lane
+  constexpr int EL = kbytes(PREC) - kMxScaleBytes;            // element bytes per k-block
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     const unsigned char* f = fr + kb * kbytes(PREC);
     const i4 lo = *reinterpret_cast<const i4*>(f + lane * 16);
     i4 hi = {0, 0, 0, 0};
     if constexpr (PREC == 4) hi = *reinterpret_cast<const i4*>(f + kFrag + lane * 16);
+    if constexpr (PREC == 6) {
+      const uint2 m = *reinterpret_cast<const uint2*>(f + kFrag + lane * 8);
+      hi = i4{(int)m.x, (int)m.y, 0, 0};
+    }
     const i8v a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     const int sa = *reinterpret_cast<const int*>(f + EL + lane * 4);
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
       i8v bb;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bb[j] = (PREC == 4 || j < 4) ? (int)b.v[rb][kb][PREC == 4 ? j : (j & 3)] : 0;
+      for (int j = 0; j < 8; ++j) bb[j] = j < ND ? (int)b.v[rb][kb][j < ND ? j : 0] : 0;
       acc[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bb, acc[rb], FMT, FMT, 0, sa, 0,
                                                                  (int)b.sc[rb][kb]);
     }
@@ -1547,7 +1600,7 @@ struct KernelEntry {
   TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
-                                       TABNET_SHAPES(4) TABNET_SHAPES(5)
+                                       TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
 

@@ -48,11 +48,12 @@
 // MX formats (OCP microscaling: blocks of 32 K positions share a power-of-two E8M0
 // scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA: MXFP8 packs per
 // k-block [64 lanes x 16 B: E4M3 elements 0-15][64 x 16 B: elements 16-31][64 x 4 B: the
-// E8M0 scale each lane supplies, in byte 0]; MXFP4 packs [64 x 16 B: 32 E2M1 elements,
-// element e in nibble e][64 x 4 B: scales].  Element e of a lane holds feature
+// E8M0 scale each lane supplies, in byte 0]; MXFP6 packs [64 x 16 B: bytes 0-15][64 x 8 B:
+// bytes 16-23 of 32 E2M3 elements, element e in bits 6 e .. 6 e + 5][64 x 4 B: scales];
+// MXFP4 packs [64 x 16 B: 32 E2M1 elements, element e in nibble e][64 x 4 B: scales].  Element e of a lane holds feature
 // 16 (8 kb + e / 4) + 4 q + e % 4.  The instruction groups a lane row's 128 K slots into
 // four blocks of 32 consecutive slots and takes block b's scale from lane group b:
-//   MXFP4: lane group q holds slots 32 q + e, so its block is its own 32 elements;
+//   MXFP6, MXFP4: lane group q holds slots 32 q + e, so its block is its own 32 elements;
 //   MXFP8: lane group q holds slots 16 q + e (e < 16) and 64 + 16 q + (e - 16), so block
 //          b' + 2 h (b' = q / 2, h = e / 16) pairs lane groups 2 b' and 2 b' + 1.
 // The scales are applied inside the instruction, so MX units carry shifts only.
@@ -80,7 +81,7 @@ struct GemmPlan {
   int nchunks;
 };
 
-// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (MXFP8, MXFP4)
+// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (MXFP8, MXFP4, MXFP6)
 constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 1 ? 2 : (prec <= 3 ? 4 : 8)); }
 constexpr int kblocks(int prec, int KT) {
   return (KT + ktiles_per_block(prec) - 1) / ktiles_per_block(prec);
@@ -88,7 +89,8 @@ constexpr int kblocks(int prec, int KT) {
 // Bytes of one k-block of one output tile: a fragment, or the MX elements and scales.
 constexpr int kMxScaleBytes = 256;
 constexpr int kbytes(int prec) {
-  return prec == 4 ? 2 * kFrag + kMxScaleBytes : (prec == 5 ? kFrag + kMxScaleBytes : kFrag);
+  return prec == 4 ? 2 * kFrag + kMxScaleBytes
+                   : (prec == 5 ? kFrag + kMxScaleBytes : (prec == 6 ? kFrag + kFrag / 2 + kMxScaleBytes : kFrag));
 }
 // Per-output scales after the shifts (E4M3, INT8)
 constexpr bool has_channel_scales(int prec) { return prec == 2 || prec == 3; }
@@ -130,7 +132,7 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 // prec: 0 FP32, 1 BF16, 2 E4M3 and 3 INT8 weights and activations (codes in the fragments,
 // one FP32 scale per output channel after the shifts, one scale per input row formed in
-// the kernel), 4 MXFP8 and 5 MXFP4 (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
+// the kernel), 4 MXFP8, 5 MXFP4 and 6 MXFP6 (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
 // KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const int sc = has_channel_scales(prec) ? 2 : 1;   // shifts, or shifts + scales

@@ -266,6 +266,20 @@ uint8_t e2m1_bits_rne(double x) {
   return sign | (uint8_t)code;
 }
 
+// FP6 E2M3 bits (sign in bit 5) of x, round to nearest even, saturating at +-7.5.  The grid
+// has a step of 1/8 up to 2, 1/4 up to 4 and 1/2 up to 7.5; as for E2M1, each step range
+// maps the rounded multiple to the code by an offset of the same parity.
+uint8_t e2m3_bits_rne(double x) {
+  const uint8_t sign = std::signbit(x) ? 32 : 0;
+  const double a = std::fabs(x);
+  if (std::isnan(x)) return 31;
+  int code;
+  if (a < 2.0) code = (int)std::nearbyint(8.0 * a);             // 0 .. 16 (16 = 2.0)
+  else if (a < 4.0) code = (int)std::nearbyint(4.0 * a) + 8;    // 16 .. 24 (24 = 4.0)
+  else code = std::min(31, (int)std::nearbyint(2.0 * a) + 16);  // 24 .. 31, saturating
+  return sign | (uint8_t)code;
+}
+
 int mx_exponent(double amax, int emax) {
   if (!(amax > 0)) return 0;
   int e;
@@ -312,7 +326,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         for (int r = 0; r < 4; ++r) v[r] = (float)wv(i, 16 * kt + 4 * q + r);
         emit(wts, v, sizeof v);
       }
-  } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP4) {
+  } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP4 || precision == TABNET_MXFP6) {
     // Per k-block of eight K tiles: the E8M0 exponent of each of an output row's four
     // blocks, then the elements lane by lane, then the scale each lane supplies (the
     // instruction takes block b's scale from lane group b).
@@ -346,6 +360,24 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
             }
             emit(wts, v, sizeof v);
           }
+      } else if (precision == TABNET_MXFP6) {
+        // 32 six-bit elements per lane, element e in bits 6 e .. 6 e + 5 of 24 bytes:
+        // bytes 0-15 of every lane, then bytes 16-23 of every lane
+        uint8_t bytes[64][24];
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane & 15, q = lane >> 4;
+          uint64_t w[3] = {0, 0, 0};
+          for (int e = 0; e < 32; ++e) {
+            const int tt = e / 4, j = e % 4;
+            const uint64_t c = e2m3_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
+            const int bit = 6 * e;
+            w[bit / 64] |= c << (bit % 64);
+            if (bit % 64 > 58) w[bit / 64 + 1] |= c >> (64 - bit % 64);
+          }
+          std::memcpy(bytes[lane], w, 24);
+        }
+        for (int lane = 0; lane < 64; ++lane) emit(wts, bytes[lane], 16);
+        for (int lane = 0; lane < 64; ++lane) emit(wts, bytes[lane] + 16, 8);
       } else {
         for (int lane = 0; lane < 64; ++lane) {
           const int i = lane & 15, q = lane >> 4;

@@ -44,6 +44,8 @@ uint8_t e4m3_bits_rne(double x);
 // FP4 E2M1 bits of a double (round to nearest even, saturating at +-6), and the OCP MX
 // shared exponent floor(log2 amax) - emax clamped to [-126, 127] (0 for amax = 0).
 uint8_t e2m1_bits_rne(double x);
+// FP6 E2M3 bits of a double (round to nearest even, saturating at +-7.5).
+uint8_t e2m3_bits_rne(double x);
 int mx_exponent(double amax, int emax);
 double bf16_value(uint16_t bits);
 double e4m3_value(uint8_t bits);

@@ -115,13 +115,19 @@ def test_rounding_hooks_match_torch(L):
 
 
 def test_mx_encoders_match_oracle(L):
-    """The packer's E2M1 encoder and MX exponent rule against the oracle's."""
+    """The packer's E2M1 and E2M3 encoders and MX exponent rule against the oracle's."""
     from oracle.rounding import mx_scale_exponent, round_e2m1
     rng = np.random.default_rng(9)
     x = np.concatenate([rng.uniform(-8, 8, 3000), np.arange(-7, 7.01, 0.25), [0.0, -0.0, 100.0, -1e-3]])
     table = [(-1.0 if c & 8 else 1.0) * [0, 0.5, 1, 1.5, 2, 3, 4, 6][c & 7] for c in range(16)]
     got = np.array([table[L.tabnet_hook_e2m1_bits(float(v))] for v in x])
     np.testing.assert_array_equal(got, round_e2m1(x))
+    from oracle.rounding import round_e2m3
+    t6 = [(-1.0 if c & 32 else 1.0) * ((c & 7) / 8.0 if (c >> 3) & 3 == 0 else (1 + (c & 7) / 8.0) * 2.0 ** (((c >> 3) & 3) - 1))
+          for c in range(64)]
+    x6 = np.concatenate([rng.uniform(-9, 9, 3000), np.arange(-8, 8.01, 1 / 16), [0.0, -0.0, 100.0]])
+    got6 = np.array([t6[L.tabnet_hook_e2m3_bits(float(v))] for v in x6])
+    np.testing.assert_array_equal(got6, round_e2m3(x6))
     amax = np.concatenate([np.abs(rng.normal(0, 10, 2000)), [0.0, 1.0, 448.0, 2.0 ** -140, 3e38]])
     for fmt, emax in (("mxfp8", 8), ("mxfp4", 2)):
         got = np.array([L.tabnet_hook_mx_exponent(float(a), emax) for a in amax])
@@ -181,9 +187,9 @@ def test_packed_sizes(L):
         target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in (0, 1, 2, 3, 4, 5):
-            per = {0: 1, 1: 2, 2: 4, 3: 4, 4: 8, 5: 8}[prec]     # K tiles per k-block
-            kbb = {4: 2 * 1024 + 256, 5: 1024 + 256}.get(prec, 1024)   # MX: elements + 64 scale dwords
+        for prec in (0, 1, 2, 3, 4, 5, 6):
+            per = {0: 1, 1: 2, 2: 4, 3: 4, 4: 8, 5: 8, 6: 8}[prec]     # K tiles per k-block
+            kbb = {4: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256}.get(prec, 1024)   # MX: elements + scales
             kbytes = (lambda KT, per=per, kbb=kbb: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
             ex = 2 if prec in (2, 3) else 1     # E4M3 and INT8 units also carry one scale per output
             glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}

@@ -145,7 +145,7 @@ def test_bf16_parity(tmp_path, name, B):
     assert e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
 def test_optional_step_masks_and_empty_batch(tmp_path, prec):
     params, X = synth.workload("adult108", rows=777)
     _say(f"case masks_step NULL {prec}")
@@ -310,7 +310,7 @@ def test_int8_unsupported_shape_and_round_trip(tmp_path):
 
 # Against plain FP64 the MX formats' own error decides: the oracle on MX operands differs
 # from plain FP64 by up to (logits, aggregate L1, step L1) = (1.2e-2, 0.22, 0.31) in MXFP8
-# and (3.3e-2, 0.45, 0.86) in MXFP4 on these rows, with argmax unchanged; the gates leave
+# and (3.3e-2, 0.45, 0.86) in MXFP4 on these rows (MXFP6 below), with argmax unchanged; the gates leave
 # a quarter more.  Per row against the same MX operands: flips of an E2M1 element move a
 # value by up to a third, hence the wider worst-row bounds for MXFP4.  The E4M3 form of
 # the scaled MFMA does not sum its products exactly in FP32: on known operands it
@@ -318,10 +318,12 @@ def test_int8_unsupported_shape_and_round_trip(tmp_path):
 # exact), so every MXFP8 GEMM output carries an error of that order and the typical
 # MXFP8 row moves by ~1e-5; its typical-row gate is the median row within 1e-4.
 MX_GATES = {"mxfp8": dict(fp64=(1.5e-2, 0.28, 0.4), worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4)),
+            # MXFP6 (E2M3): format error (1.3e-2, 0.097, 0.27); its instruction form sums exactly
+            "mxfp6": dict(fp64=(1.7e-2, 0.125, 0.35), worst=(0.1, 0.05, 5e-3), typical=(0.9, 1e-5)),
             "mxfp4": dict(fp64=(4.2e-2, 0.56, 1.08), worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5))}
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
 def test_mx_parity(tmp_path, name, B, fmt):
     """OCP MX formats on both GEMM operands (E8M0 block scales applied by the scaled MFMA)."""
@@ -341,7 +343,7 @@ def test_mx_parity(tmp_path, name, B, fmt):
     np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp4"])
+@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
 def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
     params, X = synth.workload("adult108", rows=300)
     _say(f"case {fmt} row independence")
