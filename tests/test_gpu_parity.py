@@ -360,3 +360,28 @@ def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
     with pytest.raises(tb.TabNetError) as ei:
         tb.Model(path, fmt)
     assert ei.value.status == tb.E_UNSUPPORTED
+
+
+# per-row gates of each scaled format against FP64 on its own operands (see the tests above)
+ROW_GATES = {"int8": ("int8", (2.5e-2, 1e-2, 2e-3), (0.9, 1e-5)),
+             "fp8": ("e4m3", (0.1, 0.05, 5e-3), (0.5, 1e-4)),
+             "mxfp8": ("mxfp8", MX_GATES["mxfp8"]["worst"], MX_GATES["mxfp8"]["typical"]),
+             "mxfp6": ("mxfp6", MX_GATES["mxfp6"]["worst"], MX_GATES["mxfp6"]["typical"]),
+             "mxfp4": ("mxfp4", MX_GATES["mxfp4"]["worst"], MX_GATES["mxfp4"]["typical"])}
+
+
+@pytest.mark.parametrize("fmt", list(ROW_GATES))
+@pytest.mark.parametrize("k", range(len(SMALL)))
+def test_scaled_formats_small_shapes(tmp_path, k, fmt):
+    """The scaled formats on the small shapes: attention halves that start 1, 3, 4, 5 or 8
+    channels into a tile (the row scales and MX blocks of the attentive GEMM cover the
+    attention channels only, at their positions in h's tiles), no shared or no step
+    layers, a single feature."""
+    cfg = TabNetConfig(**SMALL[k])
+    params = synth.make_params(cfg, 100 + k)
+    X = synth.make_normal_inputs(300, cfg.D, seed=200 + k)
+    _say(f"case {fmt} small shape {k}: {SMALL[k]}")
+    oracle_fmt, worst, typical = ROW_GATES[fmt]
+    with load(params, tmp_path, fmt) as m:
+        got = run(m, X)
+    check_rows_on_rounded(got, params, X, oracle_fmt, f"{fmt} small {k}", worst=worst, typical=typical)
