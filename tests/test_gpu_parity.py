@@ -176,17 +176,21 @@ def test_rows_independent_and_deterministic(tmp_path, prec):
             np.testing.assert_array_equal(part[2], full[2][:, lo_:hi_])
 
 
-def test_nonfinite_row_is_contained(tmp_path):
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
+def test_nonfinite_row_is_contained(tmp_path, prec):
+    """A NaN or Inf in a row changes nothing in the other rows; in the scaled formats the
+    row (or block) scale is taken from that row alone."""
     params, X = synth.workload("hr35", rows=200)
     Xb = X.copy()
     Xb[3, 5] = np.nan
     Xb[150, :] = np.inf
-    _say("case non-finite rows")
-    with load(params, tmp_path, "bf16") as m:
+    Xb[77, 2] = -np.inf
+    _say(f"case non-finite rows {prec}")
+    with load(params, tmp_path, prec) as m:
         clean = run(m, X)
         dirty = run(m, Xb)
     keep = np.ones(200, bool)
-    keep[[3, 150]] = False
+    keep[[3, 77, 150]] = False
     for u, v in zip(clean, dirty):
         if u.ndim == 3:
             np.testing.assert_array_equal(u[:, keep], v[:, keep])
