@@ -202,7 +202,7 @@ int tabnet_abi_version(void);
 /* ------------------------------------------------------------------------------------
  * Mask statistics.
  *
- * The paper judges whether TabNet's explanations stay stable under production load by
+ * The paper assesses whether TabNet's explanations stay stable under production load by
  * the variance of each feature's mask value over many served rows, reported next to
  * each feature's importance (Sec. IV-C, Sec. V-C, Table IV).  These calls compute, on
  * the GPU, the per-feature mean (importance over a set of rows) and the population

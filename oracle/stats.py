@@ -3,7 +3,7 @@
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import this
 module; it shares no code with the HIP path.
 
-What it computes.  The paper judges whether TabNet's masks stay stable under load by the
+What it computes.  The paper assesses whether TabNet's masks stay stable under load by the
 variance of each feature's mask value over many served rows (Sec. IV-C, Sec. V-C: 100
 random samples at peak throughput), and reports per-feature importance next to it
 (Table IV).  The paper gives no formula for its stability score; the computable part is

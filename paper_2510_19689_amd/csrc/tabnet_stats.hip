@@ -1,7 +1,7 @@
 // Per-feature statistics of mask rows on the GPU: mean and population variance of every
 // column of an [B, D] FP32 matrix (the aggregate mask, or one step's mask).
 //
-// The paper judges the stability of TabNet's explanations under load by the variance of
+// The paper assesses the stability of TabNet's explanations under load by the variance of
 // each feature's mask value over many served rows, next to each feature's importance
 // (Sec. IV-C, Sec. V-C, Table IV).  These kernels compute both for any set of rows, as
 // shifted sums: with K_d = m[0][d] (the column's first value, which every workgroup can
