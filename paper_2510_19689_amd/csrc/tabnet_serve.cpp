@@ -23,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -44,7 +45,7 @@ struct Request {
   uint64_t id;
   int model;
   int64_t rows;
-  std::vector<float> X;          // copied at submit
+  std::unique_ptr<float[]> X;    // copied at submit
   float* logits;
   float* magg;
   float* msteps;                 // may be null
@@ -65,6 +66,84 @@ struct Launch {
   int model;
   int64_t rows;
   std::vector<Segment> segs;
+};
+
+// Host copies of the serving path, split over a few worker threads when large.  At ten
+// thousand mixed requests per second one thread's memcpy is about as fast as the rows
+// arrive, so copies of 1 MiB or more are cut into 64-byte-aligned pieces, one per worker
+// plus one for the calling thread, which waits for all of them.
+class CopyPool {
+ public:
+  static constexpr size_t kMinSplit = 1 << 20;
+
+  explicit CopyPool(int workers) {
+    for (int i = 0; i < workers; ++i) thr_.emplace_back([this] { run(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : thr_) t.join();
+  }
+  void copy(void* dst, const void* src, size_t bytes) {
+    if (bytes < kMinSplit || thr_.empty()) {
+      std::memcpy(dst, src, bytes);
+      return;
+    }
+    const size_t parts = thr_.size() + 1;
+    const size_t piece = (bytes / parts + 63) & ~(size_t)63;
+    Latch latch;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t k = 1; k < parts && k * piece < bytes; ++k) {
+        const size_t off = k * piece;
+        jobs_.push_back(Job{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off,
+                            std::min(piece, bytes - off), &latch});
+        ++latch.n;
+      }
+    }
+    cv_.notify_all();
+    std::memcpy(dst, src, std::min(piece, bytes));
+    std::unique_lock<std::mutex> lk(latch.m);
+    latch.cv.wait(lk, [&] { return latch.n == 0; });
+  }
+
+ private:
+  struct Latch {
+    std::mutex m;
+    std::condition_variable cv;
+    int n = 0;
+  };
+  struct Job {
+    char* dst;
+    const char* src;
+    size_t bytes;
+    Latch* latch;
+  };
+  void run() {
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || !jobs_.empty(); });
+      if (jobs_.empty()) return;   // stopping, nothing left
+      const Job j = jobs_.front();
+      jobs_.pop_front();
+      lk.unlock();
+      std::memcpy(j.dst, j.src, j.bytes);
+      {
+        // the waiter may destroy the latch as soon as it sees n == 0: touch it only here
+        std::lock_guard<std::mutex> ll(j.latch->m);
+        if (--j.latch->n == 0) j.latch->cv.notify_all();
+      }
+      lk.lock();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<Job> jobs_;
+  bool stop_ = false;
+  std::vector<std::thread> thr_;
 };
 
 }  // namespace
@@ -97,6 +176,7 @@ struct ServerImpl {
   // per model: statistics (mean[D], M2[D], n) of masks_agg of its last launches, oldest first
   std::vector<std::deque<std::vector<double>>> mask_windows;
 
+  CopyPool copies{3};
   std::thread sched_thr, comp_thr;
 
   uint64_t req_bytes(int model, int64_t rows) const {
@@ -149,7 +229,7 @@ struct ServerImpl {
       const int D = models[L.model].cfg.D;
       float* in = exec->input(L.slot);
       for (const Segment& sg : L.segs)
-        std::memcpy(in + sg.dst_row * D, sg.req->X.data() + sg.src_row * D, (size_t)sg.rows * D * sizeof(float));
+        copies.copy(in + sg.dst_row * D, sg.req->X.get() + sg.src_row * D, (size_t)sg.rows * D * sizeof(float));
       const bool ok = exec->launch(L.slot, L.model, L.rows);
       lk.lock();
       ++launches;
@@ -198,11 +278,11 @@ struct ServerImpl {
         const float* ms = exec->out_steps(L.slot);
         for (const Segment& sg : L.segs) {
           Request& r = *sg.req;
-          std::memcpy(r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4);
-          std::memcpy(r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4);
+          copies.copy(r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4);
+          copies.copy(r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4);
           if (r.msteps && ms)
             for (int s = 0; s < S; ++s)
-              std::memcpy(r.msteps + ((int64_t)s * r.rows + sg.src_row) * D,
+              copies.copy(r.msteps + ((int64_t)s * r.rows + sg.src_row) * D,
                           ms + ((int64_t)s * L.rows + sg.dst_row) * D, (size_t)sg.rows * D * 4);
         }
       }
@@ -227,8 +307,7 @@ struct ServerImpl {
           rows_done += (uint64_t)r.rows;
           lat_us.push_back((double)(t - r.arrival_ns) * 1e-3);
           last_done = std::max(last_done, t);
-          r.X.clear();
-          r.X.shrink_to_fit();
+          r.X.reset();
         }
       }
       free_slots.push_back(L.slot);
@@ -277,7 +356,9 @@ tabnet_status server_submit(ServerImpl* s, int model, const float* X, int64_t ro
     set_error("tabnet_serve_submit: request larger than the memory budget");
     return TABNET_E_ADMISSION;
   }
-  r->X.assign(X, X + (size_t)rows * mi.cfg.D);
+  const size_t nx = (size_t)rows * mi.cfg.D;
+  r->X.reset(new float[nx]);
+  s->copies.copy(r->X.get(), X, nx * sizeof(float));
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) {
     set_error("tabnet_serve_submit: server stopped");

@@ -1,6 +1,7 @@
 // Host-only driver for the serving scheduler with the CPU stand-in executor; built by
 // tests/test_sanitizers.py under ThreadSanitizer and under AddressSanitizer+UBSan.
-// Several submitter threads, requests split across launches, concurrent waits, stop.
+// Several submitter threads, requests split across launches, concurrent waits, stop; then
+// megabyte requests that take the split path of the server's host copies.
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -72,5 +73,52 @@ int main() {
   for (int k = 0; k < 5; ++k) server_submit(s, 0, X.data(), 50, lo.data(), ag.data(), nullptr, 0, &id);
   server_stop(s);
   std::printf("completed=%llu bad=%d\n", (unsigned long long)st.completed, bad.load());
-  return (bad.load() == 0 && st.completed == 160) ? 0 : 1;
+  if (bad.load() != 0 || st.completed != 160) return 1;
+
+  // Wide rows: requests of megabytes, so that the server's host copies (input at submit,
+  // gather into the launch buffer, scatter of the outputs) take their split path.
+  const int D = 2048;
+  tabnet_config w = c;
+  w.D = D;
+  w.n_out = 2;
+  w.n_steps = 1;
+  std::vector<ModelInfo> wide{ModelInfo{w, 4ull * (D + 2 + D + D), nullptr}};
+  tabnet_serve_opts ow = o;
+  ow.mem_budget_bytes = 1ull << 30;
+  ow.max_rows_per_launch = 512;
+  ow.slots = 2;
+  Executor* ew = make_fake_executor(wide, ow, 50);
+  ServerImpl* sw = nullptr;
+  if (server_create(wide, ew, ow, &sw) != TABNET_OK) return 2;
+  std::atomic<int> bad2{0};
+  std::vector<std::thread> tw;
+  for (int t = 0; t < 2; ++t)
+    tw.emplace_back([&, t] {
+      std::mt19937 rng(100 + t);
+      for (int k = 0; k < 4; ++k) {
+        const int rows = 300 + (int)(rng() % 400);
+        std::vector<float> X((size_t)rows * D), lo(rows * 2), ag((size_t)rows * D), ms((size_t)rows * D);
+        for (size_t i = 0; i < X.size(); ++i) X[i] = (float)((i * 7 + k + 3 * t) % 1000) / 100.f;
+        uint64_t id = 0;
+        if (server_submit(sw, 0, X.data(), rows, lo.data(), ag.data(), ms.data(), 0, &id) != TABNET_OK ||
+            server_wait(sw, id, -1) != TABNET_OK) {
+          ++bad2;
+          continue;
+        }
+        for (int r = 0; r < rows; ++r) {
+          for (int o2 = 0; o2 < 2; ++o2)
+            if (lo[r * 2 + o2] != X[(size_t)r * D + o2] + (float)o2) ++bad2;
+          for (int j = 0; j < D; ++j) {
+            if (ag[(size_t)r * D + j] != 2.f * X[(size_t)r * D + j]) ++bad2;
+            if (ms[(size_t)r * D + j] != X[(size_t)r * D + j]) ++bad2;
+          }
+        }
+      }
+    });
+  for (auto& th : tw) th.join();
+  tabnet_serve_stats sw_st{};
+  server_stats(sw, &sw_st);
+  server_stop(sw);
+  std::printf("wide completed=%llu bad=%d\n", (unsigned long long)sw_st.completed, bad2.load());
+  return (bad2.load() == 0 && sw_st.completed == 8) ? 0 : 1;
 }
