@@ -8,9 +8,10 @@ prior, sparsemax, prior update, decision and mask aggregation, final map), with 
 the aggregate mask and all per-step masks written to HBM.  Inputs are seeded synthetic
 rows shaped like the paper's Adult table (Sec. IV-A), resident in HBM before timing.
 
-The JSON line reports BF16 rows/s as `value`, the plain FP32 path on the same GPU beside
-it, the roofline of the fused kernel (algorithmic bytes per launch over the event-timed
-launch duration), and the FP64 CPU oracle timed on a bounded sample on the host.
+The JSON line reports BF16 rows/s as `value`, the plain FP32 path and the reduced-precision
+paths (FP8, INT8, MX) on the same GPU beside it, the roofline of the fused kernel
+(algorithmic bytes per launch over the event-timed launch duration), the serving legs, and
+the FP64 CPU oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
