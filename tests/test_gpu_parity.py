@@ -198,10 +198,15 @@ def test_nonfinite_row_is_contained(tmp_path, prec):
             np.testing.assert_array_equal(u[keep], v[keep])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "int8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
 def test_full_size_adult108_sampled(tmp_path, prec):
-    """The benchmarked launch (65,536 rows, step masks on): sampled rows against the
-    oracle, invariants on every row."""
+    """The benchmarked launch (65,536 rows, step masks on) in every precision the benchmark
+    times: sampled rows against the oracle, invariants on every row.  The scaled formats
+    take the row-by-row gates of their smaller cases against FP64 on the same quantised
+    operands, and their plain-FP64 gates; on these 384 rows the formats themselves move
+    (logits, aggregate L1, step L1) by at most (7.6e-3, 4.2e-2, 0.16) in FP8,
+    (1.4e-3, 1.7e-2, 7.5e-2) in INT8, (9.4e-3, 6.2e-2, 0.21) in MXFP8,
+    (7.6e-3, 5.6e-2, 0.20) in MXFP6 and (2.9e-2, 0.20, 0.72) in MXFP4."""
     params, X = synth.workload("adult108")
     assert X.shape == (65536, 108)
     _say(f"case full adult108 {prec}")
@@ -222,8 +227,12 @@ def test_full_size_adult108_sampled(tmp_path, prec):
         assert e["logit_abs"] <= 2e-2 and e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
         assert e["argmax"] >= 0.999, e
     else:
-        check_int8((lo[idx], ag[idx], ms[:, idx]), params, X[idx], "full adult108 int8")
-        assert e["logit_abs"] <= 5e-2 and e["agg_l1"] <= 0.1 and e["step_l1"] <= 0.25, e
+        oracle_fmt, worst, typical = ROW_GATES[prec]
+        check_rows_on_rounded((lo[idx], ag[idx], ms[:, idx]), params, X[idx], oracle_fmt,
+                              f"full adult108 {prec}", worst=worst, typical=typical)
+        lo_t, agg_t, step_t = FP64_GATES[prec]
+        assert e["logit_abs"] <= lo_t and e["agg_l1"] <= agg_t and e["step_l1"] <= step_t, e
+        assert e["argmax"] >= 0.995, e
 
 
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
@@ -243,9 +252,9 @@ def test_fp8_parity(tmp_path, name, B):
     check_rows_on_rounded(got, params, X, "e4m3", f"fp8 {name}", worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4))
     e = errs(got, oracle.forward(params, X))
     _say(f"fp8 {name} vs fp64", e)
-    assert e["logit_abs"] <= 2e-2, e
+    lo_t, agg_t, step_t = FP64_GATES["fp8"]
+    assert e["logit_abs"] <= lo_t and e["agg_l1"] <= agg_t and e["step_l1"] <= step_t, e
     assert e["argmax"] >= 0.999, e
-    assert e["agg_l1"] <= 0.12 and e["step_l1"] <= 0.25, e
 
 
 def check_int8(got, params, X, tag):
@@ -293,9 +302,9 @@ def test_int8_parity(tmp_path, name, B):
     check_int8(got, params, X, f"int8 {name}")
     e = errs(got, oracle.forward(params, X))
     _say(f"int8 {name} vs fp64", e)
-    assert e["logit_abs"] <= 5e-2, e
+    lo_t, agg_t, step_t = FP64_GATES["int8"]
+    assert e["logit_abs"] <= lo_t and e["agg_l1"] <= agg_t and e["step_l1"] <= step_t, e
     assert e["argmax"] >= 0.995, e
-    assert e["agg_l1"] <= 0.1 and e["step_l1"] <= 0.25, e
 
 
 def test_int8_unsupported_shape_and_round_trip(tmp_path):
@@ -367,6 +376,10 @@ def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
 
 
 # per-row gates of each scaled format against FP64 on its own operands (see the tests above)
+# Against plain FP64: (logits, aggregate L1, step L1) per scaled format.
+FP64_GATES = {"fp8": (2e-2, 0.12, 0.25), "int8": (5e-2, 0.1, 0.25),
+              **{f: MX_GATES[f]["fp64"] for f in ("mxfp8", "mxfp6", "mxfp4")}}
+
 ROW_GATES = {"int8": ("int8", (2.5e-2, 1e-2, 2e-3), (0.9, 1e-5)),
              "fp8": ("e4m3", (0.1, 0.05, 5e-3), (0.5, 1e-4)),
              "mxfp8": ("mxfp8", MX_GATES["mxfp8"]["worst"], MX_GATES["mxfp8"]["typical"]),
