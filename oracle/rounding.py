@@ -20,9 +20,13 @@ compared both with exact FP64 TabNet and with FP64 TabNet on the rounded operand
                   scale 2^X (an E8M0 byte) with X = floor(log2 max|v|) - emax_elem, and
                   each element is v / 2^X rounded to nearest even in the element format,
                   saturating at its largest normal.  Elements: E4M3 (MXFP8, emax 8, max
-                  448), E2M3 (MXFP6, emax 2, step 1/8 below 1, 3 stored mantissa bits
-                  from 1 up, max 7.5) and E2M1 (MXFP4, emax 2, grid 0, 0.5, 1, 1.5, 2,
-                  3, 4, 6).  X is
+                  448), E5M2 (MXFP8 in its other element form: exponent bias 15, 2 stored
+                  mantissa bits, smallest normal 2^-14, subnormal step 2^-16, emax 15,
+                  max 57344), E2M3 (MXFP6, emax 2, step 1/8 below 1, 3 stored mantissa
+                  bits from 1 up, max 7.5), E3M2 (MXFP6 in its other form: exponent bias
+                  3, 2 stored mantissa bits, smallest normal 1/4, step 1/16 below it,
+                  emax 4, max 28) and E2M1 (MXFP4, emax 2, grid 0, 0.5, 1, 1.5, 2, 3, 4,
+                  6).  X is
                   clamped to [-126, 127] (a block of zeros takes X = 0).  Which 32
                   positions of a K axis form a block is given by mx_block_of: the matrix
                   instruction that consumes these formats (128 K positions per operand
@@ -84,7 +88,33 @@ def round_int8_rows(x) -> np.ndarray:
 # ---- OCP MX block formats ----
 E2M1_MAX = 6.0
 E2M3_MAX = 7.5
-MX_ELEMENTS = {"mxfp8": (8, E4M3_MAX), "mxfp6": (2, E2M3_MAX), "mxfp4": (2, E2M1_MAX)}   # emax, largest normal
+E3M2_MAX = 28.0
+E5M2_MAX = 57344.0
+# element format of each MX format: (emax, largest normal)
+MX_ELEMENTS = {"mxfp8": (8, E4M3_MAX), "mxfp8_e5m2": (15, E5M2_MAX), "mxfp6": (2, E2M3_MAX),
+               "mxfp6_e3m2": (4, E3M2_MAX), "mxfp4": (2, E2M1_MAX)}
+# MX formats whose blocks are one lane group of eight tiles (the 4- and 6-bit element forms)
+MX_LANE_BLOCKS = ("mxfp6", "mxfp6_e3m2", "mxfp4")
+
+
+def round_e5m2(x) -> np.ndarray:
+    """Nearest float8 E5M2 value (ties to even), saturating at +-57344, as float64.  E5M2
+    has 3 significant bits from 2^-14 up (exponent bias 15) and a step of 2^-16 below."""
+    x = np.asarray(x, dtype=np.float64)
+    normal = _round_sig(x, 3)
+    sub = np.rint(x * 2.0 ** 16) * 2.0 ** -16
+    out = np.where(np.abs(x) < 2.0 ** -14, sub, normal)
+    return np.clip(out, -E5M2_MAX, E5M2_MAX)
+
+
+def round_e3m2(x) -> np.ndarray:
+    """Nearest FP6 E3M2 value (ties to even), saturating at +-28, as float64.  E3M2 has
+    3 significant bits from 1/4 up (exponent bias 3) and a step of 1/16 below 1/4."""
+    x = np.asarray(x, dtype=np.float64)
+    normal = _round_sig(x, 3)
+    sub = np.rint(x * 16.0) / 16.0
+    out = np.where(np.abs(x) < 0.25, sub, normal)
+    return np.clip(out, -E3M2_MAX, E3M2_MAX)
 
 
 def round_e2m3(x) -> np.ndarray:
@@ -108,19 +138,21 @@ def round_e2m1(x) -> np.ndarray:
 
 
 def _round_element(v, fmt):
-    return {"mxfp8": round_e4m3, "mxfp6": round_e2m3, "mxfp4": round_e2m1}[fmt](v)
+    return {"mxfp8": round_e4m3, "mxfp8_e5m2": round_e5m2, "mxfp6": round_e2m3, "mxfp6_e3m2": round_e3m2,
+            "mxfp4": round_e2m1}[fmt](v)
 
 
 def mx_block_of(p, fmt) -> np.ndarray:
     """Block index of K position p.  Positions run in 16-wide tiles t = p // 16, each made
     of four groups q = (p % 16) // 4; eight tiles (128 positions) form one operand row of
     the matrix instruction, k-block kb = t // 8, which holds four blocks:
-      mxfp4, mxfp6: block q  (group q of all eight tiles),
-      mxfp8:        block q // 2 + 2 * ((t % 8) // 4)  (groups 2 b', 2 b' + 1 of four tiles).
+      4- and 6-bit elements (mxfp4, mxfp6, mxfp6_e3m2): block q  (group q of all eight tiles),
+      8-bit elements (mxfp8, mxfp8_e5m2): block q // 2 + 2 * ((t % 8) // 4)  (groups 2 b',
+      2 b' + 1 of four tiles).
     Returns kb * 4 + block."""
     p = np.asarray(p)
     t, q = p // 16, (p % 16) // 4
-    within = q if fmt in ("mxfp4", "mxfp6") else q // 2 + 2 * ((t % 8) // 4)
+    within = q if fmt in MX_LANE_BLOCKS else q // 2 + 2 * ((t % 8) // 4)
     return (t // 8) * 4 + within
 
 

@@ -39,8 +39,8 @@ with s = gamma / sqrt(var + eps) (E4M3 with one scale per output channel,
 max|W'_n|/448; INT8 with one scale per output channel, max|W'_n|/127); acts in
 {None, "bf16", "e4m3", "int8"} act on each GEMM input (one scale per row, max|u_r|/448
 or max|u_r|/127).  The GEMM input of the attentive transformer is the attention half
-a = h[:, n_d:] alone, so its row scale is taken over those channels.  "mxfp8" / "mxfp6" / "mxfp4"
-(either operand) take OCP MX blocks of 32 K positions with one power-of-two scale each
+a = h[:, n_d:] alone, so its row scale is taken over those channels.  The MX formats
+"mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2" and "mxfp4" (either operand) take OCP MX blocks of 32 K positions with one power-of-two scale each
 (rounding.round_mx_rows), along K for both the weight rows and the input rows; the K
 position of a column is its index, except for the attention half, whose columns keep
 their place in h's 16-channel tiles (position = column + n_d mod 16).  The folded shift
@@ -53,7 +53,7 @@ import math
 
 import numpy as np
 
-from .rounding import round_bf16, round_e4m3, round_int8_rows, round_mx_rows, E4M3_MAX
+from .rounding import MX_ELEMENTS, round_bf16, round_e4m3, round_int8_rows, round_mx_rows, E4M3_MAX
 from .sparsemax import sparsemax
 
 SQRT_HALF = math.sqrt(0.5)
@@ -91,7 +91,7 @@ def _round_acts(u: np.ndarray, mode, k_offset: int = 0):
         return round_e4m3(u / scale) * scale
     if mode == "int8":
         return round_int8_rows(u)
-    if mode in ("mxfp8", "mxfp6", "mxfp4"):
+    if mode in MX_ELEMENTS:
         return round_mx_rows(u, mode, k_offset)
     raise ValueError(mode)
 
@@ -111,7 +111,7 @@ def _fc_bn(u: np.ndarray, W, bn: dict, eps: float, weights=None, acts=None, k_of
         Wf = round_e4m3(Wf / sc) * sc
     elif weights == "int8":
         Wf = round_int8_rows(Wf)
-    elif weights in ("mxfp8", "mxfp6", "mxfp4"):
+    elif weights in MX_ELEMENTS:
         Wf = round_mx_rows(Wf, weights, k_offset)
     elif weights is not None:
         raise ValueError(weights)

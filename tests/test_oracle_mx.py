@@ -1,12 +1,21 @@
-"""Pins for the oracle's OCP MX block formats (MXFP8 = E4M3 elements, MXFP4 = E2M1
-elements, one power-of-two scale per block of 32; CPU only)."""
+"""Pins for the oracle's OCP MX block formats (MXFP8 = E4M3 or E5M2 elements, MXFP6 =
+E2M3 or E3M2 elements, MXFP4 = E2M1 elements, one power-of-two scale per block of 32;
+CPU only)."""
 import numpy as np
 import pytest
 import torch
 
-from oracle.rounding import (E2M1_MAX, E2M3_MAX, mx_block_of, mx_scale_exponent, round_e2m1, round_e2m3,
-                             round_e4m3, round_mx_rows)
+from oracle.rounding import (E2M1_MAX, E2M3_MAX, E3M2_MAX, E5M2_MAX, mx_block_of, mx_scale_exponent, round_e2m1,
+                             round_e2m3, round_e3m2, round_e4m3, round_e5m2, round_mx_rows)
 from oracle import tabnet as ot
+
+FMTS = ["mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2", "mxfp4"]
+ROUND = {"mxfp8": round_e4m3, "mxfp8_e5m2": round_e5m2, "mxfp6": round_e2m3, "mxfp6_e3m2": round_e3m2,
+         "mxfp4": round_e2m1}
+# from the element formats' definitions: (emax, largest normal, stored mantissa bits)
+ELEM = {"mxfp8": (8, 448.0, 3), "mxfp8_e5m2": (15, 57344.0, 2), "mxfp6": (2, 7.5, 3), "mxfp6_e3m2": (4, 28.0, 2),
+        "mxfp4": (2, 6.0, 1)}
+LANE_BLOCKS = ("mxfp4", "mxfp6", "mxfp6_e3m2")    # 4- and 6-bit elements: 32 slots per lane group
 
 
 def e2m1_table():
@@ -60,22 +69,67 @@ def test_e2m3_grid_and_brute_force_rounding():
         assert g == np.copysign(pos[code], v), (v, g, pos[code])
 
 
+def e3m2_table():
+    """All 32 FP6 E3M2 magnitudes decoded from the bit fields: 3-bit exponent (bias 3),
+    2-bit mantissa; exponent 0 is subnormal (m / 4 * 2^-2)."""
+    vals = []
+    for c in range(32):
+        e, m = c >> 2, c & 3
+        vals.append(m / 16.0 if e == 0 else (1 + m / 4.0) * 2.0 ** (e - 3))
+    return np.array(vals)
+
+
+def test_e3m2_grid_and_brute_force_rounding():
+    pos = e3m2_table()
+    assert pos.max() == E3M2_MAX and len(set(pos)) == 32 and pos[1] == 1 / 16 and pos[4] == 0.25
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.uniform(-33, 33, 5000), rng.uniform(-0.6, 0.6, 3000), np.arange(-30, 30.01, 1 / 32),
+                        [0.0, 100.0, -100.0]])
+    got = round_e3m2(x)
+    for v, g in zip(x, got):
+        a = min(abs(v), E3M2_MAX)
+        d = np.abs(pos - a)
+        best = np.flatnonzero(d == d.min())
+        code = best[0] if len(best) == 1 else [b for b in best if b % 2 == 0][0]   # ties: even code
+        assert g == np.copysign(pos[code], v), (v, g, pos[code])
+
+
+def test_e5m2_matches_torch_and_saturates():
+    """torch's float8_e5m2 decodes every code and rounds float32 values to nearest even;
+    its cast does not saturate (from 61440 up it gives inf), the oracle's does."""
+    codes = torch.arange(256, dtype=torch.int32).to(torch.uint8).view(torch.float8_e5m2).to(torch.float64).numpy()
+    fin = np.unique(codes[np.isfinite(codes)])
+    np.testing.assert_array_equal(round_e5m2(fin), fin)            # every finite code is on the grid
+    assert fin.max() == E5M2_MAX and np.abs(fin[fin != 0]).min() == 2.0 ** -16
+    mid = (fin[:-1] + fin[1:]) / 2                                  # ties between neighbours
+    rng = np.random.default_rng(7)
+    n = 20000
+    wide = np.ldexp(rng.uniform(1, 2, n), rng.integers(-20, 17, n)) * rng.choice([-1.0, 1.0], n)
+    x = np.concatenate([wide, mid, fin]).astype(np.float32).astype(np.float64)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.float8_e5m2).to(torch.float64).numpy()
+    ok = np.isfinite(ref)
+    np.testing.assert_array_equal(round_e5m2(x[ok]), ref[ok])
+    assert (np.abs(x[~ok]) >= 61440).all() and (~ok).any()
+    np.testing.assert_array_equal(round_e5m2(np.array([61440.0, 1e6, -7e4])), [E5M2_MAX, E5M2_MAX, -E5M2_MAX])
+
+
 def slot_block(p, fmt):
     """The block of K position p derived from the matrix instruction's operand layout (a
     row of 128 K slots over 4 lane groups of 32 elements; blocks are 32 consecutive
     slots).  The position's lane group is q = (p % 16) // 4 and its element within the
     lane e = 4 * (t % 8) + p % 4 for tile t = p // 16.  MXFP4 and MXFP6 lanes hold slots 32 q + e;
-    MXFP8 lanes hold slots 16 q + e for e < 16 and 64 + 16 q + (e - 16) for the rest."""
+    MXFP8 lanes (either element form) hold slots 16 q + e for e < 16 and 64 + 16 q + (e - 16)
+    for the rest."""
     t, q = p // 16, (p % 16) // 4
     e = 4 * (t % 8) + p % 4
-    if fmt in ("mxfp4", "mxfp6"):
+    if fmt in LANE_BLOCKS:
         slot = 32 * q + e
     else:
         slot = 16 * q + e if e < 16 else 64 + 16 * q + (e - 16)
     return (t // 8) * 4 + slot // 32
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("fmt", FMTS)
 def test_block_partition_matches_instruction_layout(fmt):
     p = np.arange(512)
     got = mx_block_of(p, fmt)
@@ -93,7 +147,8 @@ def test_scale_exponent_ocp_rule():
     assert X8[6] == 0 and X4[6] == 0
     assert X8[7] == 127 - 8 and X8[8] == -126     # clamped below
     # the block maximum lands in [2^emax, 2^(emax + 1)) after scaling
-    for fmt, emax in (("mxfp8", 8), ("mxfp4", 2)):
+    for fmt in FMTS:
+        emax = ELEM[fmt][0]
         a = np.abs(np.random.default_rng(2).normal(0, 5, 1000)) + 1e-3
         r = a / np.ldexp(1.0, mx_scale_exponent(a, fmt))
         assert ((r >= 2.0 ** emax) & (r < 2.0 ** (emax + 1))).all()
@@ -104,7 +159,7 @@ def brute_mx(x, fmt, offset):
     then round (pure Python loops over a small matrix)."""
     rows, K = x.shape
     out = np.zeros_like(x)
-    emax, vmax = {"mxfp8": (8, 448.0), "mxfp6": (2, 7.5), "mxfp4": (2, 6.0)}[fmt]
+    emax, vmax, _ = ELEM[fmt]
     for r in range(rows):
         for j in range(K):
             b = slot_block(j + offset, fmt)
@@ -116,13 +171,12 @@ def brute_mx(x, fmt, offset):
             X = int(np.floor(np.log2(m))) - emax
             X = min(max(X, -126), 127)
             v = x[r, j] / 2.0 ** X
-            rnd = {"mxfp8": round_e4m3, "mxfp6": round_e2m3, "mxfp4": round_e2m1}[fmt]
-            v = float(rnd(np.array([v]))[0])
+            v = float(ROUND[fmt](np.array([v]))[0])
             out[r, j] = max(-vmax, min(vmax, v)) * 2.0 ** X
     return out
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("K,offset", [(35, 0), (108, 0), (24, 8), (64, 0)])
 def test_round_mx_rows_matches_brute_force(fmt, K, offset):
     rng = np.random.default_rng(K + offset)
@@ -152,7 +206,7 @@ def test_mxfp8_elements_match_torch_e4m3_and_saturate():
     assert r[0, 0] == 448.0 and r[0, 1] == 1.0
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("fmt", FMTS)
 def test_mx_exact_on_grid_and_scale_equivariant(fmt):
     rng = np.random.default_rng(4)
     x = rng.normal(0, 1, (6, 100))
@@ -163,11 +217,11 @@ def test_mx_exact_on_grid_and_scale_equivariant(fmt):
     # per element: within half a step of the grid at the block's scale (the step of the
     # top binade [2^emax, 2^(emax+1)) bounds all), or saturated at the largest normal
     blk = mx_block_of(np.arange(100), fmt)
-    vmax = {"mxfp8": 448.0, "mxfp6": E2M3_MAX, "mxfp4": E2M1_MAX}[fmt]
+    emax, vmax, mbits = ELEM[fmt]
     for b in np.unique(blk):
         cols = blk == b
         sc = np.ldexp(1.0, mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), fmt))
-        step = sc * {"mxfp8": 2.0 ** (8 - 3), "mxfp6": 2.0 ** (2 - 3), "mxfp4": 2.0 ** (2 - 1)}[fmt]
+        step = sc * 2.0 ** (emax - mbits)
         err = np.abs(r[:, cols] - x[:, cols])
         sat = (np.abs(x[:, cols]) > vmax * sc) & (np.abs(r[:, cols]) == vmax * sc)
         assert ((err <= step / 2 * (1 + 1e-12)) | sat).all()
