@@ -320,9 +320,10 @@ def main():
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
-    ap.add_argument("--quant", default="fp8,int8,mxfp8,mxfp6,mxfp4",
+    ap.add_argument("--quant", default="fp8,int8,mxfp8,mxfp8_e5m2,mxfp6,mxfp6_e3m2,mxfp4",
                     help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights and GEMM inputs; int8: "
-                         "INT8 weights and GEMM inputs; mxfp8 / mxfp6 / mxfp4: OCP MX on both GEMM operands); "
+                         "INT8 weights and GEMM inputs; mxfp8, mxfp8_e5m2, mxfp6, mxfp6_e3m2, mxfp4: OCP MX on both GEMM "
+                         "operands); "
                          "empty to skip")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
                     help="request rates (req/s) of the serving leg; empty to skip")
@@ -474,8 +475,12 @@ def main():
                                 "per row), INT32 products"),
                        ("mxfp8", "OCP MXFP8 (E4M3 elements, E8M0 scale per 32) on both GEMM operands, "
                                  "scaled MFMA"),
+                       ("mxfp8_e5m2", "OCP MXFP8 with E5M2 elements (E8M0 scale per 32) on both GEMM "
+                                      "operands, scaled MFMA"),
                        ("mxfp6", "OCP MXFP6 (E2M3 elements, E8M0 scale per 32) on both GEMM operands, "
                                  "scaled MFMA"),
+                       ("mxfp6_e3m2", "OCP MXFP6 with E3M2 elements (E8M0 scale per 32) on both GEMM "
+                                      "operands, scaled MFMA"),
                        ("mxfp4", "OCP MXFP4 (E2M1 elements, E8M0 scale per 32) on both GEMM operands, "
                                  "scaled MFMA")):
         if prec in res:

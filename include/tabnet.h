@@ -49,7 +49,9 @@ typedef enum {
     TABNET_INT8 = 3,      /* INT8 weights and GEMM inputs, INT32 products; see below      */
     TABNET_MXFP8 = 4,     /* OCP MX: E4M3 elements in blocks of 32 with E8M0 scales       */
     TABNET_MXFP4 = 5,     /* OCP MX: E2M1 elements in blocks of 32 with E8M0 scales       */
-    TABNET_MXFP6 = 6      /* OCP MX: E2M3 elements in blocks of 32 with E8M0 scales       */
+    TABNET_MXFP6 = 6,     /* OCP MX: E2M3 elements in blocks of 32 with E8M0 scales       */
+    TABNET_MXFP8_E5M2 = 7,  /* OCP MX: E5M2 elements in blocks of 32 with E8M0 scales     */
+    TABNET_MXFP6_E3M2 = 8   /* OCP MX: E3M2 elements in blocks of 32 with E8M0 scales     */
 } tabnet_precision;
 
 /* Model hyper-parameters as stored in the weight file.  N = n_d + n_a. */
@@ -104,16 +106,18 @@ typedef struct tabnet_handle tabnet_handle;
  * model served by the split-feature kernel (the 512-feature shape) is TABNET_E_UNSUPPORTED
  * in these formats.
  *
- * TABNET_MXFP8 / TABNET_MXFP6 / TABNET_MXFP4 put both operands of every GEMM in an OCP
- * microscaling format: along K, blocks of 32 values share one power-of-two scale 2^X
- * (E8M0) with X = floor(log2 max|v|) - emax (8 for E4M3, 2 for E2M3 and E2M1), and each
- * value is stored as v / 2^X rounded to nearest even in the element format, saturating
- * (+-448, +-7.5, +-6).  The
+ * TABNET_MXFP8 / TABNET_MXFP8_E5M2 / TABNET_MXFP6 / TABNET_MXFP6_E3M2 / TABNET_MXFP4 put
+ * both operands of every GEMM in an OCP microscaling format: along K, blocks of 32 values
+ * share one power-of-two scale 2^X (E8M0) with X = floor(log2 max|v|) - emax (8 for
+ * E4M3, 15 for E5M2, 2 for E2M3 and E2M1, 4 for E3M2), and each value is stored as
+ * v / 2^X rounded to nearest even in the element format, saturating (+-448, +-57344,
+ * +-7.5, +-28, +-6).  The
  * weights are coded at load, each GEMM input row in the kernel; the gfx950 scaled matrix
  * instruction applies both scales, and everything else stays in FP32.  A block is the
  * 32 K positions the instruction groups together: with K positions in 16-wide tiles of
- * four 4-wide groups q and eight tiles per instruction, an MXFP4 or MXFP6 block is group q of the
- * eight tiles, an MXFP8 block groups 2b and 2b+1 of four consecutive tiles.  The
+ * four 4-wide groups q and eight tiles per instruction, a block of 4- or 6-bit elements
+ * is group q of the eight tiles, a block of 8-bit elements groups 2b and 2b+1 of four
+ * consecutive tiles.  The
  * attentive transformer's input keeps the channel positions of the hidden state's
  * tiles.  Same kernel coverage and non-finite behaviour as TABNET_INT8.
  */

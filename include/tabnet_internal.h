@@ -26,6 +26,10 @@ uint8_t tabnet_hook_e4m3_bits(double x);
 uint8_t tabnet_hook_e2m1_bits(double x);
 /* FP6 E2M3 bits (sign in bit 5) of x, round to nearest even, saturating at +-7.5. */
 uint8_t tabnet_hook_e2m3_bits(double x);
+/* float8 E5M2 bits of x, round to nearest even, saturating at +-57344. */
+uint8_t tabnet_hook_e5m2_bits(double x);
+/* FP6 E3M2 bits (sign in bit 5) of x, round to nearest even, saturating at +-28. */
+uint8_t tabnet_hook_e3m2_bits(double x);
 /* OCP MX shared exponent of a block with largest magnitude amax for an element format
  * with largest exponent emax: floor(log2 amax) - emax, clamped to [-126, 127]; 0 for 0. */
 int tabnet_hook_mx_exponent(double amax, int emax);

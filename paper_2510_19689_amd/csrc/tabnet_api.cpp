@@ -76,7 +76,7 @@ const char* tabnet_last_error(void) { return g_err.c_str(); }
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out) {
   if (out == nullptr || path == nullptr) return fail(TABNET_E_INVALID, "tabnet_load: NULL argument");
   *out = nullptr;
-  if (precision < TABNET_FP32 || precision > TABNET_MXFP6)
+  if (precision < TABNET_FP32 || precision > TABNET_MXFP6_E3M2)
     return fail(TABNET_E_INVALID, "tabnet_load: unknown precision");
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(TABNET_E_IO, std::string("tabnet_load: cannot open ") + path);

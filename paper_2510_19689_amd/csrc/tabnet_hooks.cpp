@@ -15,6 +15,8 @@ uint16_t tabnet_hook_bf16_bits(double x) { return bf16_bits_rne(x); }
 uint8_t tabnet_hook_e4m3_bits(double x) { return e4m3_bits_rne(x); }
 uint8_t tabnet_hook_e2m1_bits(double x) { return e2m1_bits_rne(x); }
 uint8_t tabnet_hook_e2m3_bits(double x) { return e2m3_bits_rne(x); }
+uint8_t tabnet_hook_e5m2_bits(double x) { return e5m2_bits_rne(x); }
+uint8_t tabnet_hook_e3m2_bits(double x) { return e3m2_bits_rne(x); }
 int tabnet_hook_mx_exponent(double amax, int emax) { return mx_exponent(amax, emax); }
 
 void tabnet_hook_int8_rows(double* W, int rows, int cols, double* scales) {
@@ -64,7 +66,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   std::string err;
   tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
   if (st != TABNET_OK) return st;
-  if (precision < TABNET_FP32 || precision > TABNET_MXFP6) return TABNET_E_INVALID;
+  if (precision < TABNET_FP32 || precision > TABNET_MXFP6_E3M2) return TABNET_E_INVALID;
   const Shape sh = shape_of(m.cfg);
   const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);
   if (!k) return TABNET_E_UNSUPPORTED;

@@ -221,21 +221,23 @@ __device__ __forceinline__ int mx_exponent(float amax) {
   return amax > 0.f ? (X < -126 ? -126 : (X > 127 ? 127 : X)) : 0;
 }
 
-// MXFP8: per row block and k-block (eight K tiles), 32 E4M3 elements (element 4 tt + i =
-// feature 16 (8 kb + tt) + 4 g + i, four to a dword) and the E8M0 scale this lane
-// supplies to the instruction.  Tiles 0-3 of the k-block form, with the partner lane
+// MXFP8: per row block and k-block (eight K tiles), 32 8-bit elements, E4M3 (E5M2 when
+// E5M2 is set) (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i, four to a dword) and the E8M0
+// scale this lane supplies to the instruction.  Tiles 0-3 of the k-block form, with the partner lane
 // group (g ^ 1), block g / 2; tiles 4-7 block 2 + g / 2.  The instruction reads block b's
 // scale from lane group b: groups 0 and 3 own the blocks they supply, group 1 supplies
 // block 1 (tiles 0-3 of groups 2 and 3) and group 2 block 2 (tiles 4-7 of groups 0 and
-// 1), each received from the lane 32 away.  Elements are v / 2^X, clamped to +-448 and
-// rounded to nearest even.
-template <int KT, int R>
-struct BOp<4, KT, R> {
+// 1), each received from the lane 32 away.  Elements are v / 2^X, clamped to the largest
+// normal (+-448, E5M2 +-57344) and rounded to nearest even.
+template <int KT, int R, bool E5M2>
+struct MxF8Op {
   static constexpr int KB = kblocks(4, KT);
   uint32_t v[R][KB][8];
   uint32_t sc[R][KB];
   template <class F>
   __device__ __forceinline__ void build(F src) {
+    constexpr int kEmax = E5M2 ? 15 : 8;
+    constexpr float kMax = E5M2 ? 57344.0f : 448.0f;
     const int g = ((int)threadIdx.x >> 4) & 3;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
@@ -249,20 +251,25 @@ struct BOp<4, KT, R> {
             for (int i = 0; i < 4; ++i) a[tt >> 2] = fmaxf(a[tt >> 2], fabsf(src(rb, 8 * kb + tt, i)));
         int X[2];
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) X[hf] = mx_exponent<8>(pair16_max(a[hf]));
+        for (int hf = 0; hf < 2; ++hf) X[hf] = mx_exponent<kEmax>(pair16_max(a[hf]));
 #pragma unroll
         for (int tt = 0; tt < 8; ++tt) {
           const int t = 8 * kb + tt;
           if (t < KT) {
             const float scale = __builtin_amdgcn_ldexpf(1.0f, X[tt >> 2]);
-            const float lim = 448.0f * scale;
+            const float lim = kMax * scale;
             float c[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_fmed3f(src(rb, t, i), -lim, lim);
             typedef short sh2 __attribute__((ext_vector_type(2)));
             sh2 w = {0, 0};
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[0], c[1], scale, false);
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[2], c[3], scale, true);
+            if constexpr (E5M2) {
+              w = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(w, c[0], c[1], scale, false);
+              w = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(w, c[2], c[3], scale, true);
+            } else {
+              w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[0], c[1], scale, false);
+              w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[2], c[3], scale, true);
+            }
             v[rb][kb][tt] = __builtin_bit_cast(uint32_t, w);
           } else {
             v[rb][kb][tt] = 0u;
@@ -276,6 +283,10 @@ struct BOp<4, KT, R> {
       }
   }
 };
+template <int KT, int R>
+struct BOp<4, KT, R> : MxF8Op<KT, R, false> {};
+template <int KT, int R>
+struct BOp<7, KT, R> : MxF8Op<KT, R, true> {};
 
 // MXFP4: per row block and k-block, 32 E2M1 elements (element 4 tt + i in nibble
 // 4 tt + i, eight to a dword) forming one block, the lane's own, with its E8M0 scale.
@@ -323,15 +334,15 @@ struct BOp<5, KT, R> {
   }
 };
 
-// MXFP6: per row block and k-block, 32 E2M3 elements forming one block, the lane's own
-// (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i in bits 6 e .. 6 e + 5 of six dwords),
-// with its E8M0 scale.  The conversion takes two vectors of 16 values and interleaves them
-// (element 2 j from the first, 2 j + 1 from the second), rounds v / 2^X to nearest even and
-// saturates at +-7.5.  It writes its result while it still reads its sources, so the
+// MXFP6: per row block and k-block, 32 6-bit elements, E2M3 (E3M2 when E3M2 is set),
+// forming one block, the lane's own (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i in bits
+// 6 e .. 6 e + 5 of six dwords), with its E8M0 scale.  The conversion takes two vectors of
+// 16 values and interleaves them (element 2 j from the first, 2 j + 1 from the second),
+// rounds v / 2^X to nearest even and saturates (+-7.5, E3M2 +-28).  It writes its result while it still reads its sources, so the
 // result must not share registers with them: the instruction is issued with an
 // early-clobber result operand (the builtin's register allocation allows the overlap).
-template <int KT, int R>
-struct BOp<6, KT, R> {
+template <int KT, int R, bool E3M2>
+struct MxF6Op {
   static constexpr int KB = kblocks(6, KT);
   uint32_t v[R][KB][6];
   uint32_t sc[R][KB];
@@ -358,18 +369,25 @@ struct BOp<6, KT, R> {
               m0 = fmaxf(m0, fabsf(x));
             }
           }
-        const int X = mx_exponent<2>(fmaxf(m0, m1));
+        const int X = mx_exponent<E3M2 ? 4 : 2>(fmaxf(m0, m1));
         const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
         typedef unsigned u6v __attribute__((ext_vector_type(6)));
         u6v r;
         // early-clobber result: the destination registers may not overlap a, b or scale
-        asm("v_cvt_scalef32_2xpk16_fp6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
+        if constexpr (E3M2)
+          asm("v_cvt_scalef32_2xpk16_bf6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
+        else
+          asm("v_cvt_scalef32_2xpk16_fp6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
 #pragma unroll
         for (int d = 0; d < 6; ++d) v[rb][kb][d] = r[d];
         sc[rb][kb] = (uint32_t)(X + 127);
       }
   }
 };
+template <int KT, int R>
+struct BOp<6, KT, R> : MxF6Op<KT, R, false> {};
+template <int KT, int R>
+struct BOp<8, KT, R> : MxF6Op<KT, R, true> {};
 
 // acc[rb] += W(one output tile, all K) * B[rb] with both operands in an MX format: one
 // 16x16x128 scaled MFMA per k-block, the block scales applied inside the instruction.
@@ -377,16 +395,17 @@ template <int PREC, int KT, int R>
 __device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<PREC, KT, R>& b, f4 (&acc)[R],
                                             int lane) {
   constexpr int KB = kblocks(PREC, KT);
-  constexpr int FMT = PREC == 4 ? 0 : (PREC == 6 ? 2 : 4);   // E4M3, E2M3 or E2M1 elements
-  constexpr int ND = PREC == 4 ? 8 : (PREC == 6 ? 6 : 4);    // operand dwords per lane
+  // element format code: E4M3 0, E5M2 1, E2M3 2, E3M2 3, E2M1 4
+  constexpr int FMT = PREC == 4 ? 0 : (PREC == 7 ? 1 : (PREC == 6 ? 2 : (PREC == 8 ? 3 : 4)));
+  constexpr int ND = is_mx8(PREC) ? 8 : (is_mx6(PREC) ? 6 : 4);   // operand dwords per lane
   constexpr int EL = kbytes(PREC) - kMxScaleBytes;            // element bytes per k-block
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     const unsigned char* f = fr + kb * kbytes(PREC);
     const i4 lo = *reinterpret_cast<const i4*>(f + lane * 16);
     i4 hi = {0, 0, 0, 0};
-    if constexpr (PREC == 4) hi = *reinterpret_cast<const i4*>(f + kFrag + lane * 16);
-    if constexpr (PREC == 6) {
+    if constexpr (is_mx8(PREC)) hi = *reinterpret_cast<const i4*>(f + kFrag + lane * 16);
+    if constexpr (is_mx6(PREC)) {
       const uint2 m = *reinterpret_cast<const uint2*>(f + kFrag + lane * 8);
       hi = i4{(int)m.x, (int)m.y, 0, 0};
     }
@@ -1601,6 +1620,7 @@ struct KernelEntry {
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
                                        TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
+                                       TABNET_SHAPES(7) TABNET_SHAPES(8)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
 

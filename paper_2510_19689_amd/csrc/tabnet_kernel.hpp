@@ -81,7 +81,10 @@ struct GemmPlan {
   int nchunks;
 };
 
-// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (MXFP8, MXFP4, MXFP6)
+// MX precisions by element width: 8-bit (E4M3, E5M2) and 6-bit (E2M3, E3M2) elements
+constexpr bool is_mx8(int prec) { return prec == 4 || prec == 7; }
+constexpr bool is_mx6(int prec) { return prec == 6 || prec == 8; }
+// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (every MX format)
 constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 1 ? 2 : (prec <= 3 ? 4 : 8)); }
 constexpr int kblocks(int prec, int KT) {
   return (KT + ktiles_per_block(prec) - 1) / ktiles_per_block(prec);
@@ -89,8 +92,8 @@ constexpr int kblocks(int prec, int KT) {
 // Bytes of one k-block of one output tile: a fragment, or the MX elements and scales.
 constexpr int kMxScaleBytes = 256;
 constexpr int kbytes(int prec) {
-  return prec == 4 ? 2 * kFrag + kMxScaleBytes
-                   : (prec == 5 ? kFrag + kMxScaleBytes : (prec == 6 ? kFrag + kFrag / 2 + kMxScaleBytes : kFrag));
+  return is_mx8(prec) ? 2 * kFrag + kMxScaleBytes
+                      : (prec == 5 ? kFrag + kMxScaleBytes : (is_mx6(prec) ? kFrag + kFrag / 2 + kMxScaleBytes : kFrag));
 }
 // Per-output scales after the shifts (E4M3, INT8)
 constexpr bool has_channel_scales(int prec) { return prec == 2 || prec == 3; }

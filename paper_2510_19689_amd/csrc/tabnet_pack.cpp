@@ -280,6 +280,43 @@ uint8_t e2m3_bits_rne(double x) {
   return sign | (uint8_t)code;
 }
 
+// FP8 E5M2: bias 15, 2 stored mantissa bits, normals from 2^-14, subnormals k * 2^-16,
+// largest finite 57344 (S.11110.11); values beyond saturate to +-57344.
+uint8_t e5m2_bits_rne(double x) {
+  const uint8_t sign = std::signbit(x) ? 0x80 : 0;
+  const double ax = std::fabs(x);
+  if (std::isnan(x)) return 0x7f;
+  if (ax >= 57344.0) return sign | 0x7b;
+  if (ax < std::ldexp(1.0, -14)) return sign | (uint8_t)std::nearbyint(std::ldexp(ax, 16));   // 4 = 2^-14
+  int e;
+  const double m = std::frexp(ax, &e);                     // ax = m 2^e, m in [0.5, 1)
+  double q = std::nearbyint(std::ldexp(m, 3));              // 4..8
+  if (q == 8.0) {
+    q = 4.0;
+    ++e;
+  }
+  const int eb = (e - 1) + 15;
+  if (eb > 30) return sign | 0x7b;
+  return sign | (uint8_t)((eb << 2) | ((int)q - 4));
+}
+
+// FP6 E3M2 bits (sign in bit 5) of x, round to nearest even, saturating at +-28.  Below
+// 1/2 the grid has a step of 1/16 (subnormals up to 3/16, then the binade [1/4, 1/2));
+// each binade [2^k, 2^(k+1)) above has a step of 2^(k-2).  The code is the rounded
+// multiple plus the even offset 4 k + 8, so ties to the even multiple are ties to the
+// even code.
+uint8_t e3m2_bits_rne(double x) {
+  const uint8_t sign = std::signbit(x) ? 32 : 0;
+  const double a = std::fabs(x);
+  if (std::isnan(x)) return 31;
+  if (a >= 28.0) return sign | 31;
+  int e = 0;
+  if (a >= 0.5) std::frexp(a, &e);                          // a = m 2^e, m in [0.5, 1)
+  const int k = a >= 0.5 ? e - 1 : -2;
+  const int code = (int)std::nearbyint(std::ldexp(a, 2 - k)) + 4 * k + 8;
+  return sign | (uint8_t)std::min(31, code);
+}
+
 int mx_exponent(double amax, int emax) {
   if (!(amax > 0)) return 0;
   int e;
@@ -326,11 +363,17 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         for (int r = 0; r < 4; ++r) v[r] = (float)wv(i, 16 * kt + 4 * q + r);
         emit(wts, v, sizeof v);
       }
-  } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP4 || precision == TABNET_MXFP6) {
+  } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP8_E5M2 || precision == TABNET_MXFP4 ||
+             precision == TABNET_MXFP6 || precision == TABNET_MXFP6_E3M2) {
     // Per k-block of eight K tiles: the E8M0 exponent of each of an output row's four
     // blocks, then the elements lane by lane, then the scale each lane supplies (the
-    // instruction takes block b's scale from lane group b).
-    const bool f8 = precision == TABNET_MXFP8;
+    // instruction takes block b's scale from lane group b).  The two 8-bit element forms
+    // share one layout, and so do the two 6-bit forms.
+    const bool f8 = precision == TABNET_MXFP8 || precision == TABNET_MXFP8_E5M2;
+    const bool f6 = precision == TABNET_MXFP6 || precision == TABNET_MXFP6_E3M2;
+    const int emax = precision == TABNET_MXFP8 ? 8 : (precision == TABNET_MXFP8_E5M2 ? 15 : (precision == TABNET_MXFP6_E3M2 ? 4 : 2));
+    uint8_t (*const enc8)(double) = precision == TABNET_MXFP8 ? e4m3_bits_rne : e5m2_bits_rne;
+    uint8_t (*const enc6)(double) = precision == TABNET_MXFP6 ? e2m3_bits_rne : e3m2_bits_rne;
     const int KB = (KT + 7) / 8;
     auto block_of = [&](int tt, int q) { return f8 ? q / 2 + 2 * (tt / 4) : q; };
     auto val = [&](int i, int kb, int tt, int q, int j) {
@@ -347,7 +390,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
               double& a = amax[block_of(tt, q)];
               a = std::fmax(a, std::fabs(val(i, kb, tt, q, j)));
             }
-        for (int b = 0; b < 4; ++b) X[i][b] = mx_exponent(amax[b], f8 ? 8 : 2);
+        for (int b = 0; b < 4; ++b) X[i][b] = mx_exponent(amax[b], emax);
       }
       if (f8) {
         for (int half = 0; half < 2; ++half)
@@ -356,11 +399,11 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
             uint8_t v[16];
             for (int e = 16 * half; e < 16 * half + 16; ++e) {
               const int tt = e / 4, j = e % 4;
-              v[e - 16 * half] = e4m3_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][block_of(tt, q)]));
+              v[e - 16 * half] = enc8(std::ldexp(val(i, kb, tt, q, j), -X[i][block_of(tt, q)]));
             }
             emit(wts, v, sizeof v);
           }
-      } else if (precision == TABNET_MXFP6) {
+      } else if (f6) {
         // 32 six-bit elements per lane, element e in bits 6 e .. 6 e + 5 of 24 bytes:
         // bytes 0-15 of every lane, then bytes 16-23 of every lane
         uint8_t bytes[64][24];
@@ -369,7 +412,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
           uint64_t w[3] = {0, 0, 0};
           for (int e = 0; e < 32; ++e) {
             const int tt = e / 4, j = e % 4;
-            const uint64_t c = e2m3_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
+            const uint64_t c = enc6(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
             const int bit = 6 * e;
             w[bit / 64] |= c << (bit % 64);
             if (bit % 64 > 58) w[bit / 64 + 1] |= c >> (64 - bit % 64);

@@ -46,6 +46,10 @@ uint8_t e4m3_bits_rne(double x);
 uint8_t e2m1_bits_rne(double x);
 // FP6 E2M3 bits of a double (round to nearest even, saturating at +-7.5).
 uint8_t e2m3_bits_rne(double x);
+// FP8 E5M2 and FP6 E3M2 bits of a double (round to nearest even, saturating at +-57344
+// and +-28).
+uint8_t e5m2_bits_rne(double x);
+uint8_t e3m2_bits_rne(double x);
 int mx_exponent(double amax, int emax);
 double bf16_value(uint16_t bits);
 double e4m3_value(uint8_t bits);

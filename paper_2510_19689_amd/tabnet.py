@@ -15,9 +15,9 @@ LIB_PATH = os.environ.get("TABNET_LIB") or os.path.join(HERE, "libtabnet.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_IO, E_ADMISSION, E_TIMEOUT, E_STOPPED, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
-FP32, BF16, FP8_E4M3, INT8, MXFP8, MXFP4, MXFP6 = 0, 1, 2, 3, 4, 5, 6
+FP32, BF16, FP8_E4M3, INT8, MXFP8, MXFP4, MXFP6, MXFP8_E5M2, MXFP6_E3M2 = 0, 1, 2, 3, 4, 5, 6, 7, 8
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "int8": INT8, "mxfp8": MXFP8, "mxfp4": MXFP4,
-              "mxfp6": MXFP6}
+              "mxfp6": MXFP6, "mxfp8_e5m2": MXFP8_E5M2, "mxfp6_e3m2": MXFP6_E3M2}
 
 
 class TabNetError(RuntimeError):
@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
     L.tabnet_hook_e2m1_bits.restype = ctypes.c_uint8
     L.tabnet_hook_e2m3_bits.argtypes = [ctypes.c_double]
     L.tabnet_hook_e2m3_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e5m2_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e5m2_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e3m2_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e3m2_bits.restype = ctypes.c_uint8
     L.tabnet_hook_mx_exponent.argtypes = [ctypes.c_double, i32]
     L.tabnet_hook_mx_exponent.restype = i32
     L.tabnet_hook_int8_rows.argtypes = [vp, i32, i32, vp]

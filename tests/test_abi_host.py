@@ -50,7 +50,8 @@ def test_missing_and_bad_files(tmp_path, L):
     trunc = tmp_path / "trunc.tnw"
     trunc.write_bytes(raw[:-8])
     assert L.tabnet_load(str(trunc).encode(), 0, 0, ctypes.byref(h)) == tb.E_IO
-    assert L.tabnet_load(str(trunc).encode(), 7, 0, ctypes.byref(h)) == tb.E_INVALID
+    assert L.tabnet_load(str(trunc).encode(), 9, 0, ctypes.byref(h)) == tb.E_INVALID
+    assert L.tabnet_load(str(trunc).encode(), -1, 0, ctypes.byref(h)) == tb.E_INVALID
     assert L.tabnet_load(None, 0, 0, ctypes.byref(h)) == tb.E_INVALID
 
 
@@ -115,7 +116,8 @@ def test_rounding_hooks_match_torch(L):
 
 
 def test_mx_encoders_match_oracle(L):
-    """The packer's E2M1 and E2M3 encoders and MX exponent rule against the oracle's."""
+    """The packer's E2M1, E2M3, E3M2 and E5M2 encoders and MX exponent rule against the
+    oracle's (codes decoded from their bit fields here)."""
     from oracle.rounding import mx_scale_exponent, round_e2m1
     rng = np.random.default_rng(9)
     x = np.concatenate([rng.uniform(-8, 8, 3000), np.arange(-7, 7.01, 0.25), [0.0, -0.0, 100.0, -1e-3]])
@@ -128,8 +130,28 @@ def test_mx_encoders_match_oracle(L):
     x6 = np.concatenate([rng.uniform(-9, 9, 3000), np.arange(-8, 8.01, 1 / 16), [0.0, -0.0, 100.0]])
     got6 = np.array([t6[L.tabnet_hook_e2m3_bits(float(v))] for v in x6])
     np.testing.assert_array_equal(got6, round_e2m3(x6))
+    from oracle.rounding import round_e3m2, round_e5m2
+
+    def e3m2(c):     # sign bit 5, exponent bits 4-2 (bias 3), mantissa bits 1-0
+        e, m = (c >> 2) & 7, c & 3
+        v = m / 16.0 if e == 0 else (1 + m / 4.0) * 2.0 ** (e - 3)
+        return -v if c & 32 else v
+
+    def e5m2(c):     # sign bit 7, exponent bits 6-2 (bias 15), mantissa bits 1-0
+        e, m = (c >> 2) & 31, c & 3
+        v = m * 2.0 ** -16 if e == 0 else (1 + m / 4.0) * 2.0 ** (e - 15)
+        return -v if c & 128 else v
+    x3 = np.concatenate([rng.uniform(-33, 33, 3000), rng.uniform(-0.6, 0.6, 2000), np.arange(-30, 30.01, 1 / 32),
+                         [0.0, -0.0, 100.0, -1e9]])
+    got3 = np.array([e3m2(L.tabnet_hook_e3m2_bits(float(v))) for v in x3])
+    np.testing.assert_array_equal(got3, round_e3m2(x3))
+    x5 = np.concatenate([np.ldexp(rng.uniform(-2, 2, 5000), rng.integers(-20, 17, 5000)),
+                         [0.0, -0.0, 61440.0, -61439.0, 1e9, 2.0 ** -17, 3 * 2.0 ** -17]])
+    got5 = np.array([e5m2(L.tabnet_hook_e5m2_bits(float(v))) for v in x5])
+    np.testing.assert_array_equal(got5, round_e5m2(x5))
+    assert L.tabnet_hook_e5m2_bits(1e9) == 0x7B and L.tabnet_hook_e3m2_bits(-1e9) == 63
     amax = np.concatenate([np.abs(rng.normal(0, 10, 2000)), [0.0, 1.0, 448.0, 2.0 ** -140, 3e38]])
-    for fmt, emax in (("mxfp8", 8), ("mxfp4", 2)):
+    for fmt, emax in (("mxfp8", 8), ("mxfp4", 2), ("mxfp8_e5m2", 15), ("mxfp6_e3m2", 4)):
         got = np.array([L.tabnet_hook_mx_exponent(float(a), emax) for a in amax])
         np.testing.assert_array_equal(got, mx_scale_exponent(amax, fmt))
 
@@ -187,9 +209,10 @@ def test_packed_sizes(L):
         target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
         sh_k, ind_k = synth.layer_in_dims(cfg)
         ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in (0, 1, 2, 3, 4, 5, 6):
-            per = {0: 1, 1: 2, 2: 4, 3: 4, 4: 8, 5: 8, 6: 8}[prec]     # K tiles per k-block
-            kbb = {4: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256}.get(prec, 1024)   # MX: elements + scales
+        for prec in range(9):
+            per = {0: 1, 1: 2, 2: 4, 3: 4}.get(prec, 8)     # K tiles per k-block (8 for every MX format)
+            # MX: elements (8-, 4- and 6-bit) + scales
+            kbb = {4: 2 * 1024 + 256, 7: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256, 8: 1536 + 256}.get(prec, 1024)
             kbytes = (lambda KT, per=per, kbb=kbb: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
             ex = 2 if prec in (2, 3) else 1     # E4M3 and INT8 units also carry one scale per output
             glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}

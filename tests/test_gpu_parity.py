@@ -25,6 +25,8 @@ from paper_2510_19689_amd.synth import TabNetConfig  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
+MX_FORMATS = ["mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2", "mxfp4"]
+
 
 def _say(*a):
     print(*a, flush=True)
@@ -145,7 +147,7 @@ def test_bf16_parity(tmp_path, name, B):
     assert e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8"] + MX_FORMATS)
 def test_optional_step_masks_and_empty_batch(tmp_path, prec):
     params, X = synth.workload("adult108", rows=777)
     _say(f"case masks_step NULL {prec}")
@@ -176,7 +178,7 @@ def test_rows_independent_and_deterministic(tmp_path, prec):
             np.testing.assert_array_equal(part[2], full[2][:, lo_:hi_])
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "int8"] + MX_FORMATS)
 def test_nonfinite_row_is_contained(tmp_path, prec):
     """A NaN or Inf in a row changes nothing in the other rows; in the scaled formats the
     row (or block) scale is taken from that row alone."""
@@ -198,7 +200,7 @@ def test_nonfinite_row_is_contained(tmp_path, prec):
             np.testing.assert_array_equal(u[keep], v[keep])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8"] + MX_FORMATS)
 def test_full_size_adult108_sampled(tmp_path, prec):
     """The benchmarked launch (65,536 rows, step masks on) in every precision the benchmark
     times: sampled rows against the oracle, invariants on every row.  The scaled formats
@@ -206,7 +208,8 @@ def test_full_size_adult108_sampled(tmp_path, prec):
     operands, and their plain-FP64 gates; on these 384 rows the formats themselves move
     (logits, aggregate L1, step L1) by at most (7.6e-3, 4.2e-2, 0.16) in FP8,
     (1.4e-3, 1.7e-2, 7.5e-2) in INT8, (9.4e-3, 6.2e-2, 0.21) in MXFP8,
-    (7.6e-3, 5.6e-2, 0.20) in MXFP6 and (2.9e-2, 0.20, 0.72) in MXFP4."""
+    (7.6e-3, 5.6e-2, 0.20) in MXFP6, (2.9e-2, 0.20, 0.72) in MXFP4, (1.6e-2, 0.10, 0.39)
+    in MXFP8 with E5M2 elements and (1.7e-2, 0.11, 0.39) in MXFP6 with E3M2 elements."""
     params, X = synth.workload("adult108")
     assert X.shape == (65536, 108)
     _say(f"case full adult108 {prec}")
@@ -333,10 +336,15 @@ def test_int8_unsupported_shape_and_round_trip(tmp_path):
 MX_GATES = {"mxfp8": dict(fp64=(1.5e-2, 0.28, 0.4), worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4)),
             # MXFP6 (E2M3): format error (1.3e-2, 0.097, 0.27); its instruction form sums exactly
             "mxfp6": dict(fp64=(1.7e-2, 0.125, 0.35), worst=(0.1, 0.05, 5e-3), typical=(0.9, 1e-5)),
-            "mxfp4": dict(fp64=(4.2e-2, 0.56, 1.08), worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5))}
+            "mxfp4": dict(fp64=(4.2e-2, 0.56, 1.08), worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5)),
+            # E5M2 and E3M2 elements carry two mantissa bits (a flip moves a value by up to an
+            # eighth): format error (1.8e-2, 0.19, 0.39) and (2.0e-2, 0.20, 0.41).  The 8-bit form
+            # of the instruction sums as the E4M3 one does; the 6-bit form as E2M3.
+            "mxfp8_e5m2": dict(fp64=(2.3e-2, 0.24, 0.49), worst=(0.2, 0.1, 1e-2), typical=(0.5, 1e-4)),
+            "mxfp6_e3m2": dict(fp64=(2.5e-2, 0.25, 0.51), worst=(0.2, 0.1, 1e-2), typical=(0.9, 1e-5))}
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("fmt", MX_FORMATS)
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
 def test_mx_parity(tmp_path, name, B, fmt):
     """OCP MX formats on both GEMM operands (E8M0 block scales applied by the scaled MFMA)."""
@@ -356,7 +364,7 @@ def test_mx_parity(tmp_path, name, B, fmt):
     np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
 
 
-@pytest.mark.parametrize("fmt", ["mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("fmt", MX_FORMATS)
 def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
     params, X = synth.workload("adult108", rows=300)
     _say(f"case {fmt} row independence")
@@ -378,13 +386,11 @@ def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
 # per-row gates of each scaled format against FP64 on its own operands (see the tests above)
 # Against plain FP64: (logits, aggregate L1, step L1) per scaled format.
 FP64_GATES = {"fp8": (2e-2, 0.12, 0.25), "int8": (5e-2, 0.1, 0.25),
-              **{f: MX_GATES[f]["fp64"] for f in ("mxfp8", "mxfp6", "mxfp4")}}
+              **{f: MX_GATES[f]["fp64"] for f in MX_FORMATS}}
 
 ROW_GATES = {"int8": ("int8", (2.5e-2, 1e-2, 2e-3), (0.9, 1e-5)),
              "fp8": ("e4m3", (0.1, 0.05, 5e-3), (0.5, 1e-4)),
-             "mxfp8": ("mxfp8", MX_GATES["mxfp8"]["worst"], MX_GATES["mxfp8"]["typical"]),
-             "mxfp6": ("mxfp6", MX_GATES["mxfp6"]["worst"], MX_GATES["mxfp6"]["typical"]),
-             "mxfp4": ("mxfp4", MX_GATES["mxfp4"]["worst"], MX_GATES["mxfp4"]["typical"])}
+             **{f: (f, MX_GATES[f]["worst"], MX_GATES[f]["typical"]) for f in MX_FORMATS}}
 
 
 @pytest.mark.parametrize("fmt", list(ROW_GATES))

@@ -47,7 +47,8 @@ def to_np(*ts):
     return [None if t is None else t.cpu().numpy() for t in ts]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp6", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8", "mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2",
+                                  "mxfp4"])
 @pytest.mark.parametrize("name", ["adult108", "hr35"])
 @pytest.mark.parametrize("B", [1, 63, 65, 1000])
 def test_raw_equals_embedded_forward(name, prec, B, tmp_path):

@@ -82,7 +82,7 @@ def test_mix_equals_alone(models, use_graph):
             assert np.abs(ag[:64] - rag).sum(-1).max() <= 1e-2
 
 
-@pytest.mark.parametrize("prec_a,prec_h", [("int8", "mxfp4"), ("mxfp8", "int8")])
+@pytest.mark.parametrize("prec_a,prec_h", [("int8", "mxfp4"), ("mxfp8", "int8"), ("mxfp8_e5m2", "mxfp6_e3m2")])
 def test_mix_quantised_equals_alone(models, prec_a, prec_h):
     """Quantised models (INT8, MX) served together: each request's outputs are those of the
     model's own forward of that request alone, bit for bit (the row coding is per row)."""
