@@ -238,6 +238,68 @@ def test_full_size_adult108_sampled(tmp_path, prec):
         assert e["argmax"] >= 0.995, e
 
 
+def run_full_sampled(m, X, idx):
+    """One launch over every row of X with step masks on (the launch the benchmark times);
+    the invariants are checked on the device for every row (finite, non-negative, each
+    step mask sums to 1, each aggregate mask sums to 1 or is a zero row), and only the
+    rows idx come back to the host."""
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    lo, ag, ms = m.outputs(X.shape[0], True)
+    for t in (lo, ag, ms):
+        t.fill_(float("nan"))
+    m.forward_into(Xd, lo, ag, ms)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(lo).all()) and bool(torch.isfinite(ag).all()) and bool(torch.isfinite(ms).all())
+    assert bool((ms >= 0).all()) and bool((ag >= 0).all())
+    assert float((ms.sum(-1) - 1).abs().max()) <= 2e-5
+    sa = ag.sum(-1)
+    assert bool((((sa - 1).abs() <= 2e-5) | (sa == 0)).all())
+    it = torch.from_numpy(idx).cuda()
+    out = lo[it].cpu().numpy(), ag[it].cpu().numpy(), ms[:, it].cpu().numpy()
+    del Xd, lo, ag, ms, sa
+    return out
+
+
+@pytest.fixture(scope="module")
+def wide200_full():
+    """The 200-feature workload at its full batch (1,048,576 rows), 384 sampled rows (the
+    first, the last, the middle and 381 at random) and plain FP64 on those rows."""
+    params, X = synth.workload("wide200")
+    assert X.shape == (1048576, 200)
+    n = X.shape[0]
+    idx = np.random.default_rng(0).choice(n, 384, replace=False)
+    idx[:3] = [0, n - 1, n // 2]
+    return params, X, idx, oracle.forward(params, X[idx])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8"] + MX_FORMATS)
+def test_full_size_wide200_sampled(tmp_path, wide200_full, prec):
+    """The 200-feature model at its full batch (1,048,576 rows, 7 steps, step masks on), in
+    the launch configuration of `bench.py --workload wide200`: invariants on every row,
+    sampled rows against the oracle with the gates of the smaller cases.  On these rows
+    the formats themselves move (logits, aggregate L1, step L1) by at most
+    (6.1e-4, 2.6e-3, 8.1e-3) in BF16, (1.2e-2, 3.5e-2, 0.12) in FP8, (2.2e-3, 8.8e-3, 2.8e-2)
+    in INT8 and (2.9e-2, 0.16, 0.56) in MXFP4, the largest among the MX formats."""
+    params, X, idx, ref = wide200_full
+    _say(f"case full wide200 {prec}")
+    with load(params, tmp_path, prec) as m:
+        got = run_full_sampled(m, X, idx)
+    e = errs(got, ref)
+    _say(f"full wide200 {prec} sampled", e)
+    if prec == "fp32":
+        assert e["logit_rel"] <= 1e-4 and e["agg_abs"] <= 1e-5 and e["step_abs"] <= 1e-5, e
+    elif prec == "bf16":
+        check_reduced(got, params, X[idx], "bf16", "bf16", "full wide200 bf16")
+        assert e["logit_abs"] <= 2e-2 and e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
+        assert e["argmax"] >= 0.995, e
+    else:
+        oracle_fmt, worst, typical = ROW_GATES[prec]
+        check_rows_on_rounded(got, params, X[idx], oracle_fmt, f"full wide200 {prec}", worst=worst, typical=typical)
+        lo_t, agg_t, step_t = FP64_GATES[prec]
+        assert e["logit_abs"] <= lo_t and e["agg_l1"] <= agg_t and e["step_l1"] <= step_t, e
+        assert e["argmax"] >= 0.995, e
+
+
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
 def test_fp8_parity(tmp_path, name, B):
     """E4M3 weights (one scale per output channel) and E4M3 GEMM inputs (one scale per row,

@@ -87,6 +87,46 @@ def test_bf16_matches_oracle(B, tmp_path):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_full_size_sampled(prec, tmp_path):
+    """The 512-feature workload at its full batch (65,536 rows, 10 steps, step masks on), in
+    the launch configuration of `bench.py --workload wide512`: invariants on every row on
+    the device, 256 sampled rows against the oracle with the gates above.  (On these rows
+    BF16 operands alone move the logits by 5.4e-4 and a step mask by 1.1e-2 in L1.)"""
+    params, X = synth.workload("wide512")
+    assert X.shape == (65536, 512)
+    n = X.shape[0]
+    idx = np.random.default_rng(0).choice(n, 256, replace=False)
+    idx[:3] = [0, n - 1, n // 2]
+    path = str(tmp_path / "w.tnw")
+    synth.write_weights(params, path)
+    _say(f"case wide512 full size {prec}")
+    with tb.Model(path, prec) as m:
+        lo, ag, ms = m.forward(torch.from_numpy(X).cuda())
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(lo).all()) and bool(torch.isfinite(ag).all()) and bool(torch.isfinite(ms).all())
+        assert bool((ms >= 0).all()) and bool((ag >= 0).all())
+        assert float((ms.sum(-1) - 1).abs().max()) <= 2e-5
+        sa = ag.sum(-1)
+        assert bool((((sa - 1).abs() <= 2e-5) | (sa == 0)).all())
+        it = torch.from_numpy(idx).cuda()
+        lo, ag, ms = lo[it].cpu().numpy(), ag[it].cpu().numpy(), ms[:, it].cpu().numpy()
+    rlo, rag, rms = oracle.forward(params, X[idx])
+    _say(prec, "logits", np.abs(lo - rlo).max(), "agg", np.abs(ag - rag).max(), "step", np.abs(ms - rms).max())
+    if prec == "fp32":
+        cfg = WIDE
+        rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+        mt = 1e-5 * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)
+        assert rel <= 1e-4
+        assert np.abs(ag - rag).max() <= mt and np.abs(ms - rms).max() <= mt
+    else:
+        qlo, qag, qms = oracle.forward(params, X[idx], weights="bf16", acts="bf16")
+        assert np.abs(lo - rlo).max() <= 2e-2
+        assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.995
+        assert np.abs(lo - qlo).max() <= 1e-3
+        assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_rows_independent_optional_masks_empty(prec, tmp_path):
     _say(f"case wide rows independent {prec}")
     params, m = load(WIDE, 1005, prec, tmp_path)
