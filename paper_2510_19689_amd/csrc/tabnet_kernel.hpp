@@ -46,11 +46,12 @@
 // the factor of the sigmoid's exponent, and the shifts are not divided by the scales (the
 // products of codes are dequantised before the shift is added).
 // MX formats (OCP microscaling: blocks of 32 K positions share a power-of-two E8M0
-// scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA: MXFP8 packs per
-// k-block [64 lanes x 16 B: E4M3 elements 0-15][64 x 16 B: elements 16-31][64 x 4 B: the
-// E8M0 scale each lane supplies, in byte 0]; MXFP6 packs [64 x 16 B: bytes 0-15][64 x 8 B:
-// bytes 16-23 of 32 E2M3 elements, element e in bits 6 e .. 6 e + 5][64 x 4 B: scales];
-// MXFP4 packs [64 x 16 B: 32 E2M1 elements, element e in nibble e][64 x 4 B: scales].  Element e of a lane holds feature
+// scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA: MXFP8 (E4M3 or E5M2
+// elements) packs per k-block [64 lanes x 16 B: elements 0-15][64 x 16 B: elements
+// 16-31][64 x 4 B: the E8M0 scale each lane supplies, in byte 0]; MXFP6 (E2M3 or E3M2)
+// packs [64 x 16 B: bytes 0-15][64 x 8 B: bytes 16-23 of 32 six-bit elements, element e in
+// bits 6 e .. 6 e + 5][64 x 4 B: scales]; MXFP4 packs [64 x 16 B: 32 E2M1 elements, element
+// e in nibble e][64 x 4 B: scales].  Element e of a lane holds feature
 // 16 (8 kb + e / 4) + 4 q + e % 4.  The instruction groups a lane row's 128 K slots into
 // four blocks of 32 consecutive slots and takes block b's scale from lane group b:
 //   MXFP6, MXFP4: lane group q holds slots 32 q + e, so its block is its own 32 elements;
@@ -135,7 +136,8 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 // prec: 0 FP32, 1 BF16, 2 E4M3 and 3 INT8 weights and activations (codes in the fragments,
 // one FP32 scale per output channel after the shifts, one scale per input row formed in
-// the kernel), 4 MXFP8, 5 MXFP4 and 6 MXFP6 (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
+// the kernel), 4 MXFP8, 5 MXFP4, 6 MXFP6, 7 MXFP8 with E5M2 elements and 8 MXFP6 with E3M2
+// elements (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
 // KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const int sc = has_channel_scales(prec) ? 2 : 1;   // shifts, or shifts + scales
