@@ -455,6 +455,54 @@ ROW_GATES = {"int8": ("int8", (2.5e-2, 1e-2, 2e-3), (0.9, 1e-5)),
              **{f: (f, MX_GATES[f]["worst"], MX_GATES[f]["typical"]) for f in MX_FORMATS}}
 
 
+# Compiled register-resident shape families: (D range, n_d + n_a range, n_d range), i.e.
+# 16-feature tiles DT = 1, 2, 3, 4 with one hidden tile, DT = 4 with two, 7 with four and 13
+# with eight (and the matching first attention tile).
+FAMILIES = [((1, 16), (2, 16), (1, 15)), ((17, 32), (2, 16), (1, 15)), ((33, 48), (2, 16), (1, 15)),
+            ((49, 64), (2, 16), (1, 15)), ((49, 64), (17, 32), (16, 31)), ((97, 112), (49, 64), (32, 47)),
+            ((193, 208), (113, 128), (64, 79))]
+
+
+def random_config(k):
+    """Seeded model configuration k: family k mod 7, widths, 1-6 steps, 0-3 shared and 0-3
+    step layers (at least one), 1-8 outputs, gamma in [1, 2), and a batch of 1-259 rows."""
+    rng = np.random.default_rng(5000 + k)
+    (d0, d1), (N0, N1), (nd0, nd1) = FAMILIES[k % len(FAMILIES)]
+    D = int(rng.integers(d0, d1 + 1))
+    n_d = int(rng.integers(nd0, nd1 + 1))
+    N = int(rng.integers(max(N0, n_d + 1), N1 + 1))
+    n_sh, n_ind = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+    if n_sh + n_ind == 0:
+        n_ind = 1
+    cfg = TabNetConfig(D=D, n_d=n_d, n_a=N - n_d, n_steps=int(rng.integers(1, 7)), n_shared=n_sh, n_indep=n_ind,
+                       n_out=int(rng.integers(1, 9)), gamma=float(rng.uniform(1.0, 2.0)))
+    return cfg, int(rng.integers(1, 260))
+
+
+@pytest.mark.parametrize("k", range(14))
+def test_random_configurations(tmp_path, k):
+    """Two seeded random models per compiled shape family: FP32 against FP64 with the gates
+    of the small models (check_fp32_tight: logits 1e-5 relative, masks 1e-6 times the
+    prior's growth max(1, gamma^(S-1) / 2); measured at most 4.4e-6 and 1.0e-6), BF16 against FP64
+    on bf16-rounded operands (check_reduced), and one scaled format (in turn) against FP64
+    on its own operands with its row gates."""
+    cfg, B = random_config(k)
+    fmt = list(ROW_GATES)[k % len(ROW_GATES)]
+    params = synth.make_params(cfg, 6000 + k)
+    X = synth.make_normal_inputs(B, cfg.D, seed=7000 + k)
+    _say(f"case random configuration {k}: {cfg} B={B}, scaled format {fmt}")
+    ref = oracle.forward(params, X)
+    with load(params, tmp_path, "fp32", "a") as m:
+        check_fp32_tight(run(m, X), ref, f"random {k} fp32", cfg)
+    with load(params, tmp_path, "bf16", "b") as m:
+        check_reduced(run(m, X), params, X, "bf16", "bf16", f"random {k} bf16")
+    oracle_fmt, worst, typical = ROW_GATES[fmt]
+    with load(params, tmp_path, fmt, "c") as m:
+        got = run(m, X)
+    check_rows_on_rounded(got, params, X, oracle_fmt, f"random {k} {fmt}", worst=worst,
+                          typical=typical if B >= 50 else (0.0, 1.0))
+
+
 @pytest.mark.parametrize("fmt", list(ROW_GATES))
 @pytest.mark.parametrize("k", range(len(SMALL)))
 def test_scaled_formats_small_shapes(tmp_path, k, fmt):
