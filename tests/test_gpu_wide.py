@@ -86,6 +86,49 @@ def test_bf16_matches_oracle(B, tmp_path):
     assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
 
 
+def random_wide(k):
+    """Seeded configuration k of the split-feature kernel's family (D = 497..512, n_d + n_a =
+    113..128, 64 <= n_d < 80): 1-10 steps, 0-3 shared and 0-3 step layers (at least one),
+    1-8 outputs, gamma in [1, 2), and a batch of 1-199 rows."""
+    rng = np.random.default_rng(8000 + k)
+    D = int(rng.integers(497, 513))
+    n_d = int(rng.integers(64, 80))
+    N = int(rng.integers(113, 129))
+    n_sh, n_ind = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+    if n_sh + n_ind == 0:
+        n_ind = 1
+    cfg = TabNetConfig(D=D, n_d=n_d, n_a=N - n_d, n_steps=int(rng.integers(1, 11)), n_shared=n_sh, n_indep=n_ind,
+                       n_out=int(rng.integers(1, 9)), gamma=float(rng.uniform(1.0, 2.0)))
+    return cfg, int(rng.integers(1, 200))
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_random_wide_configurations(k, tmp_path):
+    """Seeded random models on the split-feature kernel: FP32 with the gates above (masks
+    scaled by the prior's growth max(1, gamma^(S-1) / 2)), BF16 against FP64 on bf16-rounded
+    operands (logits 1e-3, mask L1 per row 5e-3)."""
+    cfg, B = random_wide(k)
+    X = synth.make_normal_inputs(B, cfg.D, 9500 + k)
+    _say(f"case wide random {k}: {cfg} B={B}")
+    params, m = load(cfg, 9000 + k, "fp32", tmp_path, "a")
+    with m:
+        lo, ag, ms = run(m, X)
+    rlo, rag, rms = oracle.forward(params, X)
+    rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+    mt = 1e-5 * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)
+    _say(k, "fp32 logit_rel", rel, "agg", np.abs(ag - rag).max(), "step", np.abs(ms - rms).max(), "mask gate", mt)
+    assert rel <= 1e-4
+    assert np.abs(ag - rag).max() <= mt and np.abs(ms - rms).max() <= mt
+    _, m = load(cfg, 9000 + k, "bf16", tmp_path, "b")
+    with m:
+        lo, ag, ms = run(m, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="bf16", acts="bf16")
+    _say(k, "bf16 vs rounded: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
+         "step L1", np.abs(ms - qms).sum(-1).max())
+    assert np.abs(lo - qlo).max() <= 1e-3
+    assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_full_size_sampled(prec, tmp_path):
     """The 512-feature workload at its full batch (65,536 rows, 10 steps, step masks on), in
