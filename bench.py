@@ -331,9 +331,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--quant", default="fp8,int8,mxfp8,mxfp8_e5m2,mxfp6,mxfp6_e3m2,mxfp4",
-                    help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights and GEMM inputs; int8: "
-                         "INT8 weights and GEMM inputs; mxfp8, mxfp8_e5m2, mxfp6, mxfp6_e3m2, mxfp4: OCP MX on both GEMM "
-                         "operands); "
+                    help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights and GEMM "
+                         "inputs; int8: INT8 weights and GEMM inputs; mxfp8, mxfp8_e5m2, mxfp6, mxfp6_e3m2, "
+                         "mxfp4: OCP MX on both GEMM operands); "
                          "empty to skip")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
                     help="request rates (req/s) of the serving leg; empty to skip")

@@ -371,7 +371,10 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
     // share one layout, and so do the two 6-bit forms.
     const bool f8 = precision == TABNET_MXFP8 || precision == TABNET_MXFP8_E5M2;
     const bool f6 = precision == TABNET_MXFP6 || precision == TABNET_MXFP6_E3M2;
-    const int emax = precision == TABNET_MXFP8 ? 8 : (precision == TABNET_MXFP8_E5M2 ? 15 : (precision == TABNET_MXFP6_E3M2 ? 4 : 2));
+    const int emax = precision == TABNET_MXFP8        ? 8     // E4M3
+                     : precision == TABNET_MXFP8_E5M2 ? 15    // E5M2
+                     : precision == TABNET_MXFP6_E3M2 ? 4     // E3M2
+                                                      : 2;    // E2M3, E2M1
     uint8_t (*const enc8)(double) = precision == TABNET_MXFP8 ? e4m3_bits_rne : e5m2_bits_rne;
     uint8_t (*const enc6)(double) = precision == TABNET_MXFP6 ? e2m3_bits_rne : e3m2_bits_rne;
     const int KB = (KT + 7) / 8;
