@@ -65,6 +65,70 @@ def test_raw_equals_embedded_forward(name, prec, B, tmp_path):
     np.testing.assert_allclose(ms_r, oe.reduce_columns(ms, dims), rtol=0, atol=1e-6)
 
 
+# one model per compiled shape family: (D, n_d, n_a)
+RANDOM_SHAPES = [(13, 5, 6), (30, 8, 8), (47, 4, 10), (60, 20, 12), (104, 40, 24), (205, 70, 58)]
+
+
+def random_spec(D, rng):
+    """A random embedding of D model features: continuous columns (width 1) and categorical
+    columns of 2-60 levels and width 1-24, so that columns start and end anywhere in the
+    16-feature tiles; float32 tables N(0, 1)."""
+    cards, dims, at = [], [], 0
+    while at < D:
+        if rng.random() < 0.4:
+            cards.append(0)
+            dims.append(1)
+        else:
+            dims.append(int(rng.integers(1, min(24, D - at) + 1)))
+            cards.append(int(rng.integers(2, 61)))
+        at += dims[-1]
+    cards = np.array(cards, np.int32)
+    dims = np.array(dims, np.int32)
+    return cards, dims, rng.normal(0, 1, int((cards.astype(np.int64) * dims).sum())).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("k", range(len(RANDOM_SHAPES)))
+def test_random_embedding_specs(k, prec, tmp_path):
+    """Random embeddings on every compiled shape family: the raw-row logits equal the
+    embedded forward's bit for bit, each column's masks equal the FP32 sum of its features'
+    masks (|d| <= 2e-6: at most 24 values below 1), and in FP32 the raw forward matches the
+    FP64 oracle (logits 1e-4 relative, masks 1e-5 times the widest column and the prior's
+    growth).  A few categorical entries hold invalid levels, which embed to zero."""
+    rng = np.random.default_rng(400 + k)
+    D, n_d, n_a = RANDOM_SHAPES[k]
+    cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=int(rng.integers(1, 6)), n_shared=int(rng.integers(1, 3)),
+                             n_indep=int(rng.integers(0, 3)), n_out=int(rng.integers(1, 6)),
+                             gamma=float(rng.uniform(1.0, 1.8)))
+    cards, dims, tables = random_spec(D, rng)
+    B = int(rng.integers(1, 400))
+    X_raw = np.empty((B, cards.size), np.float32)
+    for c, card in enumerate(cards):
+        X_raw[:, c] = rng.normal(0, 1, B) if card == 0 else rng.integers(0, card, B)
+    cat = np.nonzero(cards)[0]
+    if cat.size and B > 3:
+        X_raw[0, cat[0]], X_raw[1, cat[-1]], X_raw[2, cat[0]] = -1.0, float(cards[cat[-1]]), np.nan
+    params = synth.make_params(cfg, 500 + k)
+    path = str(tmp_path / "m.tnw")
+    synth.write_weights(params, path)
+    _say(f"case random embedding {k} {prec}: {cfg} columns={cards.size} widest={dims.max()} B={B}")
+    X = oe.embed(X_raw, cards, dims, tables).astype(np.float32)
+    with tb.Model(path, prec) as m:
+        m.set_embeddings(cards, dims, tables)
+        lo_r, ag_r, ms_r = to_np(*m.forward_raw(torch.from_numpy(X_raw).cuda()))
+        lo, ag, ms = to_np(*m.forward(torch.from_numpy(X).cuda()))
+    np.testing.assert_array_equal(lo_r, lo)
+    np.testing.assert_allclose(ag_r, oe.reduce_columns(ag, dims), rtol=0, atol=2e-6)
+    np.testing.assert_allclose(ms_r, oe.reduce_columns(ms, dims), rtol=0, atol=2e-6)
+    if prec == "fp32":
+        rlo, rag, rms = oe.forward_raw(params, X_raw, cards, dims, tables)
+        rel = (np.abs(lo_r - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+        mt = 1e-5 * int(dims.max()) * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)
+        _say(k, "logit_rel", rel, "agg", np.abs(ag_r - rag).max(), "step", np.abs(ms_r - rms).max(), "gate", mt)
+        assert rel <= 1e-4
+        assert np.abs(ag_r - rag).max() <= mt and np.abs(ms_r - rms).max() <= mt
+
+
 @pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 2000)])
 def test_raw_fp32_matches_oracle(name, B, tmp_path):
     _say(f"case raw fp32 vs oracle {name} B={B}")
