@@ -56,3 +56,20 @@ def test_c_program_links_and_reports_errors(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "status -4" in r.stdout
+
+
+@pytest.mark.parametrize("prog", ["serve_load.c", "serve_rate.c"])
+def test_native_clients_build(tmp_path, prog):
+    """The C clients under tests/native (the serving test's client and the load generator)
+    compile as strict C99 and link against the library."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    if not os.path.exists(tb.LIB_PATH):
+        pytest.skip("libtabnet.so not built")
+    libdir = os.path.dirname(os.path.abspath(tb.LIB_PATH))
+    r = subprocess.run([gcc, "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-D_POSIX_C_SOURCE=199309L",
+                        f"-I{ROOT}/include", os.path.join(ROOT, "tests", "native", prog), "-o", str(tmp_path / "a.out"),
+                        f"-L{libdir}", "-ltabnet", f"-Wl,-rpath,{libdir}", "-pthread", "-lm"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
