@@ -236,6 +236,30 @@ size_t tabnet_mask_stats_workspace_bytes(int64_t B, int32_t D);
 tabnet_status tabnet_mask_stats(const float* masks, int64_t B, int32_t D, double* mean, double* var,
                                 void* workspace, size_t workspace_bytes, void* stream);
 
+/* Bytes of the library's own scratch for tabnet_mask_stats_noalloc (8 MiB per GPU). */
+size_t tabnet_mask_stats_noalloc_max_bytes(void);
+
+/*
+ * tabnet_mask_stats_noalloc -- tabnet_mask_stats without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels, same results bit for bit.
+ *
+ *   masks, B, D, mean, var, stream   as in tabnet_mask_stats
+ *
+ * The partial sums live in a fixed device array of the library, one per GPU, held until
+ * the process ends; the call allocates nothing.  Its first call on a device takes the
+ * array's address on that device.  Every call on one GPU uses that GPU's array: calls
+ * whose work overlaps on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Nothing in the array needs clearing between calls: each call
+ * writes every partial sum it reads.
+ *
+ * Errors: TABNET_E_INVALID (NULL pointer, B < 1, D out of range, or
+ * tabnet_mask_stats_workspace_bytes(B, D) larger than tabnet_mask_stats_noalloc_max_bytes();
+ * nothing is enqueued), TABNET_E_HIP (address lookup or launch failed).
+ */
+tabnet_status tabnet_mask_stats_noalloc(const float* masks, int64_t B, int32_t D, double* mean, double* var,
+                                        void* stream);
+
 /* ------------------------------------------------------------------------------------
  * Serving: continuous batching of variable-row requests.
  *

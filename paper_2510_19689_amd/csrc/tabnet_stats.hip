@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/tabnet.h"
@@ -176,6 +177,36 @@ hipError_t enqueue_mask_stats(const float* masks, int64_t rows, const int64_t* r
   return hipGetLastError();
 }
 
+// Scratch of tabnet_mask_stats_noalloc: the partial sums of the statistics kernels, in a
+// file-scope device array that each GPU holds for the life of the process.  In host code
+// `scratch` is a stand-in symbol, not a device address: the address of a device's copy
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (set up on the first call per device).
+hipError_t scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 }  // namespace tabnet
 
 extern "C" {
@@ -203,6 +234,35 @@ tabnet_status tabnet_mask_stats(const float* masks, int64_t B, int32_t D, double
                                                   static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     tabnet::set_error(std::string("tabnet_mask_stats: ") + hipGetErrorString(e));
+    return TABNET_E_HIP;
+  }
+  return TABNET_OK;
+}
+
+size_t tabnet_mask_stats_noalloc_max_bytes(void) { return tabnet::kNoAllocScratchBytes; }
+
+tabnet_status tabnet_mask_stats_noalloc(const float* masks, int64_t B, int32_t D, double* mean, double* var,
+                                        void* stream) {
+  if (!masks || !mean || !var) {
+    tabnet::set_error("tabnet_mask_stats_noalloc: NULL pointer argument");
+    return TABNET_E_INVALID;
+  }
+  if (B < 1 || D < 1 || D > (1 << 24) || B > (INT64_MAX / 4) / D) {
+    tabnet::set_error("tabnet_mask_stats_noalloc: B must be >= 1 and D in [1, 2^24] with B * D addressable");
+    return TABNET_E_INVALID;
+  }
+  if (tabnet::mask_stats_workspace_bytes(B, D) > tabnet::kNoAllocScratchBytes) {
+    tabnet::set_error("tabnet_mask_stats_noalloc: tabnet_mask_stats_workspace_bytes(B, D) exceeds the library's "
+                      "scratch (tabnet_mask_stats_noalloc_max_bytes); use tabnet_mask_stats with a workspace");
+    return TABNET_E_INVALID;
+  }
+  void* ws = nullptr;
+  hipError_t e = tabnet::scratch_ptr(&ws);
+  if (e == hipSuccess)
+    e = tabnet::enqueue_mask_stats(masks, B, nullptr, D, mean, var, nullptr, nullptr, ws,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    tabnet::set_error(std::string("tabnet_mask_stats_noalloc: ") + hipGetErrorString(e));
     return TABNET_E_HIP;
   }
   return TABNET_OK;

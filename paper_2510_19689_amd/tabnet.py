@@ -128,6 +128,10 @@ def lib() -> ctypes.CDLL:
     L.tabnet_mask_stats_workspace_bytes.restype = ctypes.c_size_t
     L.tabnet_mask_stats.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
     L.tabnet_mask_stats.restype = i32
+    L.tabnet_mask_stats_noalloc_max_bytes.argtypes = []
+    L.tabnet_mask_stats_noalloc_max_bytes.restype = ctypes.c_size_t
+    L.tabnet_mask_stats_noalloc.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp]
+    L.tabnet_mask_stats_noalloc.restype = i32
     L.tabnet_serve_now_ns.argtypes = []
     L.tabnet_serve_now_ns.restype = i64
     L.tabnet_serve_stop.argtypes = [vp]
@@ -258,6 +262,32 @@ def mask_stats_into(masks, mean, var, workspace, stream=None) -> None:
     check(lib().tabnet_mask_stats(masks.data_ptr(), B, D, mean.data_ptr(), var.data_ptr(),
                                   workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                   _stream_ptr(stream)))
+
+
+def _check_stats_args(masks, mean, var) -> None:
+    """masks: contiguous float32 [B, D] on a GPU; mean / var: contiguous float64 [D] on the
+    same GPU (a host tensor's address must never reach the kernels)."""
+    import torch
+    if masks.dtype != torch.float32 or masks.dim() != 2 or not masks.is_contiguous() or not masks.is_cuda:
+        raise ValueError("masks must be a contiguous float32 [B, D] CUDA tensor")
+    D = int(masks.shape[1])
+    for name, t in (("mean", mean), ("var", var)):
+        if (t.dtype != torch.float64 or t.dim() != 1 or int(t.shape[0]) != D or not t.is_contiguous()
+                or t.device != masks.device):
+            raise ValueError(f"{name} must be a contiguous float64 [{D}] tensor on {masks.device}")
+
+
+def mask_stats_noalloc_max_bytes() -> int:
+    return int(lib().tabnet_mask_stats_noalloc_max_bytes())
+
+
+def mask_stats_noalloc_into(masks, mean, var, stream=None) -> None:
+    """tabnet_mask_stats_noalloc on caller-provided device tensors: masks float32 [B, D],
+    mean / var float64 [D]; the partial sums go to the library's own device scratch."""
+    _check_stats_args(masks, mean, var)
+    B, D = int(masks.shape[0]), int(masks.shape[1])
+    check(lib().tabnet_mask_stats_noalloc(masks.data_ptr(), B, D, mean.data_ptr(), var.data_ptr(),
+                                          _stream_ptr(stream)))
 
 
 def mask_stats(masks, stream=None):

@@ -256,3 +256,9 @@ def test_mask_stats_workspace_and_argument_checks(L):
     ]
     for m, B, D, mean, var, ws, nb in cases:
         assert L.tabnet_mask_stats(m, B, D, mean, var, ws, nb, None) == tb.E_INVALID
+    # the no-allocation variant checks the same arguments, and its scratch limit, first
+    assert L.tabnet_mask_stats_noalloc_max_bytes() == 8 << 20
+    for m, B, D, mean, var in [(None, 100, 7, fake, fake), (fake, 100, 7, None, fake), (fake, 100, 7, fake, None),
+                               (fake, 0, 7, fake, fake), (fake, 100, 0, fake, fake), (fake, 1 << 22, 4096, fake, fake)]:
+        assert L.tabnet_mask_stats_noalloc(m, B, D, mean, var, None) == tb.E_INVALID
+    assert b"exceeds" in L.tabnet_last_error()
