@@ -113,13 +113,13 @@ typedef struct tabnet_handle tabnet_handle;
  * v / 2^X rounded to nearest even in the element format, saturating (+-448, +-57344,
  * +-7.5, +-28, +-6).  The
  * weights are coded at load, each GEMM input row in the kernel; the gfx950 scaled matrix
- * instruction applies both scales, and everything else stays in FP32.  A block is the
- * 32 K positions the instruction groups together: with K positions in 16-wide tiles of
- * four 4-wide groups q and eight tiles per instruction, a block of 4- or 6-bit elements
- * is group q of the eight tiles, a block of 8-bit elements groups 2b and 2b+1 of four
- * consecutive tiles.  The
- * attentive transformer's input keeps the channel positions of the hidden state's
- * tiles.  Same kernel coverage and non-finite behaviour as TABNET_INT8.
+ * instruction applies both scales, and everything else stays in FP32.  A block is 32
+ * consecutive K positions of the GEMM input in its own order (the attentive
+ * transformer's input, the attention half, from its own first channel); a last block of
+ * fewer positions holds the rest.  The kernel forms blocks from pairs of 16-channel
+ * tiles, so a model whose attention half neither starts a tile (n_d % 16 == 0) nor fits
+ * the tile pair it starts in (n_d % 16 + n_a <= 32) is TABNET_E_UNSUPPORTED in these
+ * formats.  Same kernel coverage and non-finite behaviour as TABNET_INT8 otherwise.
  */
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out);
 

@@ -40,10 +40,10 @@ max|W'_n|/448; INT8 with one scale per output channel, max|W'_n|/127); acts in
 {None, "bf16", "e4m3", "int8"} act on each GEMM input (one scale per row, max|u_r|/448
 or max|u_r|/127).  The GEMM input of the attentive transformer is the attention half
 a = h[:, n_d:] alone, so its row scale is taken over those channels.  The MX formats
-"mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2" and "mxfp4" (either operand) take OCP MX blocks of 32 K positions with one power-of-two scale each
-(rounding.round_mx_rows), along K for both the weight rows and the input rows; the K
-position of a column is its index, except for the attention half, whose columns keep
-their place in h's 16-channel tiles (position = column + n_d mod 16).  The folded shift
+"mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2" and "mxfp4" (either operand) take OCP MX blocks of 32 consecutive K positions with one
+power-of-two scale each (rounding.round_mx_rows), along K for both the weight rows and
+the input rows; the K position of a column is its index in the GEMM input, so the
+attention half a = h[:, n_d:] starts its first block at its own column 0.  The folded shift
 beta - s * mean is never rounded.  With both None the computation is the definition
 above, unchanged.
 """
@@ -80,7 +80,7 @@ def glu(y: np.ndarray, N: int) -> np.ndarray:
     return y[:, :N] * sigmoid(y[:, N:])
 
 
-def _round_acts(u: np.ndarray, mode, k_offset: int = 0):
+def _round_acts(u: np.ndarray, mode):
     if mode is None:
         return u
     if mode == "bf16":
@@ -92,11 +92,11 @@ def _round_acts(u: np.ndarray, mode, k_offset: int = 0):
     if mode == "int8":
         return round_int8_rows(u)
     if mode in MX_ELEMENTS:
-        return round_mx_rows(u, mode, k_offset)
+        return round_mx_rows(u, mode)
     raise ValueError(mode)
 
 
-def _fc_bn(u: np.ndarray, W, bn: dict, eps: float, weights=None, acts=None, k_offset: int = 0) -> np.ndarray:
+def _fc_bn(u: np.ndarray, W, bn: dict, eps: float, weights=None, acts=None) -> np.ndarray:
     """BN(u W^T); with rounding enabled, the BN-folded form on rounded operands."""
     if weights is None and acts is None:
         return batch_norm(u @ _d(W).T, bn, eps)
@@ -112,10 +112,10 @@ def _fc_bn(u: np.ndarray, W, bn: dict, eps: float, weights=None, acts=None, k_of
     elif weights == "int8":
         Wf = round_int8_rows(Wf)
     elif weights in MX_ELEMENTS:
-        Wf = round_mx_rows(Wf, weights, k_offset)
+        Wf = round_mx_rows(Wf, weights)
     elif weights is not None:
         raise ValueError(weights)
-    return _round_acts(u, acts, k_offset) @ Wf.T + shift
+    return _round_acts(u, acts) @ Wf.T + shift
 
 
 def glu_layer(u, layer: dict, N: int, eps: float, weights=None, acts=None) -> np.ndarray:
@@ -148,7 +148,7 @@ def forward(params: dict, X, weights=None, acts=None, internals: bool = False):
     masks, zs, priors, etas = [], [], [], []
     for i in range(1, cfg.n_steps + 1):
         att = params["att"][i - 1]
-        z = P * _fc_bn(a, att["W"], att["bn"], cfg.bn_eps, weights, acts, k_offset=n_d % 16)
+        z = P * _fc_bn(a, att["W"], att["bn"], cfg.bn_eps, weights, acts)
         M = sparsemax(z)
         priors.append(P)
         P = P * (cfg.gamma - M)

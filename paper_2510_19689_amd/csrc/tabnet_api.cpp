@@ -98,6 +98,13 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
                   m.cfg.D, sh.DT, m.cfg.n_d + m.cfg.n_a, sh.NT, m.cfg.n_d, sh.KA0);
     return fail(TABNET_E_UNSUPPORTED, msg);
   }
+  // MX blocks are 32 consecutive channels of each GEMM input, the attention half's from its
+  // own first channel.  The kernel forms them from 16-channel tile pairs, which holds when
+  // the attention half starts a tile, or lies whole within the tile pair it starts in.
+  if (precision >= TABNET_MXFP8 && m.cfg.n_d % 16 != 0 && m.cfg.n_d % 16 + m.cfg.n_a > 32)
+    return fail(TABNET_E_UNSUPPORTED,
+                "tabnet_load: MX formats need n_d % 16 == 0 or n_d % 16 + n_a <= 32 (the attention half's "
+                "32-channel blocks must fall on the kernel's tile pairs)");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));

@@ -221,14 +221,49 @@ __device__ __forceinline__ int mx_exponent(float amax) {
   return amax > 0.f ? (X < -126 ? -126 : (X > 127 ? 127 : X)) : 0;
 }
 
-// MXFP8: per row block and k-block (eight K tiles), 32 8-bit elements, E4M3 (E5M2 when
-// E5M2 is set) (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i, four to a dword) and the E8M0
-// scale this lane supplies to the instruction.  Tiles 0-3 of the k-block form, with the partner lane
-// group (g ^ 1), block g / 2; tiles 4-7 block 2 + g / 2.  The instruction reads block b's
-// scale from lane group b: groups 0 and 3 own the blocks they supply, group 1 supplies
-// block 1 (tiles 0-3 of groups 2 and 3) and group 2 block 2 (tiles 4-7 of groups 0 and
-// 1), each received from the lane 32 away.  Elements are v / 2^X, clamped to the largest
-// normal (+-448, E5M2 +-57344) and rounded to nearest even.
+// MX blocks.  A k-block is eight K tiles (128 K positions, one scaled MFMA); its OCP MX
+// blocks are the four runs of 32 consecutive K positions, block b = tiles 2 b and 2 b + 1.
+// A lane holds 8 elements of every block (its features 4 g + i of both tiles), so a
+// block's scale is the maximum over the row's 4 lanes, and the instruction's lane groups
+// receive their blocks by exchanges within the row's 4 lanes (v_permlane16_swap,
+// v_permlane32_swap; the order of the 8-element chunks inside a block is the one the host
+// packs the weights with).
+//
+// The per-block maxima of this lane's 8 elements, over the row's 4 lanes.
+template <int KT, class F>
+__device__ __forceinline__ void mx_block_max(F src, int rb, int kb, float (&m)[4]) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = 8 * kb + 2 * b + h;
+      if (t < KT)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i & 1) a1 = fmaxf(a1, fabsf(src(rb, t, i)));
+          else a0 = fmaxf(a0, fabsf(src(rb, t, i)));
+        }
+    }
+    m[b] = row_max(fmaxf(a0, a1));
+  }
+}
+
+// The value of lane group g's entry of v[0..3] (the scale lane group g supplies).
+__device__ __forceinline__ uint32_t by_group(const uint32_t (&v)[4], int g) {
+  return g == 0 ? v[0] : (g == 1 ? v[1] : (g == 2 ? v[2] : v[3]));
+}
+
+// MXFP8 (E4M3 elements, E5M2 when E5M2 is set).  The instruction's lane group q holds
+// instruction slots 16 q .. 16 q + 15 (dwords 0-3) and 64 + 16 q .. 64 + 16 q + 15 (dwords
+// 4-7), and takes block b's scale from lane group b; slots 32 b' .. 32 b' + 31 share a
+// scale.  So lane groups 0 and 1 carry halves of blocks 0 and 2, groups 2 and 3 halves of
+// blocks 1 and 3: lane group q holds, in dwords 0-3, the elements of block q / 2 from lane
+// groups q % 2 (dwords 0-1) and q % 2 + 2 (dwords 2-3), and in dwords 4-7 the same for
+// block 2 + q / 2.  Each lane codes its 8 elements of every block (dword 2 h: tile 2 b + h,
+// element i in byte i), keeps two blocks and swaps the other two with the lane 32 away.
+// Elements are v / 2^X, clamped to the largest normal (+-448, E5M2 +-57344) and rounded
+// to nearest even.
 template <int KT, int R, bool E5M2>
 struct MxF8Op {
   static constexpr int KB = kblocks(4, KT);
@@ -243,43 +278,47 @@ struct MxF8Op {
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        float a[2] = {0.f, 0.f};
+        float m[4];
+        mx_block_max<KT>(src, rb, kb, m);
+        uint32_t e8[4], w[4][2];
 #pragma unroll
-        for (int tt = 0; tt < 8; ++tt)
-          if (8 * kb + tt < KT)
+        for (int b = 0; b < 4; ++b) {
+          const int X = mx_exponent<kEmax>(m[b]);
+          e8[b] = (uint32_t)(X + 127);
+          const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+          const float lim = kMax * scale;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[tt >> 2] = fmaxf(a[tt >> 2], fabsf(src(rb, 8 * kb + tt, i)));
-        int X[2];
+          for (int h = 0; h < 2; ++h) {
+            const int t = 8 * kb + 2 * b + h;
+            w[b][h] = 0u;
+            if (t < KT) {
+              float c[4];
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) X[hf] = mx_exponent<kEmax>(pair16_max(a[hf]));
-#pragma unroll
-        for (int tt = 0; tt < 8; ++tt) {
-          const int t = 8 * kb + tt;
-          if (t < KT) {
-            const float scale = __builtin_amdgcn_ldexpf(1.0f, X[tt >> 2]);
-            const float lim = kMax * scale;
-            float c[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_fmed3f(src(rb, t, i), -lim, lim);
-            typedef short sh2 __attribute__((ext_vector_type(2)));
-            sh2 w = {0, 0};
-            if constexpr (E5M2) {
-              w = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(w, c[0], c[1], scale, false);
-              w = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(w, c[2], c[3], scale, true);
-            } else {
-              w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[0], c[1], scale, false);
-              w = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(w, c[2], c[3], scale, true);
+              for (int i = 0; i < 4; ++i) c[i] = __builtin_amdgcn_fmed3f(src(rb, t, i), -lim, lim);
+              typedef short sh2 __attribute__((ext_vector_type(2)));
+              sh2 q = {0, 0};
+              if constexpr (E5M2) {
+                q = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(q, c[0], c[1], scale, false);
+                q = __builtin_amdgcn_cvt_scalef32_pk_bf8_f32(q, c[2], c[3], scale, true);
+              } else {
+                q = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(q, c[0], c[1], scale, false);
+                q = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(q, c[2], c[3], scale, true);
+              }
+              w[b][h] = __builtin_bit_cast(uint32_t, q);
             }
-            v[rb][kb][tt] = __builtin_bit_cast(uint32_t, w);
-          } else {
-            v[rb][kb][tt] = 0u;
           }
         }
-        const int e0 = X[0] + 127, e1 = X[1] + 127;
-        const int send = g == 3 ? e0 : e1;
-        const auto r = __builtin_amdgcn_permlane32_swap((unsigned)send, (unsigned)send, false, false);
-        const int recv = (int)((threadIdx.x & 32) ? r[0] : r[1]);
-        sc[rb][kb] = (uint32_t)(g == 0 ? e0 : (g == 3 ? e1 : recv));
+        // lanes 0-31 keep blocks 0 and 2 and receive them from the lane 32 away; lanes
+        // 32-63 keep blocks 1 and 3 and receive those
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const auto r = __builtin_amdgcn_permlane32_swap(w[2 * p][h], w[2 * p + 1][h], false, false);
+            v[rb][kb][4 * p + h] = r[0];
+            v[rb][kb][4 * p + 2 + h] = r[1];
+          }
+        sc[rb][kb] = by_group(e8, g);
       }
   }
 };
@@ -288,9 +327,12 @@ struct BOp<4, KT, R> : MxF8Op<KT, R, false> {};
 template <int KT, int R>
 struct BOp<7, KT, R> : MxF8Op<KT, R, true> {};
 
-// MXFP4: per row block and k-block, 32 E2M1 elements (element 4 tt + i in nibble
-// 4 tt + i, eight to a dword) forming one block, the lane's own, with its E8M0 scale.
-// Elements are v / 2^X rounded to nearest even, saturating at +-6.
+// MXFP4 (E2M1 elements).  The instruction's lane group q holds slots 32 q .. 32 q + 31,
+// block q, and supplies its scale.  Each lane codes its 8 elements of every block into
+// one dword (nibble 4 h + i: tile 2 b + h, element i), and a 4 x 4 transpose over the
+// row's 4 lanes (one exchange with the lane 32 away, one with the lane 16 away) gives lane
+// group q dword s = lane group s's 8 elements of block q.  Elements are v / 2^X rounded
+// to nearest even, saturating at +-6.
 template <int KT, int R>
 struct BOp<5, KT, R> {
   static constexpr int KB = kblocks(5, KT);
@@ -298,49 +340,61 @@ struct BOp<5, KT, R> {
   uint32_t sc[R][KB];
   template <class F>
   __device__ __forceinline__ void build(F src) {
+    const int g = ((int)threadIdx.x >> 4) & 3;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        float m0 = 0.f, m1 = 0.f;
+        float m[4];
+        mx_block_max<KT>(src, rb, kb, m);
+        uint32_t e8[4], w[4];
 #pragma unroll
-        for (int tt = 0; tt < 8; ++tt)
-          if (8 * kb + tt < KT)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (i & 1) m1 = fmaxf(m1, fabsf(src(rb, 8 * kb + tt, i)));
-              else m0 = fmaxf(m0, fabsf(src(rb, 8 * kb + tt, i)));
-            }
-        const int X = mx_exponent<2>(fmaxf(m0, m1));
-        const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-          // byte 2 k + p of the dword holds elements 8 d + 4 k + 2 p (low nibble) and + 1,
-          // tile t = 8 kb + 2 d + k
-          const int t0 = 8 * kb + 2 * d, t1 = t0 + 1;
-          uint32_t w = 0u;
+        for (int b = 0; b < 4; ++b) {
+          const int X = mx_exponent<2>(m[b]);
+          e8[b] = (uint32_t)(X + 127);
+          const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+          uint32_t q = 0u;
+          const int t0 = 8 * kb + 2 * b, t1 = t0 + 1;
           if (t0 < KT) {
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t0, 0), src(rb, t0, 1), scale, 0);
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t0, 2), src(rb, t0, 3), scale, 1);
+            q = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(q, src(rb, t0, 0), src(rb, t0, 1), scale, 0);
+            q = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(q, src(rb, t0, 2), src(rb, t0, 3), scale, 1);
           }
           if (t1 < KT) {
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t1, 0), src(rb, t1, 1), scale, 2);
-            w = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(w, src(rb, t1, 2), src(rb, t1, 3), scale, 3);
+            q = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(q, src(rb, t1, 0), src(rb, t1, 1), scale, 2);
+            q = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(q, src(rb, t1, 2), src(rb, t1, 3), scale, 3);
           }
-          v[rb][kb][d] = w;
+          w[b] = q;
         }
-        sc[rb][kb] = (uint32_t)(X + 127);
+        // transpose: [w0 w1 w2 w3] of lane group s (block b in w_b) -> lane group q holds
+        // [block q of groups 0, 1, 2, 3]
+        uint32_t t4[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const auto r = __builtin_amdgcn_permlane32_swap(w[k], w[k + 2], false, false);
+          t4[k] = r[0];
+          t4[k + 2] = r[1];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k += 2) {
+          const auto r = __builtin_amdgcn_permlane16_swap(t4[k], t4[k + 1], false, false);
+          v[rb][kb][k] = r[0];
+          v[rb][kb][k + 1] = r[1];
+        }
+        sc[rb][kb] = by_group(e8, g);
       }
   }
 };
 
-// MXFP6: per row block and k-block, 32 6-bit elements, E2M3 (E3M2 when E3M2 is set),
-// forming one block, the lane's own (element 4 tt + i = feature 16 (8 kb + tt) + 4 g + i in bits
-// 6 e .. 6 e + 5 of six dwords), with its E8M0 scale.  The conversion takes two vectors of
-// 16 values and interleaves them (element 2 j from the first, 2 j + 1 from the second),
-// rounds v / 2^X to nearest even and saturates (+-7.5, E3M2 +-28).  It writes its result while it still reads its sources, so the
-// result must not share registers with them: the instruction is issued with an
-// early-clobber result operand (the builtin's register allocation allows the overlap).
+// MXFP6 (E2M3 elements, E3M2 when E3M2 is set).  The lane layout is MXFP4's: lane group q
+// holds block q as its 32 elements, element 8 s + 4 h + i from lane group s (tile 2 q + h,
+// feature 4 s + i).  The FP32 values are transposed over the row's 4 lanes first (16
+// exchanges with the lane 32 away, 16 with the lane 16 away), so that each lane holds its
+// whole block and takes its scale from its own 32 values.  The conversion takes two
+// vectors of 16 values and interleaves them (element 2 j from the first, 2 j + 1 from the
+// second), rounds v / 2^X to nearest even and saturates (+-7.5, E3M2 +-28).  It writes its
+// result while it still reads its sources, so the result must not share registers with
+// them: the instruction is issued with an early-clobber result operand (the builtin's
+// register allocation allows the overlap).
 template <int KT, int R, bool E3M2>
 struct MxF6Op {
   static constexpr int KB = kblocks(6, KT);
@@ -353,19 +407,46 @@ struct MxF6Op {
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        f16v a, b;
+        uint32_t c[4][8];   // c[b][4 h + i]: this lane's elements of block b
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int t = 8 * kb + 2 * b + h;
+              c[b][4 * h + i] = __float_as_uint(t < KT ? src(rb, t < KT ? t : 0, i) : 0.f);
+            }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const auto r = __builtin_amdgcn_permlane32_swap(c[k][e], c[k + 2][e], false, false);
+            c[k][e] = r[0];
+            c[k + 2][e] = r[1];
+          }
+#pragma unroll
+        for (int k = 0; k < 4; k += 2)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const auto r = __builtin_amdgcn_permlane16_swap(c[k][e], c[k + 1][e], false, false);
+            c[k][e] = r[0];
+            c[k + 1][e] = r[1];
+          }
+        // now c[s][e'] is element 8 s + e' of this lane group's block
+        f16v a, bv;
         float m0 = 0.f, m1 = 0.f;
 #pragma unroll
-        for (int tt = 0; tt < 8; ++tt)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int t = 8 * kb + tt, e = 4 * tt + i;
-            const float x = t < KT ? src(rb, t < KT ? t : 0, i) : 0.f;
-            if (e & 1) {
-              b[e >> 1] = x;
+          for (int e = 0; e < 8; ++e) {
+            const int el = 8 * s + e;
+            const float x = __uint_as_float(c[s][e]);
+            if (el & 1) {
+              bv[el >> 1] = x;
               m1 = fmaxf(m1, fabsf(x));
             } else {
-              a[e >> 1] = x;
+              a[el >> 1] = x;
               m0 = fmaxf(m0, fabsf(x));
             }
           }
@@ -373,11 +454,11 @@ struct MxF6Op {
         const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
         typedef unsigned u6v __attribute__((ext_vector_type(6)));
         u6v r;
-        // early-clobber result: the destination registers may not overlap a, b or scale
+        // early-clobber result: the destination registers may not overlap a, bv or scale
         if constexpr (E3M2)
-          asm("v_cvt_scalef32_2xpk16_bf6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
+          asm("v_cvt_scalef32_2xpk16_bf6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(bv), "v"(scale));
         else
-          asm("v_cvt_scalef32_2xpk16_fp6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(b), "v"(scale));
+          asm("v_cvt_scalef32_2xpk16_fp6_f32 %0, %1, %2, %3" : "=&v"(r) : "v"(a), "v"(bv), "v"(scale));
 #pragma unroll
         for (int d = 0; d < 6; ++d) v[rb][kb][d] = r[d];
         sc[rb][kb] = (uint32_t)(X + 127);

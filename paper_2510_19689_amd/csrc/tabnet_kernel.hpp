@@ -45,18 +45,20 @@
 // In E4M3 and INT8 the gate half's shifts and scales are stored multiplied by -log2(e),
 // the factor of the sigmoid's exponent, and the shifts are not divided by the scales (the
 // products of codes are dequantised before the shift is added).
-// MX formats (OCP microscaling: blocks of 32 K positions share a power-of-two E8M0
-// scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA: MXFP8 (E4M3 or E5M2
-// elements) packs per k-block [64 lanes x 16 B: elements 0-15][64 x 16 B: elements
-// 16-31][64 x 4 B: the E8M0 scale each lane supplies, in byte 0]; MXFP6 (E2M3 or E3M2)
-// packs [64 x 16 B: bytes 0-15][64 x 8 B: bytes 16-23 of 32 six-bit elements, element e in
-// bits 6 e .. 6 e + 5][64 x 4 B: scales]; MXFP4 packs [64 x 16 B: 32 E2M1 elements, element
-// e in nibble e][64 x 4 B: scales].  Element e of a lane holds feature
-// 16 (8 kb + e / 4) + 4 q + e % 4.  The instruction groups a lane row's 128 K slots into
-// four blocks of 32 consecutive slots and takes block b's scale from lane group b:
-//   MXFP6, MXFP4: lane group q holds slots 32 q + e, so its block is its own 32 elements;
-//   MXFP8: lane group q holds slots 16 q + e (e < 16) and 64 + 16 q + (e - 16), so block
-//          b' + 2 h (b' = q / 2, h = e / 16) pairs lane groups 2 b' and 2 b' + 1.
+// MX formats (OCP microscaling: blocks of 32 consecutive K positions share a power-of-two
+// E8M0 scale) take eight K tiles per k-block, one 16x16x128 scaled MFMA; block b of a
+// k-block is tiles 2 b and 2 b + 1.  MXFP8 (E4M3 or E5M2 elements) packs per k-block
+// [64 lanes x 16 B: elements 0-15][64 x 16 B: elements 16-31][64 x 4 B: the E8M0 scale
+// each lane supplies, in byte 0]; MXFP6 (E2M3 or E3M2) packs [64 x 16 B: bytes 0-15]
+// [64 x 8 B: bytes 16-23 of 32 six-bit elements, element e in bits 6 e .. 6 e + 5]
+// [64 x 4 B: scales]; MXFP4 packs [64 x 16 B: 32 E2M1 elements, element e in nibble e]
+// [64 x 4 B: scales].  The instruction takes block b's scale from lane group b, and the
+// kernel moves each block's elements to the lane groups the instruction reads them from
+// (exchanges within a row's 4 lanes).  Element e of lane group q holds tile 2 blk + h of
+// the k-block and feature 4 s + i of that tile, with i = e % 4, h = (e % 8) / 4 and
+//   MXFP6, MXFP4: blk = q, s = e / 8 (lane group q holds instruction slots 32 q + e);
+//   MXFP8: blk = q / 2 (e < 16) or 2 + q / 2 (e >= 16), s = q % 2 + 2 ((e % 16) / 8)
+//          (lane group q holds slots 16 q + e for e < 16 and 64 + 16 q + e - 16).
 // The scales are applied inside the instruction, so MX units carry shifts only.
 #pragma once
 #include <stdint.h>

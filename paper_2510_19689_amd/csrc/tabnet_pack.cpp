@@ -366,9 +366,10 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
   } else if (precision == TABNET_MXFP8 || precision == TABNET_MXFP8_E5M2 || precision == TABNET_MXFP4 ||
              precision == TABNET_MXFP6 || precision == TABNET_MXFP6_E3M2) {
     // Per k-block of eight K tiles: the E8M0 exponent of each of an output row's four
-    // blocks, then the elements lane by lane, then the scale each lane supplies (the
-    // instruction takes block b's scale from lane group b).  The two 8-bit element forms
-    // share one layout, and so do the two 6-bit forms.
+    // blocks (block b = K tiles 2 b and 2 b + 1, i.e. 32 consecutive K positions), then the
+    // elements lane by lane in the order the kernel's B operand has them, then the scale
+    // each lane supplies (the instruction takes block b's scale from lane group b).  The
+    // two 8-bit element forms share one layout, and so do the 6- and 4-bit forms.
     const bool f8 = precision == TABNET_MXFP8 || precision == TABNET_MXFP8_E5M2;
     const bool f6 = precision == TABNET_MXFP6 || precision == TABNET_MXFP6_E3M2;
     const int emax = precision == TABNET_MXFP8        ? 8     // E4M3
@@ -378,32 +379,37 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
     uint8_t (*const enc8)(double) = precision == TABNET_MXFP8 ? e4m3_bits_rne : e5m2_bits_rne;
     uint8_t (*const enc6)(double) = precision == TABNET_MXFP6 ? e2m3_bits_rne : e3m2_bits_rne;
     const int KB = (KT + 7) / 8;
-    auto block_of = [&](int tt, int q) { return f8 ? q / 2 + 2 * (tt / 4) : q; };
-    auto val = [&](int i, int kb, int tt, int q, int j) {
-      const int t = 8 * kb + tt;
-      return t < KT ? wv(i, 16 * t + 4 * q + j) : 0.0;
+    // Element e of lane group q holds tile tt (of the k-block) and feature 4 s + i of it:
+    //   8-bit: e < 16 block q / 2, e >= 16 block 2 + q / 2, lane group s = q % 2 + 2 ((e % 16) / 8);
+    //   6-, 4-bit: block q, lane group s = e / 8;
+    // tile tt = 2 block + (e % 8) / 4, i = e % 4.
+    struct Slot {
+      int tt, k;   // tile within the k-block, offset 4 s + i within the tile
+    };
+    auto slot = [&](int q, int e) {
+      const int blk = f8 ? (e < 16 ? q / 2 : 2 + q / 2) : q;
+      const int sg = f8 ? q % 2 + 2 * ((e % 16) / 8) : e / 8;
+      return Slot{2 * blk + (e % 8) / 4, 4 * sg + e % 4};
+    };
+    auto val = [&](int i, int kb, Slot sl) {
+      const int t = 8 * kb + sl.tt;
+      return t < KT ? wv(i, 16 * t + sl.k) : 0.0;
     };
     for (int kb = kb_lo; kb < (kb_hi < 0 ? KB : kb_hi); ++kb) {
       int X[16][4];
-      for (int i = 0; i < 16; ++i) {
-        double amax[4] = {0, 0, 0, 0};
-        for (int tt = 0; tt < 8; ++tt)
-          for (int q = 0; q < 4; ++q)
-            for (int j = 0; j < 4; ++j) {
-              double& a = amax[block_of(tt, q)];
-              a = std::fmax(a, std::fabs(val(i, kb, tt, q, j)));
-            }
-        for (int b = 0; b < 4; ++b) X[i][b] = mx_exponent(amax[b], emax);
-      }
+      for (int i = 0; i < 16; ++i)
+        for (int b = 0; b < 4; ++b) {
+          double amax = 0;
+          for (int p = 0; p < 32; ++p) amax = std::fmax(amax, std::fabs(val(i, kb, Slot{2 * b + p / 16, p % 16})));
+          X[i][b] = mx_exponent(amax, emax);
+        }
+      auto code = [&](int i, int kb, Slot sl, auto enc) { return enc(std::ldexp(val(i, kb, sl), -X[i][sl.tt / 2])); };
       if (f8) {
         for (int half = 0; half < 2; ++half)
           for (int lane = 0; lane < 64; ++lane) {
             const int i = lane & 15, q = lane >> 4;
             uint8_t v[16];
-            for (int e = 16 * half; e < 16 * half + 16; ++e) {
-              const int tt = e / 4, j = e % 4;
-              v[e - 16 * half] = enc8(std::ldexp(val(i, kb, tt, q, j), -X[i][block_of(tt, q)]));
-            }
+            for (int e = 16 * half; e < 16 * half + 16; ++e) v[e - 16 * half] = code(i, kb, slot(q, e), enc8);
             emit(wts, v, sizeof v);
           }
       } else if (f6) {
@@ -414,8 +420,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
           const int i = lane & 15, q = lane >> 4;
           uint64_t w[3] = {0, 0, 0};
           for (int e = 0; e < 32; ++e) {
-            const int tt = e / 4, j = e % 4;
-            const uint64_t c = enc6(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
+            const uint64_t c = code(i, kb, slot(q, e), enc6);
             const int bit = 6 * e;
             w[bit / 64] |= c << (bit % 64);
             if (bit % 64 > 58) w[bit / 64 + 1] |= c >> (64 - bit % 64);
@@ -428,11 +433,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         for (int lane = 0; lane < 64; ++lane) {
           const int i = lane & 15, q = lane >> 4;
           uint8_t v[16] = {};
-          for (int e = 0; e < 32; ++e) {
-            const int tt = e / 4, j = e % 4;
-            const uint8_t c = e2m1_bits_rne(std::ldexp(val(i, kb, tt, q, j), -X[i][q]));
-            v[e / 2] |= (uint8_t)(c << (4 * (e & 1)));
-          }
+          for (int e = 0; e < 32; ++e) v[e / 2] |= (uint8_t)(code(i, kb, slot(q, e), e2m1_bits_rne) << (4 * (e & 1)));
           emit(wts, v, sizeof v);
         }
       }

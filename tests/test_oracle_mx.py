@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.rounding import (E2M1_MAX, E2M3_MAX, E3M2_MAX, E5M2_MAX, mx_block_of, mx_scale_exponent, round_e2m1,
-                             round_e2m3, round_e3m2, round_e4m3, round_e5m2, round_mx_rows)
+from oracle.rounding import (E2M1_MAX, E2M3_MAX, E3M2_MAX, E5M2_MAX, mx_scale_exponent, round_e2m1, round_e2m3,
+                             round_e3m2, round_e4m3, round_e5m2, round_mx_rows)
 from oracle import tabnet as ot
 
 FMTS = ["mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2", "mxfp4"]
@@ -15,7 +15,6 @@ ROUND = {"mxfp8": round_e4m3, "mxfp8_e5m2": round_e5m2, "mxfp6": round_e2m3, "mx
 # from the element formats' definitions: (emax, largest normal, stored mantissa bits)
 ELEM = {"mxfp8": (8, 448.0, 3), "mxfp8_e5m2": (15, 57344.0, 2), "mxfp6": (2, 7.5, 3), "mxfp6_e3m2": (4, 28.0, 2),
         "mxfp4": (2, 6.0, 1)}
-LANE_BLOCKS = ("mxfp4", "mxfp6", "mxfp6_e3m2")    # 4- and 6-bit elements: 32 slots per lane group
 
 
 def e2m1_table():
@@ -113,31 +112,6 @@ def test_e5m2_matches_torch_and_saturates():
     np.testing.assert_array_equal(round_e5m2(np.array([61440.0, 1e6, -7e4])), [E5M2_MAX, E5M2_MAX, -E5M2_MAX])
 
 
-def slot_block(p, fmt):
-    """The block of K position p derived from the matrix instruction's operand layout (a
-    row of 128 K slots over 4 lane groups of 32 elements; blocks are 32 consecutive
-    slots).  The position's lane group is q = (p % 16) // 4 and its element within the
-    lane e = 4 * (t % 8) + p % 4 for tile t = p // 16.  MXFP4 and MXFP6 lanes hold slots 32 q + e;
-    MXFP8 lanes (either element form) hold slots 16 q + e for e < 16 and 64 + 16 q + (e - 16)
-    for the rest."""
-    t, q = p // 16, (p % 16) // 4
-    e = 4 * (t % 8) + p % 4
-    if fmt in LANE_BLOCKS:
-        slot = 32 * q + e
-    else:
-        slot = 16 * q + e if e < 16 else 64 + 16 * q + (e - 16)
-    return (t // 8) * 4 + slot // 32
-
-
-@pytest.mark.parametrize("fmt", FMTS)
-def test_block_partition_matches_instruction_layout(fmt):
-    p = np.arange(512)
-    got = mx_block_of(p, fmt)
-    ref = np.array([slot_block(int(k), fmt) for k in p])
-    np.testing.assert_array_equal(got, ref)
-    assert (np.bincount(got) == 32).all()
-
-
 def test_scale_exponent_ocp_rule():
     amax = np.array([1.0, 1.5, 2.0, 448.0, 500.0, 2.0 ** -20, 0.0, 3.0e38, 1e-40])
     X8 = mx_scale_exponent(amax, "mxfp8")
@@ -154,45 +128,105 @@ def test_scale_exponent_ocp_rule():
         assert ((r >= 2.0 ** emax) & (r < 2.0 ** (emax + 1))).all()
 
 
-def brute_mx(x, fmt, offset):
-    """Element by element: find the element's block members, their maximum, the exponent,
-    then round (pure Python loops over a small matrix)."""
+def e4m3_table():
+    """The non-negative finite FP8 E4M3 (OCP E4M3FN) values in code order, decoded from the
+    bit fields: 4-bit exponent (bias 7), 3-bit mantissa, exponent 0 subnormal (m / 8 *
+    2^-6); code 0x7f (all ones) is NaN and has no value."""
+    vals = []
+    for c in range(0x7f):
+        e, m = c >> 3, c & 7
+        vals.append(m / 8.0 * 2.0 ** -6 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7))
+    return np.array(vals)
+
+
+def e5m2_table():
+    """The non-negative finite FP8 E5M2 values in code order: 5-bit exponent (bias 15),
+    2-bit mantissa, exponent 0 subnormal (m / 4 * 2^-14); exponent 31 holds inf and NaN."""
+    vals = []
+    for c in range(0x7c):
+        e, m = c >> 2, c & 3
+        vals.append(m / 4.0 * 2.0 ** -14 if e == 0 else (1 + m / 4.0) * 2.0 ** (e - 15))
+    return np.array(vals)
+
+
+def element_table(fmt):
+    return {"mxfp8": e4m3_table, "mxfp8_e5m2": e5m2_table, "mxfp6": lambda: e2m3_table()[:32],
+            "mxfp6_e3m2": e3m2_table, "mxfp4": lambda: e2m1_table()[:8]}[fmt]()
+
+
+def nearest_code(table, v):
+    """Value of the code nearest to v in the ascending table of non-negative values, ties
+    to the even code, saturating at the largest entry; the sign is carried over."""
+    a = min(abs(v), table[-1])
+    d = [abs(t - a) for t in table]
+    lo = min(d)
+    best = [i for i, x in enumerate(d) if x == lo]
+    code = best[0] if len(best) == 1 else [i for i in best if i % 2 == 0][0]
+    return -table[code] if v < 0 else table[code]
+
+
+def brute_mx(x, fmt):
+    """From the OCP MX definition alone, element by element (pure Python over a small
+    matrix): the element's block is the 32 consecutive elements k // 32 = j // 32; the
+    block's shared exponent is the X with 2^(X + emax) <= max|block| < 2^(X + emax + 1),
+    found by stepping X, clamped to the E8M0 range [-127 + 1, 127]; the element is the
+    format's code nearest to x / 2^X (ties to even), times 2^X."""
     rows, K = x.shape
     out = np.zeros_like(x)
-    emax, vmax, _ = ELEM[fmt]
+    emax = ELEM[fmt][0]
+    table = element_table(fmt)
     for r in range(rows):
         for j in range(K):
-            b = slot_block(j + offset, fmt)
-            members = [k for k in range(K) if slot_block(k + offset, fmt) == b]
+            members = [k for k in range(K) if k // 32 == j // 32]
             m = max(abs(x[r, k]) for k in members)
             if m == 0:
-                out[r, j] = 0.0
                 continue
-            X = int(np.floor(np.log2(m))) - emax
+            X = 0
+            while 2.0 ** (X + emax) > m:
+                X -= 1
+            while 2.0 ** (X + emax + 1) <= m:
+                X += 1
             X = min(max(X, -126), 127)
-            v = x[r, j] / 2.0 ** X
-            v = float(ROUND[fmt](np.array([v]))[0])
-            out[r, j] = max(-vmax, min(vmax, v)) * 2.0 ** X
+            out[r, j] = nearest_code(table, x[r, j] / 2.0 ** X) * 2.0 ** X
     return out
 
 
+def test_element_tables_decode_the_formats():
+    assert e4m3_table()[-1] == 448.0 and e4m3_table()[1] == 2.0 ** -9 and len(set(e4m3_table())) == 127
+    assert e5m2_table()[-1] == E5M2_MAX and e5m2_table()[1] == 2.0 ** -16 and len(set(e5m2_table())) == 124
+    for fmt in FMTS:
+        t = element_table(fmt)
+        assert (np.diff(t) > 0).all() and t[0] == 0.0 and t[-1] == ELEM[fmt][1]
+
+
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("K,offset", [(35, 0), (108, 0), (24, 8), (64, 0)])
-def test_round_mx_rows_matches_brute_force(fmt, K, offset):
-    rng = np.random.default_rng(K + offset)
-    x = rng.normal(0, 1, (4, K)) * np.array([[1.0], [1e-3], [300.0], [1.0]])
+@pytest.mark.parametrize("K", [8, 35, 64, 100, 108])
+def test_round_mx_rows_matches_brute_force(fmt, K):
+    rng = np.random.default_rng(K)
+    x = rng.normal(0, 1, (5, K)) * np.array([[1.0], [1e-3], [300.0], [1.0], [1.0]])
     x[3, :] = 0.0
     x[3, min(5, K - 1)] = -2.5
-    np.testing.assert_array_equal(round_mx_rows(x, fmt, offset), brute_mx(x, fmt, offset))
+    x[4, ::7] *= 40.0            # blocks of very different ranges side by side
+    np.testing.assert_array_equal(round_mx_rows(x, fmt), brute_mx(x, fmt))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_blocks_are_consecutive_32(fmt):
+    """A large value changes the scale of its own 32-element block only."""
+    x = np.random.default_rng(9).normal(0, 1, (1, 100))
+    big = x.copy()
+    big[0, 40] = 1e4
+    a, b = round_mx_rows(x, fmt), round_mx_rows(big, fmt)
+    changed = np.flatnonzero(a[0] != b[0])
+    assert changed.min() >= 32 and changed.max() < 64 and 40 in changed
 
 
 def test_mxfp8_elements_match_torch_e4m3_and_saturate():
     rng = np.random.default_rng(3)
     x = rng.normal(0, 1, (50, 128))
     got = round_mx_rows(x, "mxfp8")
-    blk = mx_block_of(np.arange(128), "mxfp8")
     for b in range(4):
-        cols = blk == b
+        cols = slice(32 * b, 32 * b + 32)
         X = mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), "mxfp8")
         sc = np.ldexp(1.0, X)
         # torch's E4M3 cast does not saturate: clamp to the largest normal first
@@ -216,10 +250,9 @@ def test_mx_exact_on_grid_and_scale_equivariant(fmt):
     np.testing.assert_array_equal(round_mx_rows(-x, fmt), -r)
     # per element: within half a step of the grid at the block's scale (the step of the
     # top binade [2^emax, 2^(emax+1)) bounds all), or saturated at the largest normal
-    blk = mx_block_of(np.arange(100), fmt)
     emax, vmax, mbits = ELEM[fmt]
-    for b in np.unique(blk):
-        cols = blk == b
+    for b in range(4):
+        cols = slice(32 * b, 32 * b + 32)
         sc = np.ldexp(1.0, mx_scale_exponent(np.abs(x[:, cols]).max(1, keepdims=True), fmt))
         step = sc * 2.0 ** (emax - mbits)
         err = np.abs(r[:, cols] - x[:, cols])
@@ -227,33 +260,34 @@ def test_mx_exact_on_grid_and_scale_equivariant(fmt):
         assert ((err <= step / 2 * (1 + 1e-12)) | sat).all()
 
 
-def test_mx_gemm_option_uses_both_operands_and_attention_offset(monkeypatch):
-    """_fc_bn rounds the input rows and the weight rows with the same K positions; the
-    attentive GEMM's positions start at n_d mod 16."""
+def test_mx_gemm_option_uses_both_operands_and_attention_half_from_zero(monkeypatch):
+    """_fc_bn rounds the input rows and the weight rows in blocks of the same 32 K
+    positions; the attentive GEMM's input is the attention half alone, so its blocks
+    start at its own first column."""
     rng = np.random.default_rng(5)
-    u = rng.normal(0, 1, (7, 24))
-    W = rng.normal(0, 0.3, (5, 24))
+    u = rng.normal(0, 1, (7, 40))
+    W = rng.normal(0, 0.3, (5, 40))
     eps = 2.0 ** -10
     bn = {"gamma": np.ones(5), "beta": np.zeros(5), "mean": np.zeros(5), "var": np.full(5, 1 - eps)}
     for fmt in ("mxfp8", "mxfp4"):
-        got = ot._fc_bn(u, W, bn, eps, weights=fmt, acts=fmt, k_offset=8)
-        ref = round_mx_rows(u, fmt, 8) @ round_mx_rows(W, fmt, 8).T
+        got = ot._fc_bn(u, W, bn, eps, weights=fmt, acts=fmt)
+        ref = brute_mx(u, fmt) @ brute_mx(W, fmt).T
         np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
-        # MXFP8 regroups these 24 columns under a shift of 4 positions (a shift of 8 keeps
-        # the groups; MXFP4 groups by 4-position group within 128, which a shift only
-        # relabels); columns of very different size make the grouping visible
-        v = u * np.where(np.arange(24) < 4, 100.0, 1.0)
-        same = np.array_equal(round_mx_rows(v, fmt, 4), round_mx_rows(v, fmt, 0))
-        assert same == (fmt == "mxfp4")
     seen = []
     real = ot._round_acts
 
-    def spy(u_, mode, k_offset=0):
-        seen.append((u_.shape[1], k_offset))
-        return real(u_, mode, k_offset)
+    def spy(u_, mode):
+        seen.append(u_.copy())
+        return real(u_, mode)
     monkeypatch.setattr(ot, "_round_acts", spy)
     from paper_2510_19689_amd import synth
-    p, X = synth.workload("hr35", rows=3)
-    ot.forward(p, X, weights="mxfp8", acts="mxfp8")
+    p, X = synth.workload("adult108", rows=3)
     cfg = p["config"]
-    assert (cfg.n_a, cfg.n_d % 16) in seen and all(o == 0 for k, o in seen if k != cfg.n_a)
+    _, _, _, inter = ot.forward(p, X, weights="mxfp8", acts="mxfp8", internals=True)
+    widths = [s_.shape[1] for s_ in seen]
+    # per pass: the first layer on D features, the later ones on N channels; per step the
+    # attentive GEMM on the n_a channels of the attention half
+    L = cfg.n_shared + cfg.n_indep
+    assert widths.count(cfg.D) == cfg.n_steps + 1
+    assert widths.count(cfg.n_d + cfg.n_a) == (cfg.n_steps + 1) * (L - 1)
+    assert widths.count(cfg.n_a) == cfg.n_steps

@@ -236,9 +236,9 @@ def test_int8_forward_invariants_and_attention_half_scale(monkeypatch):
     seen = []
     real = tabnet._round_acts
 
-    def spy(u, mode, k_offset=0):
+    def spy(u, mode):
         seen.append(u.shape[1])
-        return real(u, mode, k_offset)
+        return real(u, mode)
     monkeypatch.setattr(tabnet, "_round_acts", spy)
     tabnet.forward(p, X[:2], weights="int8", acts="int8")
     cfg = p["config"]
