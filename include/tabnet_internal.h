@@ -1,9 +1,11 @@
 /*
- * tabnet_internal.h -- host-only hooks of libtabnet for tests (no GPU needed).
+ * tabnet_internal.h -- host-only hooks for tests (no GPU needed).
  *
  * They expose the load-time arithmetic of tabnet_load (batch-norm folding, rounding,
- * header validation) so that it can be checked on a machine without a GPU.  None of
- * them touches the HIP runtime.
+ * header validation) and a serving runtime on a CPU stand-in device, so that they can be
+ * checked on a machine without a GPU.  None of them touches the HIP runtime.  They are
+ * exported by the test library libtabnet_test.so (the product library's code plus these
+ * hooks), not by libtabnet.so.
  */
 #ifndef TABNET_INTERNAL_H
 #define TABNET_INTERNAL_H
@@ -58,13 +60,15 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
                                        int64_t* wts_bytes, int64_t* n_chunks);
 
 /* A server whose device side is a CPU stand-in (no GPU needed), for testing the
- * scheduling: admission, ordering, splitting across launches, scattering, cancellation.
- * Its "model" writes logits[r][o] = X[r][o % D] + o, masks_agg = 2 X and
- * masks_step[s] = X + s; each launch additionally sleeps delay_us microseconds.
+ * scheduling: admission, ordering, splitting across launches, scattering, cancellation
+ * and failures.  Its "model" writes logits[r][o] = X[r][o % D] + o, masks_agg = 2 X and
+ * masks_step[s] = X + s; each launch additionally sleeps delay_us microseconds.  Launch
+ * number fail_launch (counted from 0 over the server's launches) fails to launch and
+ * launch number fail_wait fails when its completion is waited on; -1 disables either.
  * Stop it with tabnet_serve_stop. */
 tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs, int n_models,
-                                           const tabnet_serve_opts* opts, int delay_us,
-                                           tabnet_server** out);
+                                           const tabnet_serve_opts* opts, int delay_us, int fail_launch,
+                                           int fail_wait, tabnet_server** out);
 
 #ifdef __cplusplus
 }

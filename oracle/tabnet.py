@@ -170,10 +170,3 @@ def forward(params: dict, X, weights=None, acts=None, internals: bool = False):
         return logits, masks_agg, masks_step, {
             "x": x, "z": zs, "prior": priors, "eta": etas, "acc": acc, "agg": agg}
     return logits, masks_agg, masks_step
-
-
-def forward_chunked(params: dict, X, chunk: int = 16384, **kw):
-    """forward() over row chunks (rows are independent at inference)."""
-    outs = [forward(params, X[r:r + chunk], **kw) for r in range(0, X.shape[0], chunk)]
-    return (np.concatenate([o[0] for o in outs]), np.concatenate([o[1] for o in outs]),
-            np.concatenate([o[2] for o in outs], axis=1))

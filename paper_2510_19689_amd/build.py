@@ -20,14 +20,20 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtabnet.so")
 ARCH = "gfx950"
 
+TEST_LIB = os.path.join(HERE, "libtabnet_test.so")
+
+# libtabnet.so: the product.  libtabnet_test.so: the same code plus the host-only test
+# hooks (include/tabnet_internal.h) and the serving runtime's CPU stand-in device.
 SOURCES = [
     "tabnet_kernel.hip",
     "tabnet_stats.hip",
     "tabnet_pack.cpp",
     "tabnet_api.cpp",
-    "tabnet_hooks.cpp",
     "tabnet_serve.cpp",
     "tabnet_serve_exec.cpp",
+]
+TEST_SOURCES = [
+    "tabnet_hooks.cpp",
     "tabnet_serve_fake.cpp",
 ]
 
@@ -53,20 +59,27 @@ def _compile(src: str, obj: str) -> None:
         sys.stderr.write("\n".join(noise) + "\n")
 
 
+def _link(objs, out: str) -> None:
+    tmp = out + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = False) -> str:
-    """Compile all sources and link libtabnet.so next to this file; returns its path."""
+    """Compile all sources and link libtabnet.so (and the test library) next to this
+    file; returns the product library's path."""
+    srcs = SOURCES + TEST_SOURCES
     with tempfile.TemporaryDirectory(prefix="tabnet_build_") as tmp:
-        objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
-        with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-            list(ex.map(_compile, SOURCES, objs))
-        out_tmp = LIB + ".tmp"
-        cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-        os.replace(out_tmp, LIB)
+        objs = [os.path.join(tmp, s + ".o") for s in srcs]
+        with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+            list(ex.map(_compile, srcs, objs))
+        _link(objs[:len(SOURCES)], LIB)
+        _link(objs, TEST_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {TEST_LIB}")
     return LIB
 
 

@@ -6,6 +6,7 @@
 
 #include "tabnet_handle.hpp"
 #include "tabnet_pack.hpp"
+#include "tabnet_serve.hpp"
 
 using namespace tabnet;
 
@@ -78,3 +79,17 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
 }
 
 }  // extern "C"
+
+extern "C" tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs, int n, const tabnet_serve_opts* opts,
+                                                      int delay_us, int fail_launch, int fail_wait,
+                                                      tabnet_server** out) {
+  using namespace tabnet;
+  if (!cfgs || n < 1 || !out) return TABNET_E_INVALID;
+  tabnet_serve_opts o;
+  tabnet_status st = fill_opts(opts, &o);
+  if (st != TABNET_OK) return st;
+  std::vector<ModelInfo> models;
+  for (int i = 0; i < n; ++i) models.push_back(info_of(cfgs[i], o.with_step_masks != 0, nullptr));
+  Executor* ex = make_fake_executor(models, o, delay_us, fail_launch, fail_wait);   // before models is moved
+  return start_with(std::move(models), ex, o, out);
+}

@@ -53,6 +53,8 @@ struct Request {
   uint64_t bytes;
   int64_t rows_launched = 0;
   int64_t rows_done = 0;
+  int segs_inflight = 0;         // segments launched whose completion has not been handled
+  bool failing = false;          // a segment failed; Failed once no segment is in flight
   ReqState state = ReqState::Pending;
 };
 
@@ -217,6 +219,7 @@ struct ServerImpl {
         }
         const int64_t take = std::min(r->rows - r->rows_launched, max_rows - L.rows);
         L.segs.push_back(Segment{r, r->rows_launched, take, L.rows});
+        ++r->segs_inflight;
         r->rows_launched += take;
         L.rows += take;
         if (r->rows_launched == r->rows)
@@ -235,7 +238,10 @@ struct ServerImpl {
       ++launches;
       launched_rows += L.rows;
       if (!ok) {
-        for (Segment& sg : L.segs) fail_request(sg.req);
+        for (Segment& sg : L.segs) {
+          --sg.req->segs_inflight;
+          fail_request(sg.req);
+        }
         free_slots.push_back(L.slot);
         continue;
       }
@@ -246,10 +252,23 @@ struct ServerImpl {
     cv_comp.notify_all();
   }
 
-  void fail_request(const std::shared_ptr<Request>& r) {   // mu held
-    if (r->state == ReqState::Failed) return;
-    if (r->state == ReqState::Admitted) inflight_bytes -= r->bytes;
+  // A segment of r failed (mu held).  Its rows not yet launched are dropped, and the
+  // request is reported Failed only once none of its segments is in flight, so that no
+  // copy-out can write to the caller's buffers after wait or poll has returned.
+  void fail_request(const std::shared_ptr<Request>& r) {
+    if (r->state != ReqState::Admitted) return;
+    if (!r->failing) {
+      r->failing = true;
+      for (auto it = admitted.begin(); it != admitted.end(); ++it)
+        if (*it == r) {
+          admitted.erase(it);
+          break;
+        }
+    }
+    if (r->segs_inflight > 0) return;
+    inflight_bytes -= r->bytes;
     r->state = ReqState::Failed;
+    r->X.reset();
     cv_done.notify_all();
   }
 
@@ -263,6 +282,10 @@ struct ServerImpl {
       }
       Launch L = std::move(inflight.front());
       inflight.pop_front();
+      // rows of a request that has failed elsewhere are not copied out (its buffers stay
+      // valid until it is reported: it still counts this segment as in flight)
+      std::vector<char> skip(L.segs.size());
+      for (size_t k = 0; k < L.segs.size(); ++k) skip[k] = L.segs[k].req->failing;
       lk.unlock();
       const bool ok = exec->wait(L.slot);
       const ModelInfo& mi = models[L.model];
@@ -276,7 +299,9 @@ struct ServerImpl {
         const float* lo = exec->out_logits(L.slot);
         const float* ag = exec->out_agg(L.slot);
         const float* ms = exec->out_steps(L.slot);
-        for (const Segment& sg : L.segs) {
+        for (size_t k = 0; k < L.segs.size(); ++k) {
+          if (skip[k]) continue;
+          const Segment& sg = L.segs[k];
           Request& r = *sg.req;
           copies.copy(r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4);
           copies.copy(r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4);
@@ -295,7 +320,8 @@ struct ServerImpl {
       }
       for (const Segment& sg : L.segs) {
         Request& r = *sg.req;
-        if (!ok) {
+        --r.segs_inflight;
+        if (!ok || r.failing) {
           fail_request(sg.req);
           continue;
         }

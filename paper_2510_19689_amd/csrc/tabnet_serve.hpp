@@ -9,6 +9,7 @@
 #include "../../include/tabnet.h"
 
 struct tabnet_handle;
+struct tabnet_server;
 
 namespace tabnet {
 
@@ -62,7 +63,16 @@ tabnet_status server_mask_stats(ServerImpl* s, int model, double* mean, double* 
 tabnet_status server_stop(ServerImpl* s);   // joins the threads, deletes the executor and s
 
 Executor* make_hip_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, tabnet_status* st);
-Executor* make_fake_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, int delay_us);
+// CPU stand-in (test library only); launch number fail_launch fails to launch and launch
+// number fail_wait fails when waited on (-1: never).
+Executor* make_fake_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, int delay_us,
+                             int fail_launch = -1, int fail_wait = -1);
+// Option defaults and validation, the per-model admission cost, and server start-up with
+// a given executor (shared by tabnet_serve_start and the test library's CPU server).
+tabnet_status fill_opts(const tabnet_serve_opts* in, tabnet_serve_opts* o);
+ModelInfo info_of(const tabnet_config& c, bool steps, tabnet_handle* h);
+tabnet_status start_with(std::vector<ModelInfo> models, Executor* ex, const tabnet_serve_opts& o,
+                         tabnet_server** out);
 void set_error(const std::string& msg);
 
 }  // namespace tabnet

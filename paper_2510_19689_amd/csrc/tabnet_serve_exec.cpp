@@ -196,7 +196,7 @@ struct tabnet_server {
   ServerImpl* impl;
 };
 
-namespace {
+namespace tabnet {
 
 tabnet_status fill_opts(const tabnet_serve_opts* in, tabnet_serve_opts* o) {
   std::memset(o, 0, sizeof *o);
@@ -229,7 +229,7 @@ tabnet_status start_with(std::vector<ModelInfo> models, Executor* ex, const tabn
   return TABNET_OK;
 }
 
-}  // namespace
+}  // namespace tabnet
 
 extern "C" {
 
@@ -253,18 +253,6 @@ tabnet_status tabnet_serve_start(tabnet_handle* const* hs, int n, const tabnet_s
   }
   Executor* ex = make_hip_executor(models, o, &st);
   if (!ex) return st;
-  return start_with(std::move(models), ex, o, out);
-}
-
-tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs, int n, const tabnet_serve_opts* opts,
-                                           int delay_us, tabnet_server** out) {
-  if (!cfgs || n < 1 || !out) return TABNET_E_INVALID;
-  tabnet_serve_opts o;
-  tabnet_status st = fill_opts(opts, &o);
-  if (st != TABNET_OK) return st;
-  std::vector<ModelInfo> models;
-  for (int i = 0; i < n; ++i) models.push_back(info_of(cfgs[i], o.with_step_masks != 0, nullptr));
-  Executor* ex = make_fake_executor(models, o, delay_us);   // before models is moved
   return start_with(std::move(models), ex, o, out);
 }
 

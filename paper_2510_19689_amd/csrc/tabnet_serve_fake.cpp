@@ -1,5 +1,6 @@
 // CPU stand-in executor of the serving runtime (no HIP): the scheduler's admission,
-// ordering, splitting and scattering can be tested, and sanitised, without a GPU.
+// ordering, splitting, scattering and failure handling can be tested, and sanitised,
+// without a GPU.  Test code only: it is linked into the test library, not libtabnet.so.
 #include <algorithm>
 #include <chrono>
 #include <thread>
@@ -19,6 +20,9 @@ class FakeExecutor : public Executor {
   tabnet_serve_opts o;
   Dims dm;
   int delay_us = 0;
+  int fail_launch = -1, fail_wait = -1;   // index of the launch that fails (-1: none)
+  int n_launch = 0;
+  std::vector<int> slot_launch;           // launch index held by each slot
   struct Slot {
     std::vector<float> x, lo, ag, ms;
     std::vector<double> st;      // mean[D], M2[D], n of the last launch's masks_agg
@@ -29,6 +33,7 @@ class FakeExecutor : public Executor {
     dm = max_dims(models);
     const size_t R = (size_t)o.max_rows_per_launch;
     slots.resize(o.slots);
+    slot_launch.assign(o.slots, -1);
     for (Slot& s : slots) {
       s.x.resize(R * dm.D);
       s.lo.resize(R * dm.n_out);
@@ -38,6 +43,9 @@ class FakeExecutor : public Executor {
   }
   float* input(int slot) override { return slots[slot].x.data(); }
   bool launch(int slot, int model, int64_t rows) override {
+    const int k = n_launch++;
+    slot_launch[slot] = k;
+    if (k == fail_launch) return false;
     Slot& s = slots[slot];
     const int D = models[model].cfg.D, n_out = models[model].cfg.n_out, S = models[model].cfg.n_steps;
     for (int64_t r = 0; r < rows; ++r) {
@@ -65,7 +73,7 @@ class FakeExecutor : public Executor {
     if (delay_us > 0) std::this_thread::sleep_for(std::chrono::microseconds(delay_us));
     return true;
   }
-  bool wait(int) override { return true; }
+  bool wait(int slot) override { return slot_launch[slot] != fail_wait; }
   const float* out_logits(int slot) override { return slots[slot].lo.data(); }
   const float* out_agg(int slot) override { return slots[slot].ag.data(); }
   const float* out_steps(int slot) override { return slots[slot].ms.empty() ? nullptr : slots[slot].ms.data(); }
@@ -74,11 +82,14 @@ class FakeExecutor : public Executor {
 
 }  // namespace
 
-Executor* make_fake_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, int delay_us) {
+Executor* make_fake_executor(const std::vector<ModelInfo>& models, const tabnet_serve_opts& o, int delay_us,
+                             int fail_launch, int fail_wait) {
   FakeExecutor* x = new FakeExecutor();
   x->models = models;
   x->o = o;
   x->delay_us = delay_us;
+  x->fail_launch = fail_launch;
+  x->fail_wait = fail_wait;
   x->init();
   return x;
 }

@@ -12,6 +12,8 @@ from typing import Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TABNET_LIB") or os.path.join(HERE, "libtabnet.so")
+# the product library plus the host-only test hooks (include/tabnet_internal.h)
+TEST_LIB_PATH = os.path.join(HERE, "libtabnet_test.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_IO, E_ADMISSION, E_TIMEOUT, E_STOPPED, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
@@ -53,17 +55,33 @@ class ServeStats(ctypes.Structure):
 
 
 _lib = None
+_test_lib = None
 
 
 def lib() -> ctypes.CDLL:
     """The loaded libtabnet.so (raises if it has not been built)."""
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"libtabnet.so not found at {LIB_PATH}; build it with "
+    if _lib is None:
+        _lib = _open(LIB_PATH)
+    return _lib
+
+
+def test_lib() -> ctypes.CDLL:
+    """The test library (libtabnet.so's code plus the host-only hooks of
+    include/tabnet_internal.h): for tests only."""
+    global _test_lib
+    if _test_lib is None:
+        L = _open(TEST_LIB_PATH)
+        _declare_hooks(L)
+        _test_lib = L
+    return _test_lib
+
+
+def _open(path: str) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"{os.path.basename(path)} not found at {path}; build it with "
                            "`python -m paper_2510_19689_amd.build` (hipcc, gfx950)")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     L.tabnet_load.argtypes = [ctypes.c_char_p, i32, i32, ctypes.POINTER(vp)]
     L.tabnet_load.restype = i32
@@ -82,36 +100,8 @@ def lib() -> ctypes.CDLL:
     L.tabnet_last_error.argtypes = []
     L.tabnet_last_error.restype = ctypes.c_char_p
     L.tabnet_abi_version.restype = i32
-    # host-only hooks (tabnet_internal.h)
-    L.tabnet_hook_bf16_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_bf16_bits.restype = ctypes.c_uint16
-    L.tabnet_hook_e4m3_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_e4m3_bits.restype = ctypes.c_uint8
-    L.tabnet_hook_e2m1_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_e2m1_bits.restype = ctypes.c_uint8
-    L.tabnet_hook_e2m3_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_e2m3_bits.restype = ctypes.c_uint8
-    L.tabnet_hook_e5m2_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_e5m2_bits.restype = ctypes.c_uint8
-    L.tabnet_hook_e3m2_bits.argtypes = [ctypes.c_double]
-    L.tabnet_hook_e3m2_bits.restype = ctypes.c_uint8
-    L.tabnet_hook_mx_exponent.argtypes = [ctypes.c_double, i32]
-    L.tabnet_hook_mx_exponent.restype = i32
-    L.tabnet_hook_int8_rows.argtypes = [vp, i32, i32, vp]
-    L.tabnet_hook_int8_rows.restype = None
-    L.tabnet_hook_parse.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(Config)]
-    L.tabnet_hook_parse.restype = i32
-    L.tabnet_hook_fold.argtypes = [vp, ctypes.c_size_t, i32, vp, vp,
-                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
-    L.tabnet_hook_fold.restype = i32
-    L.tabnet_hook_packed_sizes.argtypes = [vp, ctypes.c_size_t, i32,
-                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
-    L.tabnet_hook_packed_sizes.restype = i32
     L.tabnet_serve_start.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ServeOpts), ctypes.POINTER(vp)]
     L.tabnet_serve_start.restype = i32
-    L.tabnet_hook_serve_start_fake.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ServeOpts), i32,
-                                               ctypes.POINTER(vp)]
-    L.tabnet_hook_serve_start_fake.restype = i32
     L.tabnet_serve_submit.argtypes = [vp, i32, vp, i64, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_uint64)]
     L.tabnet_serve_submit.restype = i32
     L.tabnet_serve_wait.argtypes = [vp, ctypes.c_uint64, i64]
@@ -136,13 +126,45 @@ def lib() -> ctypes.CDLL:
     L.tabnet_serve_now_ns.restype = i64
     L.tabnet_serve_stop.argtypes = [vp]
     L.tabnet_serve_stop.restype = i32
-    _lib = L
     return L
 
 
-def check(status: int) -> None:
+def _declare_hooks(L) -> None:
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.tabnet_hook_bf16_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_bf16_bits.restype = ctypes.c_uint16
+    L.tabnet_hook_e4m3_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e4m3_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e2m1_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e2m1_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e2m3_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e2m3_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e5m2_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e5m2_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_e3m2_bits.argtypes = [ctypes.c_double]
+    L.tabnet_hook_e3m2_bits.restype = ctypes.c_uint8
+    L.tabnet_hook_mx_exponent.argtypes = [ctypes.c_double, i32]
+    L.tabnet_hook_mx_exponent.restype = i32
+    L.tabnet_hook_int8_rows.argtypes = [vp, i32, i32, vp]
+    L.tabnet_hook_int8_rows.restype = None
+    L.tabnet_hook_parse.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(Config)]
+    L.tabnet_hook_parse.restype = i32
+    L.tabnet_hook_fold.argtypes = [vp, ctypes.c_size_t, i32, vp, vp,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.tabnet_hook_fold.restype = i32
+    L.tabnet_hook_packed_sizes.argtypes = [vp, ctypes.c_size_t, i32,
+                                           ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.tabnet_hook_packed_sizes.restype = i32
+    L.tabnet_hook_serve_start_fake.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(ServeOpts), i32, i32, i32,
+                                               ctypes.POINTER(vp)]
+    L.tabnet_hook_serve_start_fake.restype = i32
+
+
+def check(status: int, L=None) -> None:
+    """Raise TabNetError for a non-OK status, with the message of the library L (default
+    libtabnet.so) that returned it."""
     if status != OK:
-        msg = lib().tabnet_last_error().decode(errors="replace")
+        msg = (L or lib()).tabnet_last_error().decode(errors="replace")
         raise TabNetError(status, msg)
 
 
@@ -151,6 +173,27 @@ def _stream_ptr(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
     return int(stream.cuda_stream)
+
+
+def _check_tensor(t, name: str, shape, device: int, dtype=None) -> None:
+    """t must be a contiguous tensor of `dtype` (float32 by default) and exactly `shape`
+    on GPU `device`: a host tensor's address must never reach a kernel."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be a CUDA tensor on cuda:{device}")
+    if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}{'' if t.is_contiguous() else ' (not contiguous)'}")
+
+
+def _check_host(a, name: str, shape) -> None:
+    """a must be a C-contiguous float32 numpy array of exactly `shape`."""
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float32 or not a.flags["C_CONTIGUOUS"] \
+            or tuple(a.shape) != tuple(shape):
+        got = f"{a.dtype} {a.shape}" if isinstance(a, np.ndarray) else type(a).__name__
+        raise ValueError(f"{name} must be a C-contiguous float32 array of shape {tuple(shape)}, got {got}")
 
 
 class Model:
@@ -189,8 +232,15 @@ class Model:
         return self._h
 
     def forward_into(self, X, logits, masks_agg, masks_step=None, stream=None) -> None:
-        """tabnet_forward on caller-provided device tensors (float32, contiguous)."""
-        B = int(X.shape[0])
+        """tabnet_forward on caller-provided device tensors (float32, contiguous, on the
+        model's GPU): X [B, D], logits [B, n_out], masks_agg [B, D], masks_step [S, B, D]."""
+        c = self.config
+        B = int(X.shape[0]) if hasattr(X, "shape") and len(X.shape) == 2 else -1
+        _check_tensor(X, "X", (B, c.D), self.device)
+        _check_tensor(logits, "logits", (B, c.n_out), self.device)
+        _check_tensor(masks_agg, "masks_agg", (B, c.D), self.device)
+        if masks_step is not None:
+            _check_tensor(masks_step, "masks_step", (c.n_steps, B, c.D), self.device)
         check(lib().tabnet_forward(self._h, X.data_ptr(), B, logits.data_ptr(),
                                    masks_agg.data_ptr(),
                                    None if masks_step is None else masks_step.data_ptr(),
@@ -210,7 +260,19 @@ class Model:
         self.n_cols = int(cards.size)
 
     def forward_raw_into(self, X_raw, logits, masks_agg_cols, masks_step_cols=None, stream=None) -> None:
-        """tabnet_forward_raw on caller-provided device tensors (float32, contiguous)."""
+        """tabnet_forward_raw on caller-provided device tensors (float32, contiguous, on the
+        model's GPU): X_raw [B, C], logits [B, n_out], masks [B, C] and [S, B, C]."""
+        c = self.config
+        B = int(X_raw.shape[0]) if hasattr(X_raw, "shape") and len(X_raw.shape) == 2 else -1
+        # before set_embeddings the library itself refuses the call (TABNET_E_INVALID)
+        C = getattr(self, "n_cols", None)
+        if C is None:
+            C = int(X_raw.shape[1]) if B >= 0 else -1
+        _check_tensor(X_raw, "X_raw", (B, C), self.device)
+        _check_tensor(logits, "logits", (B, c.n_out), self.device)
+        _check_tensor(masks_agg_cols, "masks_agg", (B, C), self.device)
+        if masks_step_cols is not None:
+            _check_tensor(masks_step_cols, "masks_step", (c.n_steps, B, C), self.device)
         check(lib().tabnet_forward_raw(self._h, X_raw.data_ptr(), int(X_raw.shape[0]), logits.data_ptr(),
                                        masks_agg_cols.data_ptr(),
                                        None if masks_step_cols is None else masks_step_cols.data_ptr(),
@@ -220,10 +282,9 @@ class Model:
         """Returns (logits[B, n_out], masks_agg[B, C], masks_step[S, B, C] or None)."""
         import torch
         C = getattr(self, "n_cols", 0)
-        if X_raw.dtype != torch.float32 or not X_raw.is_contiguous() or X_raw.dim() != 2 or X_raw.shape[1] != C:
-            raise ValueError(f"X_raw must be a contiguous float32 [B, {C}] tensor (after set_embeddings)")
+        B = int(X_raw.shape[0]) if hasattr(X_raw, "shape") and len(X_raw.shape) == 2 else -1
+        _check_tensor(X_raw, "X_raw (after set_embeddings)", (B, C), self.device)
         c = self.config
-        B = int(X_raw.shape[0])
         dev = X_raw.device
         lo = torch.empty((B, c.n_out), dtype=torch.float32, device=dev)
         ag = torch.empty((B, C), dtype=torch.float32, device=dev)
@@ -242,10 +303,9 @@ class Model:
 
     def forward(self, X, with_steps: bool = True, stream=None) -> Tuple:
         """Returns (logits[B, n_out], masks_agg[B, D], masks_step[S, B, D] or None)."""
-        import torch
-        if X.dtype != torch.float32 or not X.is_contiguous() or X.dim() != 2 or X.shape[1] != self.config.D:
-            raise ValueError(f"X must be a contiguous float32 [B, {self.config.D}] tensor")
-        lo, ag, ms = self.outputs(int(X.shape[0]), with_steps)
+        B = int(X.shape[0]) if hasattr(X, "shape") and len(X.shape) == 2 else -1
+        _check_tensor(X, "X", (B, self.config.D), self.device)
+        lo, ag, ms = self.outputs(B, with_steps)
         self.forward_into(X, lo, ag, ms, stream)
         return lo, ag, ms
 
@@ -258,6 +318,9 @@ def mask_stats_into(masks, mean, var, workspace, stream=None) -> None:
     """tabnet_mask_stats on caller-provided device tensors: masks float32 [B, D],
     mean / var float64 [D], workspace a device tensor of at least
     mask_stats_workspace_bytes(B, D) bytes."""
+    _check_stats_args(masks, mean, var)
+    if not workspace.is_cuda or workspace.device != masks.device or not workspace.is_contiguous():
+        raise ValueError(f"workspace must be a contiguous tensor on {masks.device}")
     B, D = int(masks.shape[0]), int(masks.shape[1])
     check(lib().tabnet_mask_stats(masks.data_ptr(), B, D, mean.data_ptr(), var.data_ptr(),
                                   workspace.data_ptr(), workspace.numel() * workspace.element_size(),
@@ -294,8 +357,8 @@ def mask_stats(masks, stream=None):
     """Per-column mean and population variance (float64 [D] tensors) of a device
     float32 [B, D] mask matrix."""
     import torch
-    if masks.dtype != torch.float32 or masks.dim() != 2 or not masks.is_contiguous():
-        raise ValueError("masks must be a contiguous float32 [B, D] tensor")
+    if masks.dtype != torch.float32 or masks.dim() != 2 or not masks.is_contiguous() or not masks.is_cuda:
+        raise ValueError("masks must be a contiguous float32 [B, D] CUDA tensor")
     B, D = int(masks.shape[0]), int(masks.shape[1])
     mean = torch.empty(D, dtype=torch.float64, device=masks.device)
     var = torch.empty(D, dtype=torch.float64, device=masks.device)
@@ -313,46 +376,68 @@ class Server:
 
     def __init__(self, models=None, mem_budget_bytes: int = 0, max_rows_per_launch: int = 0,
                  slots: int = 0, with_step_masks: bool = False, use_graph: bool = True,
-                 mask_stats_window: int = 0, fake_configs=None, fake_delay_us: int = 0):
+                 mask_stats_window: int = 0, fake_configs=None, fake_delay_us: int = 0,
+                 fake_fail_launch: int = -1, fake_fail_wait: int = -1):
         o = ServeOpts(mem_budget_bytes=mem_budget_bytes, max_rows_per_launch=max_rows_per_launch,
                       slots=slots, with_step_masks=int(with_step_masks), use_graph=int(use_graph),
                       mask_stats_window=int(mask_stats_window))
         h = ctypes.c_void_p()
         if fake_configs is not None:
+            self._L = test_lib()
             arr = (Config * len(fake_configs))(*fake_configs)
-            check(lib().tabnet_hook_serve_start_fake(arr, len(fake_configs), ctypes.byref(o),
-                                                     fake_delay_us, ctypes.byref(h)))
+            check(self._L.tabnet_hook_serve_start_fake(arr, len(fake_configs), ctypes.byref(o), fake_delay_us,
+                                                       fake_fail_launch, fake_fail_wait, ctypes.byref(h)), self._L)
             self.configs = list(fake_configs)
         else:
+            self._L = lib()
             hs = (ctypes.c_void_p * len(models))(*[m.handle.value for m in models])
-            check(lib().tabnet_serve_start(hs, len(models), ctypes.byref(o), ctypes.byref(h)))
+            check(self._L.tabnet_serve_start(hs, len(models), ctypes.byref(o), ctypes.byref(h)), self._L)
             self.configs = [m.config for m in models]
         self._s = h
         self.with_step_masks = with_step_masks
+        self._live = {}      # request id -> the host arrays the library writes to
 
     def submit(self, model: int, X, logits, masks_agg, masks_step=None, arrival_ns: int = 0) -> int:
+        """Queue a request on host arrays (C-contiguous float32): X [rows, D], logits
+        [rows, n_out], masks_agg [rows, D] and, if given, masks_step [S, rows, D].  The
+        arrays are kept referenced here until wait() or poll() reports the request done."""
+        if not 0 <= model < len(self.configs):
+            raise ValueError(f"model index {model} out of range")
+        c = self.configs[model]
+        rows = int(X.shape[0]) if getattr(X, "ndim", 0) == 2 else -1
+        _check_host(X, "X", (rows, c.D))
+        _check_host(logits, "logits", (rows, c.n_out))
+        _check_host(masks_agg, "masks_agg", (rows, c.D))
+        if masks_step is not None:
+            _check_host(masks_step, "masks_step", (c.n_steps, rows, c.D))
         rid = ctypes.c_uint64()
-        check(lib().tabnet_serve_submit(self._s, model, X.ctypes.data, int(X.shape[0]), logits.ctypes.data,
+        check(self._L.tabnet_serve_submit(self._s, model, X.ctypes.data, rows, logits.ctypes.data,
                                         masks_agg.ctypes.data,
                                         None if masks_step is None else masks_step.ctypes.data,
-                                        int(arrival_ns), ctypes.byref(rid)))
+                                        int(arrival_ns), ctypes.byref(rid)), self._L)
+        self._live[rid.value] = (X, logits, masks_agg, masks_step)
         return rid.value
 
     def wait(self, rid: int, timeout_us: int = -1) -> int:
-        return lib().tabnet_serve_wait(self._s, rid, timeout_us)
+        st = self._L.tabnet_serve_wait(self._s, rid, timeout_us)
+        if st != E_TIMEOUT:
+            self._live.pop(rid, None)
+        return st
 
     def poll(self, rid: int):
         d = ctypes.c_int()
-        st = lib().tabnet_serve_poll(self._s, rid, ctypes.byref(d))
+        st = self._L.tabnet_serve_poll(self._s, rid, ctypes.byref(d))
+        if st != OK or d.value:
+            self._live.pop(rid, None)
         return st, bool(d.value)
 
     def stats(self) -> dict:
         st = ServeStats()
-        check(lib().tabnet_serve_get_stats(self._s, ctypes.byref(st)))
+        check(self._L.tabnet_serve_get_stats(self._s, ctypes.byref(st)), self._L)
         return st.as_dict()
 
     def reset_stats(self) -> None:
-        check(lib().tabnet_serve_reset_stats(self._s))
+        check(self._L.tabnet_serve_reset_stats(self._s), self._L)
 
     def mask_stats(self, model: int):
         """(mean [D], var [D], rows) of masks_agg over the model's last mask_stats_window
@@ -362,8 +447,8 @@ class Server:
         mean = np.zeros(D, np.float64)
         var = np.zeros(D, np.float64)
         rows = ctypes.c_int64()
-        check(lib().tabnet_serve_mask_stats(self._s, model, mean.ctypes.data, var.ctypes.data,
-                                            ctypes.byref(rows)))
+        check(self._L.tabnet_serve_mask_stats(self._s, model, mean.ctypes.data, var.ctypes.data,
+                                            ctypes.byref(rows)), self._L)
         return mean, var, rows.value
 
     @staticmethod
@@ -372,8 +457,9 @@ class Server:
 
     def stop(self) -> None:
         if self._s is not None and self._s.value:
-            check(lib().tabnet_serve_stop(self._s))
+            check(self._L.tabnet_serve_stop(self._s), self._L)
             self._s = ctypes.c_void_p()
+            self._live.clear()
 
     def __enter__(self):
         return self

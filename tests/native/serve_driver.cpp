@@ -1,7 +1,8 @@
 // Host-only driver for the serving scheduler with the CPU stand-in executor; built by
 // tests/test_sanitizers.py under ThreadSanitizer and under AddressSanitizer+UBSan.
 // Several submitter threads, requests split across launches, concurrent waits, stop; then
-// megabyte requests that take the split path of the server's host copies.
+// megabyte requests that take the split path of the server's host copies; then a split
+// request whose second launch fails.
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -120,5 +121,46 @@ int main() {
   server_stats(sw, &sw_st);
   server_stop(sw);
   std::printf("wide completed=%llu bad=%d\n", (unsigned long long)sw_st.completed, bad2.load());
-  return (bad2.load() == 0 && sw_st.completed == 8) ? 0 : 1;
+  if (bad2.load() != 0 || sw_st.completed != 8) return 1;
+
+  // A request split over four launches whose second launch fails when waited on: once
+  // wait reports the failure the caller frees its buffers at once (AddressSanitizer sees
+  // any later write), and the next requests are served.
+  tabnet_serve_opts of = o;
+  of.max_rows_per_launch = 100;
+  of.slots = 2;
+  of.with_step_masks = 0;
+  of.mem_budget_bytes = 1ull << 30;
+  Executor* ef = make_fake_executor(models, of, 2000, -1, 1);
+  ServerImpl* sf = nullptr;
+  if (server_create(models, ef, of, &sf) != TABNET_OK) return 2;
+  int bad3 = 0;
+  {
+    const int rows = 350;
+    float* Xf = new float[rows * 9];
+    float* lof = new float[rows * 3];
+    float* agf = new float[rows * 9];
+    for (int k = 0; k < rows * 9; ++k) Xf[k] = (float)(k % 17);
+    uint64_t fid = 0;
+    if (server_submit(sf, 0, Xf, rows, lof, agf, nullptr, 0, &fid) != TABNET_OK) ++bad3;
+    if (server_wait(sf, fid, -1) != TABNET_E_HIP) ++bad3;
+    delete[] Xf;
+    delete[] lof;
+    delete[] agf;
+  }
+  for (int k = 0; k < 4; ++k) {
+    std::vector<float> Xg(60 * 9, 1.5f), log(60 * 3), agg(60 * 9);
+    uint64_t gid = 0;
+    if (server_submit(sf, 0, Xg.data(), 60, log.data(), agg.data(), nullptr, 0, &gid) != TABNET_OK ||
+        server_wait(sf, gid, -1) != TABNET_OK)
+      ++bad3;
+    for (float v : agg)
+      if (v != 3.f) ++bad3;
+  }
+  tabnet_serve_stats sf_st{};
+  server_stats(sf, &sf_st);
+  if (sf_st.inflight_bytes != 0) ++bad3;
+  server_stop(sf);
+  std::printf("failed split request: bad=%d\n", bad3);
+  return bad3 == 0 ? 0 : 1;
 }

@@ -16,14 +16,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def L():
-    if not os.path.exists(tb.LIB_PATH):
-        pytest.fail("libtabnet.so is not built (run __graft_entry__.build())")
-    return tb.lib()
+    """The test library: libtabnet.so's code plus the host-only hooks."""
+    if not os.path.exists(tb.TEST_LIB_PATH):
+        pytest.fail("libtabnet_test.so is not built (run __graft_entry__.build())")
+    return tb.test_lib()
 
 
-def declared_functions():
+def declared_functions(headers=("tabnet.h", "tabnet_internal.h")):
     names = []
-    for hdr in ("tabnet.h", "tabnet_internal.h"):
+    for hdr in headers:
         src = open(os.path.join(ROOT, "include", hdr)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         names += re.findall(r"\b(tabnet_[a-z0-9_]+)\s*\(", src)
@@ -31,11 +32,18 @@ def declared_functions():
 
 
 def test_exports_every_declared_symbol(L):
-    names = declared_functions()
-    assert "tabnet_forward" in names and "tabnet_load" in names
-    for n in names:
-        assert hasattr(L, n), f"{n} declared in include/ but not exported"
-    assert L.tabnet_abi_version() >= 100
+    """libtabnet.so exports every function of the public header and none of the test
+    hooks; the test library exports both."""
+    public, hooks = declared_functions(("tabnet.h",)), declared_functions(("tabnet_internal.h",))
+    assert "tabnet_forward" in public and "tabnet_load" in public and "tabnet_hook_parse" in hooks
+    prod = ctypes.CDLL(tb.LIB_PATH)
+    for n in public:
+        assert hasattr(prod, n), f"{n} declared in include/tabnet.h but not exported by libtabnet.so"
+        assert hasattr(L, n), f"{n} missing from the test library"
+    for n in hooks:
+        assert not hasattr(prod, n), f"test hook {n} exported by libtabnet.so"
+        assert hasattr(L, n), f"{n} declared in include/tabnet_internal.h but not exported by the test library"
+    assert prod.tabnet_abi_version() >= 100
 
 
 def test_missing_and_bad_files(tmp_path, L):

@@ -26,7 +26,7 @@ def models(tmp_path_factory):
         pytest.fail("GPU test run without a visible GPU")
     d = tmp_path_factory.mktemp("serve")
     out = {}
-    for name in ("adult108", "hr35"):
+    for name in ("adult108", "hr35", "wide200", "wide512"):
         p = synth.make_params(synth.WORKLOADS[name]["cfg"], synth.WEIGHT_SEED[name])
         path = str(d / f"{name}.tnw")
         synth.write_weights(p, path)
@@ -132,3 +132,50 @@ def test_serve_without_step_masks_and_tiny_requests(models):
         for r, lo, ag, _ in outs:
             np.testing.assert_array_equal(lo, a_lo[r:r + 3])
             np.testing.assert_array_equal(ag, a_ag[r:r + 3])
+
+
+def test_four_resident_models_mixed_equals_alone(models):
+    """The multi-model load: four resident BF16 models (35, 108, 200 and 512 features; the
+    last on the split-feature kernel) served together, the model drawn per request,
+    1-8,192 rows per request (some split across launches).  Every request's logits and
+    masks equal that model's own forward of the request alone, bit for bit, and a sample
+    of rows of each model meets the BF16 gates against the FP64 oracle."""
+    names = ["hr35", "adult108", "wide200", "wide512"]
+    kinds = {"hr35": "hr", "adult108": "adult", "wide200": "wide", "wide512": "wide512"}
+    _say("case serve four models bf16")
+    ms_ = [tb.Model(models[n][1], "bf16") for n in names]
+    try:
+        cfgs = [m.config for m in ms_]
+        pools = [synth.make_inputs(kinds[n], 12000, 90 + k) for k, n in enumerate(names)]
+        rng = np.random.default_rng(23)
+        reqs = []
+        with tb.Server(ms_, max_rows_per_launch=8192, slots=3, with_step_masks=True, use_graph=True) as s:
+            for k in range(48):
+                m = int(rng.integers(0, 4))
+                rows = int(min(np.floor(np.exp(rng.uniform(0, np.log(8193)))), 8192))
+                off = int(rng.integers(0, pools[m].shape[0] - rows + 1))
+                X = np.ascontiguousarray(pools[m][off:off + rows])
+                c = cfgs[m]
+                lo = np.full((rows, c.n_out), np.nan, np.float32)
+                ag = np.full((rows, c.D), np.nan, np.float32)
+                mk = np.full((c.n_steps, rows, c.D), np.nan, np.float32)
+                reqs.append((m, X, lo, ag, mk, s.submit(m, X, lo, ag, mk)))
+            for r in reqs:
+                assert s.wait(r[5]) == tb.OK
+            st = s.stats()
+            _say("serve stats", {k: st[k] for k in ("completed", "launches", "mean_rows_per_launch", "p99_us")})
+        assert sorted({r[0] for r in reqs}) == [0, 1, 2, 3]
+        for m, X, lo, ag, mk, _ in reqs:
+            a_lo, a_ag, a_ms = alone(ms_[m], X)
+            np.testing.assert_array_equal(lo, a_lo)
+            np.testing.assert_array_equal(ag, a_ag)
+            np.testing.assert_array_equal(mk, a_ms)
+        for m in range(4):
+            m_reqs = [r for r in reqs if r[0] == m]
+            X, lo, ag = m_reqs[0][1][:32], m_reqs[0][2][:32], m_reqs[0][3][:32]
+            rlo, rag, _ = oracle.forward(models[names[m]][0], X)
+            assert np.abs(lo - rlo).max() <= 2e-2
+            assert np.abs(ag - rag).sum(-1).max() <= 1e-2
+    finally:
+        for m in ms_:
+            m.close()

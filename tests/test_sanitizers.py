@@ -27,3 +27,4 @@ def test_serve_scheduler_sanitized(tmp_path, san):
     assert "runtime error" not in r.stderr, r.stderr
     assert "completed=160 bad=0" in r.stdout
     assert "wide completed=8 bad=0" in r.stdout
+    assert "failed split request: bad=0" in r.stdout

@@ -3,6 +3,8 @@ against the library's CPU stand-in executor (no GPU).  The stand-in's "model" wr
 logits[r][o] = X[r][o % D] + o, masks_agg = 2 X and masks_step[s] = X + s."""
 import threading
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -117,11 +119,18 @@ def test_poll_wait_timeout_and_invalid():
         assert s.wait(i) == tb.OK
         assert s.wait(i) == tb.E_INVALID            # released after completion
         assert s.wait(12345) == tb.E_INVALID
-        for bad in (dict(model=1), dict(model=-1)):
-            with pytest.raises(tb.TabNetError):
-                s.submit(bad["model"], *r)
-        with pytest.raises(tb.TabNetError):
+        # the binding refuses bad arguments before the call ...
+        for bad in (1, -1):
+            with pytest.raises(ValueError):
+                s.submit(bad, *r)
+        with pytest.raises(ValueError):
             s.submit(0, np.zeros((0, c.D), np.float32), r[1], r[2])
+        # ... and so does the C ABI
+        rid = ctypes.c_uint64()
+        X, lo, ag = r[0], r[1], r[2]
+        for model, rows in ((1, 5), (-1, 5), (0, 0), (0, -3)):
+            assert s._L.tabnet_serve_submit(s._s, model, X.ctypes.data, rows, lo.ctypes.data, ag.ctypes.data, None,
+                                            0, ctypes.byref(rid)) == tb.E_INVALID
 
 
 def test_concurrent_submitters():
@@ -207,9 +216,9 @@ def test_mask_stats_errors():
     with tb.Server(fake_configs=[c], mask_stats_window=2) as s:
         buf = np.zeros(c.D, np.float64)
         for model in (1, -1):
-            assert tb.lib().tabnet_serve_mask_stats(s._s, model, buf.ctypes.data, buf.ctypes.data,
+            assert s._L.tabnet_serve_mask_stats(s._s, model, buf.ctypes.data, buf.ctypes.data,
                                                     None) == tb.E_INVALID
-        assert tb.lib().tabnet_serve_mask_stats(s._s, 0, None, buf.ctypes.data, None) == tb.E_INVALID
+        assert s._L.tabnet_serve_mask_stats(s._s, 0, None, buf.ctypes.data, None) == tb.E_INVALID
     with pytest.raises(tb.TabNetError):
         tb.Server(fake_configs=[c], mask_stats_window=-1)
 
@@ -231,3 +240,47 @@ def test_mixed_models_batch_per_model():
         st = s.stats()
         assert st["completed"] == 20
         assert st["launches"] <= 4, st["launches"]   # first request, then at most one per model per wave
+
+
+def test_submit_checks_host_arrays():
+    """The binding accepts only C-contiguous float32 arrays of the request's exact shapes."""
+    c = cfg()
+    rng = np.random.default_rng(11)
+    with tb.Server(fake_configs=[c], with_step_masks=True) as s:
+        X, lo, ag, ms = make_req(rng, 7, c)
+        for args in ((X.astype(np.float64), lo, ag, ms), (X, lo[:, :1], ag, ms), (X, lo, ag[:6], ms),
+                     (X, lo, ag, ms[:, :6]), (np.asfortranarray(X), lo, ag, ms), (X.tolist(), lo, ag, ms),
+                     (X[::2], lo, ag, ms)):
+            with pytest.raises(ValueError):
+                s.submit(0, *args)
+        i = s.submit(0, X, lo, ag, ms)
+        assert i in s._live
+        assert s.wait(i) == tb.OK and i not in s._live
+
+
+@pytest.mark.parametrize("fail", ["launch", "wait"])
+def test_failed_segment_of_split_request(fail):
+    """A request split over four launches whose second launch fails: the request is
+    reported failed (TABNET_E_HIP) only after its launched segments have drained, nothing
+    is written to its buffers after that, its rows left unlaunched are dropped, the
+    memory budget is given back, and later requests are served normally."""
+    c = cfg()
+    rng = np.random.default_rng(12)
+    kw = {"fake_fail_launch": 1} if fail == "launch" else {"fake_fail_wait": 1}
+    with tb.Server(fake_configs=[c], max_rows_per_launch=100, slots=2, fake_delay_us=20000, **kw) as s:
+        X, lo, ag, _ = make_req(rng, 350, c, steps=False)
+        i = s.submit(0, X, lo, ag)
+        assert s.wait(i) == tb.E_HIP
+        lo[:] = -7.0
+        ag[:] = -7.0
+        later = [make_req(rng, 60, c, steps=False) for _ in range(3)]
+        ids = [s.submit(0, *r) for r in later]
+        assert all(s.wait(j) == tb.OK for j in ids)
+        for (Xr, lor, agr, _m), _ in zip(later, ids):
+            np.testing.assert_array_equal(agr, 2 * Xr)
+        assert (lo == -7.0).all() and (ag == -7.0).all(), "written after the failure was reported"
+        st = s.stats()
+        assert st["inflight_bytes"] == 0
+        # the first request's launches: at most the two slots' worth before the failure
+        # was seen; none of its four 100-row segments after that
+        assert st["launches"] <= 3 + 3
