@@ -10,8 +10,14 @@ rows shaped like the paper's Adult table (Sec. IV-A), resident in HBM before tim
 
 The JSON line reports BF16 rows/s as `value`, the plain FP32 path and the reduced-precision
 paths (FP8, INT8, MX) on the same GPU beside it, the roofline of the fused kernel
-(algorithmic bytes per launch over the event-timed launch duration), the serving legs, and
-the FP64 CPU oracle timed on a bounded sample on the host.
+(algorithmic bytes per launch over the event-timed launch duration), the 200-feature model
+at 1,048,576 rows in FP32, BF16 and FP8, the serving legs (step masks returned, a stated
+p99 bound, per-model figures for the mixed load), and the FP64 CPU oracle timed on a
+bounded sample on the host's cores (one process per core).
+
+Before the W warm-up launches the GPU is brought to its steady clock by repeating the same
+forward for a fixed time (the first launches on an idle GPU run several percent slower);
+the ramp is reported in the line.
 """
 from __future__ import annotations
 
@@ -27,7 +33,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 BF16_PEAK_TFLOPS = 2500.0      # dense
+FP8_PEAK_TFLOPS = 5000.0       # dense
 FP32_MFMA_PEAK_TFLOPS = 157.3
+SERVE_P99_BOUND_MS = 10.0      # stated p99 bound of the single-model serving load (step masks on)
+CLOCK_RAMP_S = 0.3
 # The paper's own figures (Tables I and II): end-to-end serverless invocations of a small
 # TabNet (n_d = n_a = 8, 3 steps) through an HTTP gateway, on the hardware it names.  They
 # count invocation overhead, not kernel work: context beside the line, never vs_baseline.
@@ -83,6 +92,20 @@ def algorithmic(cfg, rows: int, with_steps: bool = True):
     macs_pass = k_first * 2 * N + (cfg.n_shared + cfg.n_indep - 1) * N * 2 * N
     macs = (S + 1) * macs_pass + S * n_a * D + n_d * cfg.n_out
     return byt * rows, 2 * macs * rows
+
+
+def clock_ramp(model, X, outs, seconds: float) -> int:
+    """Repeat the forward for `seconds` (untimed) so that the GPU runs at its steady clock;
+    returns the number of launches."""
+    import torch
+    lo, ag, ms = outs
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            model.forward_into(X, lo, ag, ms)
+        n += 10
+        torch.cuda.synchronize()
+    return n
 
 
 def time_forward(model, X, outs, steps: int, warmup: int):
@@ -200,22 +223,44 @@ def time_mask_stats(masks, steps: int, warmup: int, per_graph: int = 20):
     return e0.elapsed_time(e1) / 1e3 / (reps * per_graph)
 
 
-def cpu_baseline(params, X, budget_s: float = 12.0):
-    """The FP64 oracle on the host's cores over a bounded sample of the same rows."""
-    from threadpoolctl import threadpool_info
+def _oracle_rows(params, X, payload):
     from oracle import tabnet as oracle
-    chunk = 8192
-    done, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:      # cycles over the batch until the budget
-        start = done % X.shape[0]
-        n = min(chunk, X.shape[0] - start)
-        oracle.forward(params, X[start:start + n])
-        done += n
+    oracle.forward(params, X)
+    return X.shape[0]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(params, X, budget_s: float = 30.0):
+    """The FP64 oracle on the host's cores over a bounded sample of the same rows: one
+    single-threaded worker process per core (oracle.parallel), 8,192-row chunks.  A first
+    pass over the batch sizes the sample to about budget_s; the rate counts the whole pool
+    run (worker start-up included)."""
+    import numpy as np
+    from oracle import parallel
+    workers = parallel.default_workers()
+    t0 = time.perf_counter()
+    done = sum(r for _, r in parallel.map_rows(_oracle_rows, params, X, chunk=8192, workers=workers))
+    t1 = time.perf_counter() - t0
+    passes = max(1, int(budget_s / max(t1, 1e-3)))
+    Xs = np.tile(X, (passes, 1)) if passes > 1 else X
+    t0 = time.perf_counter()
+    done = sum(r for _, r in parallel.map_rows(_oracle_rows, params, Xs, chunk=8192, workers=workers))
     dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": done / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} rows ({done / X.shape[0]:.2f} passes over the {X.shape[0]} benchmark "
-                      f"rows), FP64 numpy oracle in {chunk}-row chunks, {dt:.1f} s"}
+    return {"value": done / dt, "unit": "rows/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "sample": f"{done} rows ({passes} passes over the {X.shape[0]} benchmark rows), FP64 numpy oracle, "
+                      f"one single-threaded process per core ({workers}, OPENBLAS_NUM_THREADS=1), 8192-row "
+                      f"chunks, {dt:.1f} s including worker start-up"}
 
 
 def _ring_alloc(spans, head: int, need: int, size: int):
@@ -310,13 +355,60 @@ def serve_bench(models, Xpools, rates, warm_s: float, dur_s: float, step_masks: 
                 lock.notify_all()
             th.join()
             st = srv.stats()
-        out.append({"rate_req_s": lam, "requests": int(st["completed"]), "offered_rows_per_s": rows_meas / dur_s,
-                    "rows_per_s": st["rows_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
-                    "p999_ms": st["p999_us"] / 1e3, "mean_rows_per_launch": st["mean_rows_per_launch"],
-                    "launches": int(st["launches"])})
+            per = [srv.model_stats(k) for k in range(len(models))] if len(models) > 1 else []
+        pt = {"rate_req_s": lam, "requests": int(st["completed"]), "offered_rows_per_s": rows_meas / dur_s,
+              "rows_per_s": st["rows_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
+              "p999_ms": st["p999_us"] / 1e3, "mean_rows_per_launch": st["mean_rows_per_launch"],
+              "launches": int(st["launches"])}
+        if per:
+            pt["per_model"] = [{"requests": int(q["completed"]), "rows_per_s": q["rows_per_s"],
+                                "p50_ms": q["p50_us"] / 1e3, "p99_ms": q["p99_us"] / 1e3,
+                                "mean_rows_per_launch": q["mean_rows_per_launch"], "launches": int(q["launches"])}
+                               for q in per]
+        out.append(pt)
         print(f"[bench] serve{' mix' if len(models) > 1 else ''} {lam} req/s: p50 {st['p50_us']/1e3:.3f} ms "
               f"p99 {st['p99_us']/1e3:.3f} ms {st['rows_per_s']/1e6:.2f} M rows/s, "
               f"{st['mean_rows_per_launch']:.0f} rows/launch", file=sys.stderr, flush=True)
+    return out
+
+
+def wide_leg(precs, steps: int, tmpdir: str):
+    """The 200-feature model at its full batch (1,048,576 rows, D = 200, n_d = n_a = 64,
+    7 steps, step masks on) in each precision: time per launch (HIP events on the launch
+    stream, after a clock ramp and two untimed launches), rows/s, and the fractions of the
+    matrix-core roof of the precision and of the HBM roof."""
+    import torch
+    from paper_2510_19689_amd import synth, tabnet
+    cfg = synth.WORKLOADS["wide200"]["cfg"]
+    params, Xh = synth.workload("wide200")
+    rows = Xh.shape[0]
+    path = os.path.join(tmpdir, "wide200.tnw")
+    synth.write_weights(params, path)
+    X = torch.from_numpy(Xh).cuda()
+    byt, flops = algorithmic(cfg, rows, with_steps=True)
+    peaks = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS, "fp8": FP8_PEAK_TFLOPS}
+    n = max(3, steps // 5)
+    out = {"rows": rows, "D": cfg.D, "n_d": cfg.n_d, "n_a": cfg.n_a, "n_steps": cfg.n_steps,
+           "n_shared": cfg.n_shared, "n_indep": cfg.n_indep, "n_out": cfg.n_out, "masks_step": True,
+           "algorithmic_bytes_per_launch": byt, "algorithmic_flops_per_launch": flops, "launches_timed": n}
+    for prec in precs:
+        with tabnet.Model(path, prec) as m:
+            outs = m.outputs(rows, with_steps=True)
+            clock_ramp(m, X, outs, 0.1)
+            t, _ = time_forward(m, X, outs, n, 2)
+            per = t / n
+            out[prec] = {"ms_per_forward": per * 1e3, "rows_per_s": rows / per,
+                         "mfma_tflops": flops / per / 1e12, "mfma_frac": flops / per / 1e12 / peaks[prec],
+                         "hbm_GB_s": byt / per / 1e9, "hbm_frac": byt / per / 1e9 / HBM_PEAK_GBS}
+            print(f"[bench] wide200 {prec}: {per * 1e3:.2f} ms/forward, {rows / per / 1e6:.1f} M rows/s, "
+                  f"{out[prec]['mfma_frac'] * 100:.1f}% of the {prec} matrix roof", file=sys.stderr, flush=True)
+            del outs
+    if "bf16" in out and "fp32" in out:
+        out["bf16_over_fp32"] = out["fp32"]["ms_per_forward"] / out["bf16"]["ms_per_forward"]
+    if "bf16" in out and "fp8" in out:
+        out["fp8_over_bf16"] = out["bf16"]["ms_per_forward"] / out["fp8"]["ms_per_forward"]
+    del X
+    torch.cuda.empty_cache()
     return out
 
 
@@ -337,7 +429,15 @@ def main():
                          "empty to skip")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000",
                     help="request rates (req/s) of the serving leg; empty to skip")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-step-masks", type=int, default=1,
+                    help="serving requests also return the per-step masks (1) or only logits and the "
+                         "aggregate mask (0)")
+    ap.add_argument("--serve-mix-step-masks", type=int, default=0,
+                    help="mixed-load requests also return the per-step masks (1; up to 168 MB per "
+                         "8,192-row request of the 512-feature model) or not (0)")
+    ap.add_argument("--wide", default="fp32,bf16,fp8",
+                    help="precisions of the 200-feature leg (1,048,576 rows, 7 steps); empty to skip")
     ap.add_argument("--serve-mix-rates", default="2000,5000,10000",
                     help="request rates of a mixed load over four resident models (HR-, Adult-, "
                          "200- and 512-feature models, requests of 1..8192 rows); empty to skip")
@@ -392,6 +492,8 @@ def main():
                 continue
             with m:
                 outs = m.outputs(rows, with_steps=True)
+                if prec == "bf16":
+                    res["ramp"] = clock_ramp(m, X, outs, CLOCK_RAMP_S)
                 t, wall = time_forward(m, X, outs, args.steps, args.warmup)
                 res[prec] = (t, wall)
                 print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
@@ -421,11 +523,15 @@ def main():
                               f"{rows / t_raw / 1e6:.1f} M rows/s", file=sys.stderr, flush=True)
                         del routs, Xr
                 del outs
+        wide = None
+        if args.wide and name == "adult108":
+            wide = wide_leg([p for p in args.wide.split(",") if p], args.steps, d)
         serving = None
+        sm = bool(args.serve_step_masks)
         if args.serve_rates:
             rates = [int(r) for r in args.serve_rates.split(",") if r]
             with tabnet.Model(path, "bf16") as m:
-                serving = serve_bench([m], [Xh], rates, warm_s=0.5, dur_s=args.serve_seconds)
+                serving = serve_bench([m], [Xh], rates, warm_s=0.5, dur_s=args.serve_seconds, step_masks=sm)
         serving_mix = None
         if args.serve_mix_rates:
             rates = [int(r) for r in args.serve_mix_rates.split(",") if r]
@@ -437,11 +543,13 @@ def main():
                 models.append(tabnet.Model(p_nm, "bf16"))
                 pools.append(synth.make_inputs(synth.WORKLOADS[nm]["data"], 20000, synth.DATA_SEED[nm]))
             try:
-                serving_mix = {"models": names, "precision": "bf16", "masks": "logits + masks_agg",
+                smx = bool(args.serve_mix_step_masks)
+                serving_mix = {"models": names, "precision": "bf16",
+                               "masks": "logits + masks_agg" + (" + masks_step" if smx else ""),
                                "request_rows": "log-uniform 1..8192", "model_choice": "uniform, seeded",
-                               "arrivals": "Poisson, open loop",
+                               "arrivals": "Poisson, open loop", "seconds_per_rate": args.serve_seconds,
                                "points": serve_bench(models, pools, rates, warm_s=0.5, dur_s=args.serve_seconds,
-                                                     max_rows=8192, mix_seed=4000)}
+                                                     step_masks=smx, max_rows=8192, mix_seed=4000)}
             finally:
                 for m in models:
                     m.close()
@@ -501,6 +609,8 @@ def main():
         out["quantised"] = quant
     out["paper_context"] = PAPER_CONTEXT
     out["wall_s_bf16"] = wall_bf16
+    out["clock_ramp"] = {"seconds": CLOCK_RAMP_S, "launches": res.get("ramp", 0),
+                         "what": "untimed launches of the same forward before the warm-up"}
     if "detail" in res:
         out["bf16_forward_detail"] = res["detail"]
     if "raw" in res:
@@ -515,9 +625,15 @@ def main():
         out["mask_stats"] = {"what": "per-feature mean and variance of masks_agg", "rows": rows, "D": cfg.D,
                              "us_per_call": t_ms * 1e6, "GB_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
     if serving is not None:
-        out["serving"] = {"model": name, "precision": "bf16", "masks": "logits + masks_agg",
+        worst = max(pt["p99_ms"] for pt in serving)
+        out["serving"] = {"model": name, "precision": "bf16",
+                          "masks": "logits + masks_agg" + (" + masks_step" if sm else ""),
                           "request_rows": "log-uniform 1..4096", "arrivals": "Poisson, open loop",
-                          "points": serving}
+                          "seconds_per_rate": args.serve_seconds,
+                          "p99_bound_ms": SERVE_P99_BOUND_MS, "p99_worst_ms": worst,
+                          "p99_within_bound": bool(worst <= SERVE_P99_BOUND_MS), "points": serving}
+    if wide is not None:
+        out["wide200"] = wide
     if serving_mix is not None:
         out["serving_mix"] = serving_mix
     if not args.no_cpu_baseline:

@@ -331,8 +331,15 @@ tabnet_status tabnet_serve_wait(tabnet_server* s, uint64_t req_id, int64_t timeo
  * is what tabnet_serve_wait would return. */
 tabnet_status tabnet_serve_poll(tabnet_server* s, uint64_t req_id, int* done);
 
-/* Counters and latency percentiles since start or the last reset. */
+/* Counters and latency percentiles since start or the last reset.  (The getter is not
+ * named tabnet_serve_stats: in C that name is the statistics struct's.) */
 tabnet_status tabnet_serve_get_stats(tabnet_server* s, tabnet_serve_stats* out);
+/* The same for the requests of one model: submitted, admitted, completed, rejected,
+ * rows_completed, the latency percentiles and rows_per_s (its completed rows over the span
+ * from its first arrival to its last completion) count that model's requests only;
+ * launches and mean_rows_per_launch count the launches that served it; the in-flight
+ * byte counters are the server's.  TABNET_E_INVALID for a bad model index. */
+tabnet_status tabnet_serve_get_model_stats(tabnet_server* s, int model, tabnet_serve_stats* out);
 tabnet_status tabnet_serve_reset_stats(tabnet_server* s);
 
 /*

@@ -70,13 +70,21 @@ struct Launch {
   std::vector<Segment> segs;
 };
 
-// Host copies of the serving path, split over a few worker threads when large.  At ten
-// thousand mixed requests per second one thread's memcpy is about as fast as the rows
-// arrive, so copies of 1 MiB or more are cut into 64-byte-aligned pieces, one per worker
-// plus one for the calling thread, which waits for all of them.
+// Host copies of the serving path.  A launch's gather (request rows into the pinned input
+// buffer) and scatter (outputs into each request's buffers) are batches of copies; a batch
+// is cut into pieces of at most kPiece bytes (64-byte aligned) and shared by the worker
+// threads and the calling thread, which waits for all of them.  At ten thousand requests
+// per second with step masks the scatter alone is tens of GB/s, more than one thread's
+// memcpy.
 class CopyPool {
  public:
-  static constexpr size_t kMinSplit = 1 << 20;
+  static constexpr size_t kPiece = 256 << 10;
+
+  struct Item {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
 
   explicit CopyPool(int workers) {
     for (int i = 0; i < workers; ++i) thr_.emplace_back([this] { run(); });
@@ -89,25 +97,37 @@ class CopyPool {
     cv_.notify_all();
     for (auto& t : thr_) t.join();
   }
-  void copy(void* dst, const void* src, size_t bytes) {
-    if (bytes < kMinSplit || thr_.empty()) {
-      std::memcpy(dst, src, bytes);
+  void copy(void* dst, const void* src, size_t bytes) { copy_many({Item{dst, src, bytes}}); }
+
+  void copy_many(const std::vector<Item>& items) {
+    size_t total = 0;
+    for (const Item& it : items) total += it.bytes;
+    if (thr_.empty() || total < kPiece) {
+      for (const Item& it : items) std::memcpy(it.dst, it.src, it.bytes);
       return;
     }
-    const size_t parts = thr_.size() + 1;
-    const size_t piece = (bytes / parts + 63) & ~(size_t)63;
     Latch latch;
     {
       std::lock_guard<std::mutex> lk(mu_);
-      for (size_t k = 1; k < parts && k * piece < bytes; ++k) {
-        const size_t off = k * piece;
-        jobs_.push_back(Job{static_cast<char*>(dst) + off, static_cast<const char*>(src) + off,
-                            std::min(piece, bytes - off), &latch});
-        ++latch.n;
-      }
+      for (const Item& it : items)
+        for (size_t off = 0; off < it.bytes; off += kPiece) {
+          jobs_.push_back(Job{static_cast<char*>(it.dst) + off, static_cast<const char*>(it.src) + off,
+                              std::min(kPiece, it.bytes - off), &latch});
+          ++latch.n;
+        }
     }
     cv_.notify_all();
-    std::memcpy(dst, src, std::min(piece, bytes));
+    // the calling thread takes pieces too (any batch's: they are all short)
+    for (;;) {
+      Job j;
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (jobs_.empty()) break;
+        j = jobs_.front();
+        jobs_.pop_front();
+      }
+      finish(j);
+    }
     std::unique_lock<std::mutex> lk(latch.m);
     latch.cv.wait(lk, [&] { return latch.n == 0; });
   }
@@ -124,6 +144,12 @@ class CopyPool {
     size_t bytes;
     Latch* latch;
   };
+  static void finish(const Job& j) {
+    std::memcpy(j.dst, j.src, j.bytes);
+    // the waiter may destroy the latch as soon as it sees n == 0: touch it only here
+    std::lock_guard<std::mutex> ll(j.latch->m);
+    if (--j.latch->n == 0) j.latch->cv.notify_all();
+  }
   void run() {
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
@@ -132,12 +158,7 @@ class CopyPool {
       const Job j = jobs_.front();
       jobs_.pop_front();
       lk.unlock();
-      std::memcpy(j.dst, j.src, j.bytes);
-      {
-        // the waiter may destroy the latch as soon as it sees n == 0: touch it only here
-        std::lock_guard<std::mutex> ll(j.latch->m);
-        if (--j.latch->n == 0) j.latch->cv.notify_all();
-      }
+      finish(j);
       lk.lock();
     }
   }
@@ -175,10 +196,16 @@ struct ServerImpl {
   uint64_t launched_rows = 0;
   int64_t first_arrival = 0, last_done = 0;
   std::vector<double> lat_us;
+  struct PerModel {              // the same statistics for one model's requests and launches
+    uint64_t n_sub = 0, n_adm = 0, n_done = 0, n_rej = 0, rows_done = 0, launches = 0, launched_rows = 0;
+    int64_t first_arrival = 0, last_done = 0;
+    std::vector<double> lat_us;
+  };
+  std::vector<PerModel> per_model;
   // per model: statistics (mean[D], M2[D], n) of masks_agg of its last launches, oldest first
   std::vector<std::deque<std::vector<double>>> mask_windows;
 
-  CopyPool copies{3};
+  CopyPool copies{6};
   std::thread sched_thr, comp_thr;
 
   uint64_t req_bytes(int model, int64_t rows) const {
@@ -196,6 +223,7 @@ struct ServerImpl {
         inflight_bytes += r->bytes;
         peak_bytes = std::max(peak_bytes, inflight_bytes);
         ++n_adm;
+        ++per_model[r->model].n_adm;
         admitted.push_back(r);
       }
       if (stopping && admitted.empty()) break;
@@ -231,12 +259,16 @@ struct ServerImpl {
       // gather the rows into the slot's input buffer and enqueue the launch
       const int D = models[L.model].cfg.D;
       float* in = exec->input(L.slot);
+      std::vector<CopyPool::Item> gather;
       for (const Segment& sg : L.segs)
-        copies.copy(in + sg.dst_row * D, sg.req->X.get() + sg.src_row * D, (size_t)sg.rows * D * sizeof(float));
+        gather.push_back({in + sg.dst_row * D, sg.req->X.get() + sg.src_row * D, (size_t)sg.rows * D * sizeof(float)});
+      copies.copy_many(gather);
       const bool ok = exec->launch(L.slot, L.model, L.rows);
       lk.lock();
       ++launches;
       launched_rows += L.rows;
+      ++per_model[L.model].launches;
+      per_model[L.model].launched_rows += L.rows;
       if (!ok) {
         for (Segment& sg : L.segs) {
           --sg.req->segs_inflight;
@@ -299,17 +331,19 @@ struct ServerImpl {
         const float* lo = exec->out_logits(L.slot);
         const float* ag = exec->out_agg(L.slot);
         const float* ms = exec->out_steps(L.slot);
+        std::vector<CopyPool::Item> scatter;
         for (size_t k = 0; k < L.segs.size(); ++k) {
           if (skip[k]) continue;
           const Segment& sg = L.segs[k];
           Request& r = *sg.req;
-          copies.copy(r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4);
-          copies.copy(r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4);
+          scatter.push_back({r.logits + sg.src_row * n_out, lo + sg.dst_row * n_out, (size_t)sg.rows * n_out * 4});
+          scatter.push_back({r.magg + sg.src_row * D, ag + sg.dst_row * D, (size_t)sg.rows * D * 4});
           if (r.msteps && ms)
             for (int s = 0; s < S; ++s)
-              copies.copy(r.msteps + ((int64_t)s * r.rows + sg.src_row) * D,
-                          ms + ((int64_t)s * L.rows + sg.dst_row) * D, (size_t)sg.rows * D * 4);
+              scatter.push_back({r.msteps + ((int64_t)s * r.rows + sg.src_row) * D,
+                                 ms + ((int64_t)s * L.rows + sg.dst_row) * D, (size_t)sg.rows * D * 4});
         }
+        copies.copy_many(scatter);
       }
       const int64_t t = now_ns();
       lk.lock();
@@ -333,6 +367,11 @@ struct ServerImpl {
           rows_done += (uint64_t)r.rows;
           lat_us.push_back((double)(t - r.arrival_ns) * 1e-3);
           last_done = std::max(last_done, t);
+          PerModel& pm = per_model[r.model];
+          ++pm.n_done;
+          pm.rows_done += (uint64_t)r.rows;
+          pm.lat_us.push_back((double)(t - r.arrival_ns) * 1e-3);
+          pm.last_done = std::max(pm.last_done, t);
           r.X.reset();
         }
       }
@@ -354,6 +393,7 @@ tabnet_status server_create(std::vector<ModelInfo> models, Executor* exec, const
   s->max_rows = o.max_rows_per_launch;
   s->nslots = o.slots;
   s->mask_windows.resize(s->models.size());
+  s->per_model.resize(s->models.size());
   for (int i = s->nslots - 1; i >= 0; --i) s->free_slots.push_back(i);
   s->sched_thr = std::thread([s] { s->scheduler(); });
   s->comp_thr = std::thread([s] { s->completer(); });
@@ -379,6 +419,7 @@ tabnet_status server_submit(ServerImpl* s, int model, const float* X, int64_t ro
   if (r->bytes > s->budget) {
     std::lock_guard<std::mutex> lk(s->mu);
     ++s->n_rej;
+    ++s->per_model[model].n_rej;
     set_error("tabnet_serve_submit: request larger than the memory budget");
     return TABNET_E_ADMISSION;
   }
@@ -394,6 +435,9 @@ tabnet_status server_submit(ServerImpl* s, int model, const float* X, int64_t ro
   *id = r->id;
   if (s->n_sub == 0 || r->arrival_ns < s->first_arrival) s->first_arrival = r->arrival_ns;
   ++s->n_sub;
+  auto& pm = s->per_model[model];
+  if (pm.n_sub == 0 || r->arrival_ns < pm.first_arrival) pm.first_arrival = r->arrival_ns;
+  ++pm.n_sub;
   s->live[r->id] = r;
   s->pending.push_back(r);
   s->cv_sched.notify_one();
@@ -461,6 +505,47 @@ static double pct(std::vector<double>& v, double p) {
   return v[k];
 }
 
+static void fill_latency(std::vector<double>& lat, tabnet_serve_stats* o) {
+  if (lat.empty()) return;
+  double sum = 0, mx = 0;
+  for (double x : lat) {
+    sum += x;
+    mx = std::max(mx, x);
+  }
+  o->mean_us = sum / (double)lat.size();
+  o->max_us = mx;
+  o->p50_us = pct(lat, 0.50);
+  o->p99_us = pct(lat, 0.99);
+  o->p999_us = pct(lat, 0.999);
+}
+
+tabnet_status server_model_stats(ServerImpl* s, int model, tabnet_serve_stats* o) {
+  if (model < 0 || model >= (int)s->models.size()) {
+    set_error("tabnet_serve_get_model_stats: bad model index");
+    return TABNET_E_INVALID;
+  }
+  std::vector<double> lat;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const ServerImpl::PerModel& pm = s->per_model[model];
+    std::memset(o, 0, sizeof *o);
+    o->submitted = pm.n_sub;
+    o->admitted = pm.n_adm;
+    o->completed = pm.n_done;
+    o->rejected = pm.n_rej;
+    o->rows_completed = pm.rows_done;
+    o->launches = pm.launches;
+    o->mean_rows_per_launch = pm.launches ? (double)pm.launched_rows / (double)pm.launches : 0.0;
+    o->inflight_bytes = s->inflight_bytes;
+    o->peak_inflight_bytes = s->peak_bytes;
+    const double span = (double)(pm.last_done - pm.first_arrival) * 1e-9;
+    o->rows_per_s = (pm.n_done && span > 0) ? (double)pm.rows_done / span : 0.0;
+    lat = pm.lat_us;
+  }
+  fill_latency(lat, o);
+  return TABNET_OK;
+}
+
 tabnet_status server_stats(ServerImpl* s, tabnet_serve_stats* o) {
   std::vector<double> lat;
   {
@@ -480,18 +565,7 @@ tabnet_status server_stats(ServerImpl* s, tabnet_serve_stats* o) {
     o->rows_per_s = (s->n_done && span > 0) ? (double)s->rows_done / span : 0.0;
     lat = s->lat_us;
   }
-  if (!lat.empty()) {
-    double sum = 0, mx = 0;
-    for (double x : lat) {
-      sum += x;
-      mx = std::max(mx, x);
-    }
-    o->mean_us = sum / (double)lat.size();
-    o->max_us = mx;
-    o->p50_us = pct(lat, 0.50);
-    o->p99_us = pct(lat, 0.99);
-    o->p999_us = pct(lat, 0.999);
-  }
+  fill_latency(lat, o);
   return TABNET_OK;
 }
 
@@ -501,6 +575,7 @@ tabnet_status server_reset_stats(ServerImpl* s) {
   s->launched_rows = 0;
   s->first_arrival = s->last_done = 0;
   s->lat_us.clear();
+  for (auto& pm : s->per_model) pm = ServerImpl::PerModel();
   s->peak_bytes = s->inflight_bytes;
   for (auto& w : s->mask_windows) w.clear();
   return TABNET_OK;

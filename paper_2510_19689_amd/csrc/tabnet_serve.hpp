@@ -58,6 +58,7 @@ tabnet_status server_submit(ServerImpl* s, int model, const float* X, int64_t ro
 tabnet_status server_wait(ServerImpl* s, uint64_t id, int64_t timeout_us);
 tabnet_status server_poll(ServerImpl* s, uint64_t id, int* done);
 tabnet_status server_stats(ServerImpl* s, tabnet_serve_stats* o);
+tabnet_status server_model_stats(ServerImpl* s, int model, tabnet_serve_stats* o);
 tabnet_status server_reset_stats(ServerImpl* s);
 tabnet_status server_mask_stats(ServerImpl* s, int model, double* mean, double* var, int64_t* rows);
 tabnet_status server_stop(ServerImpl* s);   // joins the threads, deletes the executor and s

@@ -282,6 +282,11 @@ tabnet_status tabnet_serve_get_stats(tabnet_server* s, tabnet_serve_stats* out) 
   return server_stats(s->impl, out);
 }
 
+tabnet_status tabnet_serve_get_model_stats(tabnet_server* s, int model, tabnet_serve_stats* out) {
+  if (!s || !out) return TABNET_E_INVALID;
+  return server_model_stats(s->impl, model, out);
+}
+
 tabnet_status tabnet_serve_reset_stats(tabnet_server* s) {
   if (!s) return TABNET_E_INVALID;
   return server_reset_stats(s->impl);

@@ -110,6 +110,8 @@ def _open(path: str) -> ctypes.CDLL:
     L.tabnet_serve_poll.restype = i32
     L.tabnet_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.tabnet_serve_get_stats.restype = i32
+    L.tabnet_serve_get_model_stats.argtypes = [vp, i32, ctypes.POINTER(ServeStats)]
+    L.tabnet_serve_get_model_stats.restype = i32
     L.tabnet_serve_reset_stats.argtypes = [vp]
     L.tabnet_serve_reset_stats.restype = i32
     L.tabnet_serve_mask_stats.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
@@ -434,6 +436,12 @@ class Server:
     def stats(self) -> dict:
         st = ServeStats()
         check(self._L.tabnet_serve_get_stats(self._s, ctypes.byref(st)), self._L)
+        return st.as_dict()
+
+    def model_stats(self, model: int) -> dict:
+        """Statistics of one model's requests (tabnet_serve_get_model_stats)."""
+        st = ServeStats()
+        check(self._L.tabnet_serve_get_model_stats(self._s, int(model), ctypes.byref(st)), self._L)
         return st.as_dict()
 
     def reset_stats(self) -> None:

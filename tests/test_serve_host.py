@@ -284,3 +284,28 @@ def test_failed_segment_of_split_request(fail):
         # the first request's launches: at most the two slots' worth before the failure
         # was seen; none of its four 100-row segments after that
         assert st["launches"] <= 3 + 3
+
+
+def test_per_model_statistics():
+    """tabnet_serve_get_model_stats counts each model's requests, rows and launches; the
+    per-model counts add up to the server's."""
+    ca, cb = cfg(D=7, n_out=2), cfg(D=11, n_out=3)
+    rng = np.random.default_rng(13)
+    with tb.Server(fake_configs=[ca, cb], max_rows_per_launch=64) as s:
+        reqs = []
+        for k in range(30):
+            m = k % 3 == 0
+            c = cb if m else ca
+            r = make_req(rng, int(rng.integers(1, 150)), c, steps=False)
+            reqs.append((int(m), r[0].shape[0], s.submit(int(m), *r)))
+        assert all(s.wait(i) == tb.OK for _, _, i in reqs)
+        tot = s.stats()
+        per = [s.model_stats(m) for m in (0, 1)]
+        for m in (0, 1):
+            assert per[m]["completed"] == sum(1 for mm, _, _ in reqs if mm == m)
+            assert per[m]["rows_completed"] == sum(r for mm, r, _ in reqs if mm == m)
+            assert per[m]["p99_us"] > 0 and per[m]["rows_per_s"] > 0
+        for k in ("completed", "rows_completed", "launches", "submitted"):
+            assert per[0][k] + per[1][k] == tot[k]
+        with pytest.raises(tb.TabNetError):
+            s.model_stats(2)
