@@ -626,13 +626,9 @@ __device__ __forceinline__ void mma_tile_coded(const unsigned char* fr, const BO
 }
 
 // ------------------------------------------------------------------------------------
-// Double-buffered weight stream through LDS, shared by the W waves of a workgroup.
-// With TABNET_LDS_DMA the chunk goes straight from global memory into LDS
-// (global_load_lds_dwordx4: lane l of a wave writes base + 16 l); otherwise it is staged
-// through registers and stored with ds_write.
-#ifndef TABNET_LDS_DMA
-#define TABNET_LDS_DMA 1
-#endif
+// Double-buffered weight stream through LDS, shared by the W waves of a workgroup.  The
+// chunk goes straight from global memory into LDS (global_load_lds_dwordx4: lane l of a
+// wave writes base + 16 l).
 template <int W, int BUF>
 struct WeightStream {
   static constexpr int kW = W;
@@ -642,9 +638,6 @@ struct WeightStream {
   const unsigned char* wts;
   const ChunkRec* tab;
   int n, idx, cur, next_bytes;
-#if !TABNET_LDS_DMA
-  f4 stg[NSTG];
-#endif
 
   // Issue the global loads of the chunk after the current one.
   __device__ __forceinline__ void begin() {
@@ -652,7 +645,6 @@ struct WeightStream {
     if (idx + 1 < n) {
       const ChunkRec r = tab[idx + 1];
       next_bytes = r.bytes;
-#if TABNET_LDS_DMA
       const unsigned char* src = wts + r.off;
       unsigned char* dst = lds + (cur ^ 1) * BUF;
       const int wave = (int)threadIdx.x >> 6;
@@ -664,30 +656,11 @@ struct WeightStream {
               (const void __attribute__((address_space(1)))*)(src + (size_t)p * 16),
               (void __attribute__((address_space(3)))*)(dst + (j * T + wave * 64) * 16), 16, 0, 0);
       }
-#else
-      const f4* src = reinterpret_cast<const f4*>(wts + r.off);
-#pragma unroll
-      for (int j = 0; j < NSTG; ++j) {
-        const int p = (int)threadIdx.x + j * T;
-        if (p * 16 < next_bytes) stg[j] = src[p];
-      }
-#endif
     }
   }
   // Complete them, wait for the whole workgroup, switch buffers.
   __device__ __forceinline__ void end() {
-#if TABNET_LDS_DMA
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-#else
-    if (idx + 1 < n) {
-      unsigned char* dst = lds + (cur ^ 1) * BUF;
-#pragma unroll
-      for (int j = 0; j < NSTG; ++j) {
-        const int p = (int)threadIdx.x + j * T;
-        if (p * 16 < next_bytes) *reinterpret_cast<f4*>(dst + p * 16) = stg[j];
-      }
-    }
-#endif
     lds_block_sync();
     cur ^= 1;
     ++idx;
@@ -1667,18 +1640,6 @@ struct KernelEntry {
   Plan plan;                 // plan.wide: split-feature kernel, 16 rows per workgroup
 };
 
-#ifndef TABNET_ADULT_R
-#define TABNET_ADULT_R 1
-#endif
-#ifndef TABNET_ADULT_W
-#define TABNET_ADULT_W 8
-#endif
-#ifndef TABNET_WIDE_W
-#define TABNET_WIDE_W 4
-#endif
-#ifndef TABNET_WIDE_RG
-#define TABNET_WIDE_RG 2
-#endif
 #define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                                 \
   {P, DT, NT, KA0, R, W, false, tabnet_forward_kernel<P, DT, NT, KA0, R, W, false>,                      \
    make_plan(P, DT, NT, KA0, chunk_target(DT, R, W))},                                                   \
@@ -1696,14 +1657,14 @@ struct KernelEntry {
   TABNET_SHAPE(P, 3, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 2, 1, 1, 4)  \
-  TABNET_SHAPE(P, 7, 4, 2, TABNET_ADULT_R, TABNET_ADULT_W)  \
-  TABNET_SHAPE(P, 13, 8, 4, 1, TABNET_WIDE_W)
+  TABNET_SHAPE(P, 7, 4, 2, 1, 8)  \
+  TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
                                        TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
                                        TABNET_SHAPES(7) TABNET_SHAPES(8)
-                                       TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, TABNET_WIDE_RG)
-                                           TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, TABNET_WIDE_RG)};
+                                       TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
+                                           TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)};
 
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
   for (const auto& e : kKernels)

@@ -151,9 +151,7 @@ constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
 }
 
 // Fragment bytes of one K slice of the split-feature kernel, in KiB (plus the shifts).
-#ifndef TABNET_WIDE_SLICE_KIB
-#define TABNET_WIDE_SLICE_KIB 32
-#endif
+constexpr int kWideSliceKib = 32;
 // Split-feature plan: wave w owns feature tiles [w tpw, (w + 1) tpw) of the padded row
 // (tpw even, so that BF16 tile pairs never straddle waves) and output tile pairs
 // [w NT / W, (w + 1) NT / W) of every feature-transformer layer.
@@ -166,7 +164,7 @@ constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   p.wide = 1;
   p.W = W;
   p.tpw = wide_tpw(DT, W);
-  constexpr int kib = TABNET_WIDE_SLICE_KIB;
+  constexpr int kib = kWideSliceKib;
   p.sk = kib / (2 * NT) < 1 ? 1 : kib / (2 * NT);   // k-blocks per slice
   p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64;
   int tpc = p.tpw;

@@ -58,7 +58,7 @@ def test_c_program_links_and_reports_errors(tmp_path):
     assert "status -4" in r.stdout
 
 
-@pytest.mark.parametrize("prog", ["serve_load.c", "serve_rate.c"])
+@pytest.mark.parametrize("prog", ["serve_load.c"])
 def test_native_clients_build(tmp_path, prog):
     """The C clients under tests/native (the serving test's client and the load generator)
     compile as strict C99 and link against the library."""
