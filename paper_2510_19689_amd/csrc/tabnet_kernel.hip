@@ -1310,6 +1310,34 @@ __device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[T
   }
 }
 
+// Store this wave's tiles [wave TPW, (wave + 1) TPW) of a 16-row mask block (each lane's
+// row scaled by `scale`) to row r at dst_row0 + r D, through 2 KiB of LDS per wave: two
+// tiles at a time are laid out as [16 rows][32 floats], and each store instruction then
+// writes eight rows' 128 contiguous bytes, whole 128-byte lines when D % 32 == 0 (the
+// lanes' own 16-byte pieces would leave every line half-written per instruction).
+template <int TPW>
+__device__ __forceinline__ void wide_store_rows(const float (&m)[TPW][4], float scale, float* stg, float* dst_row0,
+                                                int D, int live_rows, int wave, int lane) {
+  const int g = lane >> 4, rl = lane & 15;
+#pragma unroll
+  for (int t0 = 0; t0 < TPW; t0 += 2) {
+    *reinterpret_cast<f4*>(stg + rl * 32 + 4 * g) =
+        f4{m[t0][0] * scale, m[t0][1] * scale, m[t0][2] * scale, m[t0][3] * scale};
+    *reinterpret_cast<f4*>(stg + rl * 32 + 16 + 4 * g) =
+        f4{m[t0 + 1][0] * scale, m[t0 + 1][1] * scale, m[t0 + 1][2] * scale, m[t0 + 1][3] * scale};
+    lds_wave_sync();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int r = 8 * k + (lane >> 3), c = (lane & 7) * 4;
+      const int f = 16 * (wave * TPW + t0) + c;    // padded tiles past D are not stored
+      const f4 v = *reinterpret_cast<const f4*>(stg + r * 32 + c);
+      if (r < live_rows && f < D)
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(dst_row0 + (int64_t)r * D + f));
+    }
+    lds_wave_sync();
+  }
+}
+
 // A workgroup holds RG such groups of W waves (RG blocks of 16 rows) that share every
 // weight chunk, so the weights stream once per 16 RG rows.  Two waves per SIMD: the
 // register budget is 256 per lane in all.
@@ -1323,6 +1351,8 @@ tabnet_wide_kernel(FwdArgs A) {
   constexpr int KD = KA0 + 1 < NT ? KA0 + 1 : NT;   // tiles that can hold decision channels
   constexpr Plan PL = make_wide_plan(PREC, DT, NT, KA0, W);
   constexpr int GROUP_LDS = G::UBYTES + NT * kFrag + W * 16 * 8 * 4;
+  static_assert(NT * kFrag >= W * 2048, "h_s doubles as 2 KiB of mask staging per wave");
+  static_assert(TPW % 2 == 0, "mask staging takes tile pairs");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
@@ -1544,8 +1574,12 @@ tabnet_wide_kernel(FwdArgs A) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) M[t][i] = fmaxf(M[t][i] - tau, 0.f);
     }
-    // ---- step mask out: each lane writes its 4 consecutive features of each tile ----
-    if (A.masks_step != nullptr && live) {
+    // ---- step mask out (h_s is free from the attentive GEMM until this pass's first layer
+    // ends, so it serves as the staging area) ----
+    if (A.masks_step != nullptr && (D & 31) == 0) {
+      wide_store_rows<TPW>(M, 1.f, reinterpret_cast<float*>(h_s) + wave * 512,
+                           A.masks_step + (int64_t)(s - 1) * step_stride + row0 * D, D, live_rows, wave, lane);
+    } else if (A.masks_step != nullptr && live) {
       float* dst = A.masks_step + (int64_t)(s - 1) * step_stride + row * D;
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
@@ -1612,7 +1646,10 @@ tabnet_wide_kernel(FwdArgs A) {
   float den = 0.f;
   for (int w = 0; w < W; ++w) den += ex[w * 16 + rl];
   const float inv = den > 0.f ? 1.0f / den : 0.f;
-  if (live) {
+  if ((D & 31) == 0) {
+    wide_store_rows<TPW>(agg, inv, reinterpret_cast<float*>(h_s) + wave * 512, A.masks_agg + row0 * D, D, live_rows,
+                         wave, lane);
+  } else if (live) {
     float* dst = A.masks_agg + row * D;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
