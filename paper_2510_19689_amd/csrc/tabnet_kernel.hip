@@ -229,9 +229,15 @@ __device__ __forceinline__ int mx_exponent(float amax) {
 // v_permlane32_swap; the order of the 8-element chunks inside a block is the one the host
 // packs the weights with).
 //
-// The per-block maxima of this lane's 8 elements, over the row's 4 lanes.
-template <int KT, class F>
-__device__ __forceinline__ void mx_block_max(F src, int rb, int kb, float (&m)[4]) {
+// Shared exponents of the four blocks of k-block kb.  Each lane takes the maxima of its
+// 8 elements of every block; a reduce-scatter over the row's 4 lanes (one exchange with
+// the lane 32 away, one with the lane 16 away) leaves lane group q the maximum of block q,
+// whose exponent X_q it forms; an all-gather of the biased exponents X_q + 127 (bytes)
+// gives every lane all four.  Returns the four biased exponents in bytes 0..3 and the
+// lane's own (block q = its lane group) in *own.
+template <int KT, int EMAX, class F>
+__device__ __forceinline__ uint32_t mx_block_exponents(F src, int rb, int kb, uint32_t* own) {
+  float m[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     float a0 = 0.f, a1 = 0.f;
@@ -245,13 +251,29 @@ __device__ __forceinline__ void mx_block_max(F src, int rb, int kb, float (&m)[4
           else a0 = fmaxf(a0, fabsf(src(rb, t, i)));
         }
     }
-    m[b] = row_max(fmaxf(a0, a1));
+    m[b] = fmaxf(a0, a1);
   }
+  // lanes 0-31 reduce blocks 0, 1 and lanes 32-63 blocks 2, 3 over the pair 32 apart ...
+  float p[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[k]), __float_as_uint(m[k + 2]), false, false);
+    p[k] = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+  }
+  // ... then even lane groups block 2 j and odd ones block 2 j + 1 over the pair 16 apart
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(p[0]), __float_as_uint(p[1]), false, false);
+  const uint32_t e = (uint32_t)(mx_exponent<EMAX>(fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]))) + 127);
+  *own = e;
+  // all-gather: a pair 16 apart returns blocks (2 j, 2 j + 1) in the order (even, odd)
+  const auto a = __builtin_amdgcn_permlane16_swap(e, e, false, false);
+  const uint32_t w = a[0] | (a[1] << 8);
+  const auto c = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return c[0] | (c[1] << 16);
 }
 
-// The value of lane group g's entry of v[0..3] (the scale lane group g supplies).
-__device__ __forceinline__ uint32_t by_group(const uint32_t (&v)[4], int g) {
-  return g == 0 ? v[0] : (g == 1 ? v[1] : (g == 2 ? v[2] : v[3]));
+// 2^(X_b) from the biased exponent in byte b (an E8M0 scale is an FP32 exponent field).
+__device__ __forceinline__ float mx_scale_of(uint32_t e4, int b) {
+  return __uint_as_float(((e4 >> (8 * b)) & 0xffu) << 23);
 }
 
 // MXFP8 (E4M3 elements, E5M2 when E5M2 is set).  The instruction's lane group q holds
@@ -273,19 +295,16 @@ struct MxF8Op {
   __device__ __forceinline__ void build(F src) {
     constexpr int kEmax = E5M2 ? 15 : 8;
     constexpr float kMax = E5M2 ? 57344.0f : 448.0f;
-    const int g = ((int)threadIdx.x >> 4) & 3;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        float m[4];
-        mx_block_max<KT>(src, rb, kb, m);
-        uint32_t e8[4], w[4][2];
+        uint32_t own;
+        const uint32_t e4 = mx_block_exponents<KT, kEmax>(src, rb, kb, &own);
+        uint32_t w[4][2];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int X = mx_exponent<kEmax>(m[b]);
-          e8[b] = (uint32_t)(X + 127);
-          const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+          const float scale = mx_scale_of(e4, b);
           const float lim = kMax * scale;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
@@ -318,7 +337,7 @@ struct MxF8Op {
             v[rb][kb][4 * p + h] = r[0];
             v[rb][kb][4 * p + 2 + h] = r[1];
           }
-        sc[rb][kb] = by_group(e8, g);
+        sc[rb][kb] = own;
       }
   }
 };
@@ -340,19 +359,16 @@ struct BOp<5, KT, R> {
   uint32_t sc[R][KB];
   template <class F>
   __device__ __forceinline__ void build(F src) {
-    const int g = ((int)threadIdx.x >> 4) & 3;
 #pragma unroll
     for (int rb = 0; rb < R; ++rb)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        float m[4];
-        mx_block_max<KT>(src, rb, kb, m);
-        uint32_t e8[4], w[4];
+        uint32_t own;
+        const uint32_t e4 = mx_block_exponents<KT, 2>(src, rb, kb, &own);
+        uint32_t w[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int X = mx_exponent<2>(m[b]);
-          e8[b] = (uint32_t)(X + 127);
-          const float scale = __builtin_amdgcn_ldexpf(1.0f, X);
+          const float scale = mx_scale_of(e4, b);
           uint32_t q = 0u;
           const int t0 = 8 * kb + 2 * b, t1 = t0 + 1;
           if (t0 < KT) {
@@ -380,7 +396,7 @@ struct BOp<5, KT, R> {
           v[rb][kb][k] = r[0];
           v[rb][kb][k + 1] = r[1];
         }
-        sc[rb][kb] = by_group(e8, g);
+        sc[rb][kb] = own;
       }
   }
 };
