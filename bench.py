@@ -386,7 +386,8 @@ def wide_leg(precs, steps: int, tmpdir: str):
     synth.write_weights(params, path)
     X = torch.from_numpy(Xh).cuda()
     byt, flops = algorithmic(cfg, rows, with_steps=True)
-    peaks = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS, "fp8": FP8_PEAK_TFLOPS}
+    peaks = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS, "fp8": FP8_PEAK_TFLOPS,
+             "fp8w": BF16_PEAK_TFLOPS}
     n = max(3, steps // 5)
     out = {"rows": rows, "D": cfg.D, "n_d": cfg.n_d, "n_a": cfg.n_a, "n_steps": cfg.n_steps,
            "n_shared": cfg.n_shared, "n_indep": cfg.n_indep, "n_out": cfg.n_out, "masks_step": True,
@@ -405,8 +406,9 @@ def wide_leg(precs, steps: int, tmpdir: str):
             del outs
     if "bf16" in out and "fp32" in out:
         out["bf16_over_fp32"] = out["fp32"]["ms_per_forward"] / out["bf16"]["ms_per_forward"]
-    if "bf16" in out and "fp8" in out:
-        out["fp8_over_bf16"] = out["bf16"]["ms_per_forward"] / out["fp8"]["ms_per_forward"]
+    for q in ("fp8", "fp8w"):
+        if "bf16" in out and q in out:
+            out[q + "_over_bf16"] = out["bf16"]["ms_per_forward"] / out[q]["ms_per_forward"]
     del X
     torch.cuda.empty_cache()
     return out
@@ -422,7 +424,7 @@ def main():
     ap.add_argument("--workload", default="adult108")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
-    ap.add_argument("--quant", default="fp8,int8,mxfp8,mxfp8_e5m2,mxfp6,mxfp6_e3m2,mxfp4",
+    ap.add_argument("--quant", default="fp8,fp8w,int8,mxfp8,mxfp8_e5m2,mxfp6,mxfp6_e3m2,mxfp4",
                     help="reduced-precision paths timed beside BF16 and FP32 (fp8: E4M3 weights and GEMM "
                          "inputs; int8: INT8 weights and GEMM inputs; mxfp8, mxfp8_e5m2, mxfp6, mxfp6_e3m2, "
                          "mxfp4: OCP MX on both GEMM operands); "
@@ -436,7 +438,7 @@ def main():
     ap.add_argument("--serve-mix-step-masks", type=int, default=0,
                     help="mixed-load requests also return the per-step masks (1; up to 168 MB per "
                          "8,192-row request of the 512-feature model) or not (0)")
-    ap.add_argument("--wide", default="fp32,bf16,fp8",
+    ap.add_argument("--wide", default="fp32,bf16,fp8,fp8w",
                     help="precisions of the 200-feature leg (1,048,576 rows, 7 steps); empty to skip")
     ap.add_argument("--serve-mix-rates", default="2000,5000,10000",
                     help="request rates of a mixed load over four resident models (HR-, Adult-, "
@@ -492,8 +494,9 @@ def main():
                 continue
             with m:
                 outs = m.outputs(rows, with_steps=True)
+                ramp = clock_ramp(m, X, outs, CLOCK_RAMP_S if prec == "bf16" else 0.05)
                 if prec == "bf16":
-                    res["ramp"] = clock_ramp(m, X, outs, CLOCK_RAMP_S)
+                    res["ramp"] = ramp
                 t, wall = time_forward(m, X, outs, args.steps, args.warmup)
                 res[prec] = (t, wall)
                 print(f"[bench] {prec}: {t / args.steps * 1e6:.1f} us/forward, "
@@ -589,6 +592,8 @@ def main():
     quant = {}
     for prec, what in (("fp8", "E4M3 weights (one scale per output channel) and GEMM inputs (one scale per "
                                 "row), FP8 MFMA"),
+                       ("fp8w", "E4M3 weights (one scale per output channel), BF16 GEMM inputs, codes widened "
+                                 "to BF16 for the BF16 MFMA"),
                        ("int8", "INT8 weights (one scale per output channel) and GEMM inputs (one step "
                                 "per row), INT32 products"),
                        ("mxfp8", "OCP MXFP8 (E4M3 elements, E8M0 scale per 32) on both GEMM operands, "

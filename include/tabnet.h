@@ -51,7 +51,8 @@ typedef enum {
     TABNET_MXFP4 = 5,     /* OCP MX: E2M1 elements in blocks of 32 with E8M0 scales       */
     TABNET_MXFP6 = 6,     /* OCP MX: E2M3 elements in blocks of 32 with E8M0 scales       */
     TABNET_MXFP8_E5M2 = 7,  /* OCP MX: E5M2 elements in blocks of 32 with E8M0 scales     */
-    TABNET_MXFP6_E3M2 = 8   /* OCP MX: E3M2 elements in blocks of 32 with E8M0 scales     */
+    TABNET_MXFP6_E3M2 = 8,  /* OCP MX: E3M2 elements in blocks of 32 with E8M0 scales     */
+    TABNET_FP8_WEIGHTS = 9  /* E4M3 weights, one scale per output channel; BF16 inputs    */
 } tabnet_precision;
 
 /* Model hyper-parameters as stored in the weight file.  N = n_d + n_a. */
@@ -93,6 +94,13 @@ typedef struct tabnet_handle tabnet_handle;
  * both rounded to nearest even.  The FP8 matrix instruction sums the products in FP32,
  * dequantised by sigma_n * s_r before the folded shift is added; the GLU and residual
  * epilogues, the prior, sparsemax and aggregation stay in FP32.
+ *
+ * TABNET_FP8_WEIGHTS stores the weights as TABNET_FP8_E4M3 does (E4M3 codes, one scale
+ * sigma_n per output channel) and keeps the GEMM inputs in BF16 (round to nearest even):
+ * the codes are widened to BF16 in registers (exactly: every E4M3 value is a BF16 value),
+ * the BF16 matrix instruction sums the products in FP32, and the sum is scaled by sigma_n
+ * before the folded shift is added.  It halves the weight bytes of BF16 and leaves the
+ * activations' precision as in TABNET_BF16.
  *
  * TABNET_INT8 is the paper's FP32-to-INT8 quantisation (Sec. VI-D) in symmetric form:
  * each GEMM weight row is stored as integer codes in [-127, 127] with one FP32 scale

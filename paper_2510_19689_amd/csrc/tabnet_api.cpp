@@ -76,7 +76,7 @@ const char* tabnet_last_error(void) { return g_err.c_str(); }
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out) {
   if (out == nullptr || path == nullptr) return fail(TABNET_E_INVALID, "tabnet_load: NULL argument");
   *out = nullptr;
-  if (precision < TABNET_FP32 || precision > TABNET_MXFP6_E3M2)
+  if (precision < TABNET_FP32 || precision > TABNET_FP8_WEIGHTS)
     return fail(TABNET_E_INVALID, "tabnet_load: unknown precision");
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(TABNET_E_IO, std::string("tabnet_load: cannot open ") + path);
@@ -101,7 +101,7 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   // MX blocks are 32 consecutive channels of each GEMM input, the attention half's from its
   // own first channel.  The kernel forms them from 16-channel tile pairs, which holds when
   // the attention half starts a tile, or lies whole within the tile pair it starts in.
-  if (precision >= TABNET_MXFP8 && m.cfg.n_d % 16 != 0 && m.cfg.n_d % 16 + m.cfg.n_a > 32)
+  if (precision >= TABNET_MXFP8 && precision <= TABNET_MXFP6_E3M2 && m.cfg.n_d % 16 != 0 && m.cfg.n_d % 16 + m.cfg.n_a > 32)
     return fail(TABNET_E_UNSUPPORTED,
                 "tabnet_load: MX formats need n_d % 16 == 0 or n_d % 16 + n_a <= 32 (the attention half's "
                 "32-channel blocks must fall on the kernel's tile pairs)");

@@ -67,7 +67,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   std::string err;
   tabnet_status st = parse_model((const unsigned char*)buf, len, &m, &err);
   if (st != TABNET_OK) return st;
-  if (precision < TABNET_FP32 || precision > TABNET_MXFP6_E3M2) return TABNET_E_INVALID;
+  if (precision < TABNET_FP32 || precision > TABNET_FP8_WEIGHTS) return TABNET_E_INVALID;
   const Shape sh = shape_of(m.cfg);
   const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);
   if (!k) return TABNET_E_UNSUPPORTED;

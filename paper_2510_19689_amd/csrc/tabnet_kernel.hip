@@ -140,6 +140,13 @@ struct BOp<1, KT, R> {        // BF16: two packed dwords per tile
   }
 };
 
+// E4M3 weights with BF16 inputs: the BF16 operand, and a row scale of 1 (the inputs are
+// not scaled).
+template <int KT, int R>
+struct BOp<9, KT, R> : BOp<1, KT, R> {
+  __device__ __forceinline__ float rscale(int) const { return 1.f; }
+};
+
 // E4M3 (the FP8 path): one scale per row, s = max_k |u_k| / 448, elements u_k / s rounded
 // to nearest even in E4M3, four to a dword (feature 16 t + 4 g + i in byte i).  The
 // largest element maps to 448 (|u * 448 / max| <= 448 (1 + 2^-23) rounds to 448), so no
@@ -148,6 +155,7 @@ template <int KT, int R>
 struct BOp<2, KT, R> {
   uint32_t v[R][KT];
   float s[R];
+  __device__ __forceinline__ float rscale(int rb) const { return s[rb]; }
   template <class F>
   __device__ __forceinline__ void build(F src) {
 #pragma unroll
@@ -183,6 +191,7 @@ template <int KT, int R>
 struct BOp<3, KT, R> {
   uint32_t v[R][KT];
   float s[R];                 // the row's step (0 for an all-zero row)
+  __device__ __forceinline__ float rscale(int rb) const { return s[rb]; }
   template <class F>
   __device__ __forceinline__ void build(F src) {
     constexpr float kRound = 12582912.0f;   // 1.5 * 2^23
@@ -523,7 +532,7 @@ __device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<P
 // feature 16 t + 4 g + i.
 template <int PREC, int KT, int R, class F>
 __device__ __forceinline__ void build_b(BOp<PREC, KT, R>& b, F src) {
-  if constexpr (PREC >= 2) {
+  if constexpr (PREC >= 2 && !is_fp8w(PREC)) {
     b.build(src);
   } else {
 #pragma unroll
@@ -563,7 +572,7 @@ __device__ __forceinline__ void mma_tile_i8(const unsigned char* fr, const BOp<3
 template <int PREC, int KT, int R>
 __device__ __forceinline__ void mma_tile(const unsigned char* fr, const BOp<PREC, KT, R>& b,
                                          f4 (&acc)[R], int lane) {
-  if constexpr (PREC >= 4) {
+  if constexpr (is_mx(PREC)) {
     mma_tile_mx<PREC, KT, R>(fr, b, acc, lane);
   } else if constexpr (PREC == 0) {
 #pragma unroll
@@ -622,12 +631,49 @@ __device__ __forceinline__ void mma_tile_f8(const unsigned char* fr, const BOp<2
   }
 }
 
-// Row-coded formats (E4M3, INT8): acc[rb] = Wq(one output tile) * codes[rb] as FP32, before
-// the dequantisation by (channel scale) x (row scale).
+// E4M3 weights, BF16 inputs: acc[rb] += Wq(one output tile, all K) * B[rb] in FP32.  A
+// 1 KiB fragment holds four K tiles of codes (byte j of a lane: tile 4 kb + j / 4, feature
+// 4 q + j % 4); each half (two tiles) is widened to eight BF16 values, exactly, and feeds
+// one 16x16x32 BF16 MFMA with the matching tile pair of the BF16 operand.
+template <int KT, int R>
+__device__ __forceinline__ void mma_tile_w8(const unsigned char* fr, const BOp<9, KT, R>& b, f4 (&acc)[R],
+                                            int lane) {
+  constexpr int KQ = kblocks(9, KT);
+#pragma unroll
+  for (int kb = 0; kb < KQ; ++kb) {
+    const i4 a = *reinterpret_cast<const i4*>(fr + kb * kFrag + lane * 16);
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      const int t0 = 4 * kb + 2 * hf, t1 = t0 + 1;
+      if (t0 < KT) {
+        uint32_t w[4];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          w[2 * d] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(a[2 * hf + d], 1.0f, false));
+          w[2 * d + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(a[2 * hf + d], 1.0f, true));
+        }
+        const s8 aw = __builtin_bit_cast(s8, w);
+#pragma unroll
+        for (int rb = 0; rb < R; ++rb) {
+          uint32_t q[4] = {b.v[rb][t0][0], b.v[rb][t0][1], t1 < KT ? b.v[rb][t1 < KT ? t1 : 0][0] : 0u,
+                           t1 < KT ? b.v[rb][t1 < KT ? t1 : 0][1] : 0u};
+          acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, __builtin_bit_cast(s8, q), acc[rb], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+// Formats with channel scales (E4M3, INT8, E4M3 weights): acc[rb] = Wq(one output tile) *
+// input[rb] as FP32, before the dequantisation by (channel scale) x (row scale).
 template <int PREC, int KT, int R>
 __device__ __forceinline__ void mma_tile_coded(const unsigned char* fr, const BOp<PREC, KT, R>& b, f4 (&acc)[R],
                                                int lane) {
-  if constexpr (PREC == 3) {
+  if constexpr (is_fp8w(PREC)) {
+#pragma unroll
+    for (int rb = 0; rb < R; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+    mma_tile_w8<KT, R>(fr, b, acc, lane);
+  } else if constexpr (PREC == 3) {
     i4 q[R];
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) q[rb] = i4{0, 0, 0, 0};
@@ -705,7 +751,7 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
         const unsigned char* unit = buf + u * UNIT;
         const f4 bv = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 16 * g);
         const f4 bg = *reinterpret_cast<const f4*>(unit + 2 * KB * kbytes(PREC) + 64 + 16 * g);
-        if constexpr (PREC == 2 || PREC == 3) {
+        if constexpr (has_channel_scales(PREC)) {
           // products of codes, dequantised by (channel scale) x (row scale); the gate's shift
           // and scale carry the factor -log2(e) of the sigmoid's exponent
           f4 qv[R], qg[R];
@@ -717,8 +763,8 @@ __device__ __forceinline__ void glu_layer(WS& ws, const BOp<PREC, KT, R>& b,
           for (int rb = 0; rb < R; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float v = __builtin_fmaf(qv[rb][i], sv[i] * b.s[rb], bv[i]);
-              const float e = __builtin_fmaf(qg[rb][i], sgt[i] * b.s[rb], bg[i]);
+              const float v = __builtin_fmaf(qv[rb][i], sv[i] * b.rscale(rb), bv[i]);
+              const float e = __builtin_fmaf(qg[rb][i], sgt[i] * b.rscale(rb), bg[i]);
               const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(e));
               h[rb][mt][i] = first ? v * sg : __builtin_fmaf(v, sg, h[rb][mt][i]) * kSqrtHalf;
             }
@@ -954,7 +1000,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       const int n_att_end = n_d + A.n_a;
       build_b(ba, [&](int rb, int t, int i) {
         const int ch = 16 * (KA0 + t) + 4 * g + i;
-        return PREC < 2 || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
+        return !row_coded(PREC) && !is_mx(PREC) || (ch >= n_d && ch < n_att_end) ? h[rb][KA0 + t][i] : 0.f;
       });
       constexpr int KBA = kblocks(PREC, KTA);
 #pragma unroll
@@ -967,7 +1013,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           if (mt < DT) {
             const unsigned char* unit = buf + u * PL.att.unit;
             const f4 bv = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 16 * g);
-            if constexpr (PREC == 2 || PREC == 3) {
+            if constexpr (has_channel_scales(PREC)) {
               f4 qa[R];
               mma_tile_coded<PREC, KTA, R>(unit, ba, qa, lane);
               const f4 scl = *reinterpret_cast<const f4*>(unit + KBA * kbytes(PREC) + 64 + 16 * g);
@@ -975,7 +1021,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
               for (int rb = 0; rb < R; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  const float hz = __builtin_fmaf(qa[rb][i], scl[i] * ba.s[rb], bv[i]);
+                  const float hz = __builtin_fmaf(qa[rb][i], scl[i] * ba.rscale(rb), bv[i]);
                   M[rb][mt][i] = feat_ok(mt, i) ? P[rb][mt][i] * hz : kNegBig;
                 }
             } else {
@@ -1715,7 +1761,7 @@ struct KernelEntry {
 
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
                                        TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
-                                       TABNET_SHAPES(7) TABNET_SHAPES(8)
+                                       TABNET_SHAPES(7) TABNET_SHAPES(8) TABNET_SHAPES(9)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)};
 

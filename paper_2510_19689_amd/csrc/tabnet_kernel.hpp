@@ -35,14 +35,17 @@
 // Packed layout of one GEMM (each starts 256-byte aligned), as a sequence of units:
 //   GLU layer, unit mt = 0..NT-1:  [value-tile fragments][gate-tile fragments]
 //                                  [16 value shifts][16 gate shifts]
-//                                  (E4M3, INT8: then [16 value scales][16 gate scales])
-//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (E4M3, INT8: then [16 scales])
+//                                  (E4M3, INT8, E4M3 weights: then [16 value scales]
+//                                  [16 gate scales])
+//   attentive, unit mt = 0..DT-1:  [fragments][16 shifts] (with channel scales: then
+//                                  [16 scales])
 // A fragment is 64 lanes x 16 bytes: FP32 one per 16-wide K tile (a lane's float4 feeds
 // four 16x16x4 MFMAs), BF16 one per pair of K tiles (8 bf16 per lane, one 16x16x32 MFMA;
 // an odd last tile is paired with zeros), E4M3 and INT8 one per four K tiles (16 codes per
-// lane: two 16x16x32 FP8 MFMAs, or one 16x16x64 integer MFMA; missing tiles are zeros).
+// lane: two 16x16x32 FP8 MFMAs, one 16x16x64 integer MFMA, or for E4M3 weights with BF16
+// inputs two 16x16x32 BF16 MFMAs on codes widened to BF16; missing tiles are zeros).
 // Shifts are in C-layout order: slot 4 q + i of tile mt is output feature 16 mt + 4 q + i.
-// In E4M3 and INT8 the gate half's shifts and scales are stored multiplied by -log2(e),
+// With channel scales the gate half's shifts and scales are stored multiplied by -log2(e),
 // the factor of the sigmoid's exponent, and the shifts are not divided by the scales (the
 // products of codes are dequantised before the shift is added).
 // MX formats (OCP microscaling: blocks of 32 consecutive K positions share a power-of-two
@@ -87,8 +90,12 @@ struct GemmPlan {
 // MX precisions by element width: 8-bit (E4M3, E5M2) and 6-bit (E2M3, E3M2) elements
 constexpr bool is_mx8(int prec) { return prec == 4 || prec == 7; }
 constexpr bool is_mx6(int prec) { return prec == 6 || prec == 8; }
-// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8), 8 (every MX format)
-constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 1 ? 2 : (prec <= 3 ? 4 : 8)); }
+// MX precisions (scaled matrix instruction)
+constexpr bool is_mx(int prec) { return prec >= 4 && prec <= 8; }
+// E4M3 weights with BF16 GEMM inputs (the codes are widened to BF16 for the BF16 MFMA)
+constexpr bool is_fp8w(int prec) { return prec == 9; }
+// K tiles per k-block: 1 (FP32), 2 (BF16), 4 (E4M3, INT8, E4M3 weights), 8 (every MX format)
+constexpr int ktiles_per_block(int prec) { return prec == 0 ? 1 : (prec == 1 ? 2 : (is_mx(prec) ? 8 : 4)); }
 constexpr int kblocks(int prec, int KT) {
   return (KT + ktiles_per_block(prec) - 1) / ktiles_per_block(prec);
 }
@@ -98,8 +105,10 @@ constexpr int kbytes(int prec) {
   return is_mx8(prec) ? 2 * kFrag + kMxScaleBytes
                       : (prec == 5 ? kFrag + kMxScaleBytes : (is_mx6(prec) ? kFrag + kFrag / 2 + kMxScaleBytes : kFrag));
 }
-// Per-output scales after the shifts (E4M3, INT8)
-constexpr bool has_channel_scales(int prec) { return prec == 2 || prec == 3; }
+// Per-output scales after the shifts (E4M3, INT8, E4M3 weights)
+constexpr bool has_channel_scales(int prec) { return prec == 2 || prec == 3 || prec == 9; }
+// GEMM inputs coded per row in the kernel (E4M3, INT8)
+constexpr bool row_coded(int prec) { return prec == 2 || prec == 3; }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Units per chunk: balanced chunks of at most `target` bytes (one unit if a single unit
@@ -139,7 +148,8 @@ constexpr int imax(int a, int b) { return a > b ? a : b; }
 // prec: 0 FP32, 1 BF16, 2 E4M3 and 3 INT8 weights and activations (codes in the fragments,
 // one FP32 scale per output channel after the shifts, one scale per input row formed in
 // the kernel), 4 MXFP8, 5 MXFP4, 6 MXFP6, 7 MXFP8 with E5M2 elements and 8 MXFP6 with E3M2
-// elements (weights and activations in OCP MX blocks).  DT = ceil(D/16), NT = ceil(N/16),
+// elements (weights and activations in OCP MX blocks), 9 E4M3 weights (one scale per
+// output channel) with BF16 GEMM inputs.  DT = ceil(D/16), NT = ceil(N/16),
 // KA0 = floor(n_d/16).
 constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   const int sc = has_channel_scales(prec) ? 2 : 1;   // shifts, or shifts + scales

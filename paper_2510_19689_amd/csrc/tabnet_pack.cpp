@@ -442,7 +442,7 @@ void emit_fragments(const std::vector<double>& Wf, int cols, int KT, int precisi
         emit(wts, &sc, sizeof sc);
       }
     }
-  } else if (precision == TABNET_FP8_E4M3) {
+  } else if (precision == TABNET_FP8_E4M3 || precision == TABNET_FP8_WEIGHTS) {
     // Wf holds E4M3 values of W' / s_n; byte j of a lane is tile 4 kb + j / 4
     const int KQ = (KT + 3) / 4;   // missing tiles of the last block are zeros
     for (int kb = kb_lo; kb < (kb_hi < 0 ? KQ : kb_hi); ++kb)
@@ -590,7 +590,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
   const tabnet_config& c = m.cfg;
   const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
-  const bool fp8 = precision == TABNET_FP8_E4M3;
+  const bool fp8 = precision == TABNET_FP8_E4M3 || precision == TABNET_FP8_WEIGHTS;
   const bool i8 = precision == TABNET_INT8;
   *out = Packed();
   // input BN as a per-column affine map

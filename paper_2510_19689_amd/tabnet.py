@@ -17,9 +17,9 @@ TEST_LIB_PATH = os.path.join(HERE, "libtabnet_test.so")
 
 OK, E_INVALID, E_OOM, E_HIP, E_IO, E_ADMISSION, E_TIMEOUT, E_STOPPED, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
-FP32, BF16, FP8_E4M3, INT8, MXFP8, MXFP4, MXFP6, MXFP8_E5M2, MXFP6_E3M2 = 0, 1, 2, 3, 4, 5, 6, 7, 8
+FP32, BF16, FP8_E4M3, INT8, MXFP8, MXFP4, MXFP6, MXFP8_E5M2, MXFP6_E3M2, FP8_WEIGHTS = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "int8": INT8, "mxfp8": MXFP8, "mxfp4": MXFP4,
-              "mxfp6": MXFP6, "mxfp8_e5m2": MXFP8_E5M2, "mxfp6_e3m2": MXFP6_E3M2}
+              "mxfp6": MXFP6, "mxfp8_e5m2": MXFP8_E5M2, "mxfp6_e3m2": MXFP6_E3M2, "fp8w": FP8_WEIGHTS}
 
 
 class TabNetError(RuntimeError):

@@ -58,7 +58,7 @@ def test_missing_and_bad_files(tmp_path, L):
     trunc = tmp_path / "trunc.tnw"
     trunc.write_bytes(raw[:-8])
     assert L.tabnet_load(str(trunc).encode(), 0, 0, ctypes.byref(h)) == tb.E_IO
-    assert L.tabnet_load(str(trunc).encode(), 9, 0, ctypes.byref(h)) == tb.E_INVALID
+    assert L.tabnet_load(str(trunc).encode(), 10, 0, ctypes.byref(h)) == tb.E_INVALID
     assert L.tabnet_load(str(trunc).encode(), -1, 0, ctypes.byref(h)) == tb.E_INVALID
     assert L.tabnet_load(None, 0, 0, ctypes.byref(h)) == tb.E_INVALID
 

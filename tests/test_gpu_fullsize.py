@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 MX_FORMATS = ["mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2", "mxfp4"]
 # oracle rounding of each precision's GEMM operands (weights, acts)
-ROUNDING = {"bf16": ("bf16", "bf16"), "fp8": ("e4m3", "e4m3"), "int8": ("int8", "int8"),
+ROUNDING = {"bf16": ("bf16", "bf16"), "fp8": ("e4m3", "e4m3"), "fp8w": ("e4m3", "bf16"), "int8": ("int8", "int8"),
             **{f: (f, f) for f in MX_FORMATS}}
 
 
@@ -95,7 +95,7 @@ def report(name, e):
 def test_adult108_every_row_every_precision(tmp_path):
     params, X = synth.workload("adult108")
     assert X.shape == (65536, 108)
-    precs = ["fp32", "bf16", "fp8", "int8"] + MX_FORMATS
+    precs = ["fp32", "bf16", "fp8", "fp8w", "int8"] + MX_FORMATS
     outs = launch_all(params, X, precs, tmp_path)
     invariants(outs, "adult108")
     checks = ([(p, p, None, None) for p in precs] + [(p + "@op", p, *ROUNDING[p]) for p in precs if p != "fp32"]
@@ -108,9 +108,11 @@ def test_adult108_every_row_every_precision(tmp_path):
 
 
 def test_wide200_every_row_fp32_bf16_fp8(tmp_path):
+    """The 200-feature model at its full batch in FP32, BF16 and both FP8 readings (E4M3 on
+    both GEMM operands with row scales; E4M3 weights with BF16 inputs)."""
     params, X = synth.workload("wide200")
     assert X.shape == (1048576, 200)
-    precs = ["fp32", "bf16", "fp8"]
+    precs = ["fp32", "bf16", "fp8", "fp8w"]
     outs = launch_all(params, X, precs, tmp_path)
     invariants(outs, "wide200")
     checks = [(p, p, None, None) for p in precs]
@@ -119,7 +121,7 @@ def test_wide200_every_row_fp32_bf16_fp8(tmp_path):
     all_errs = dict(errs)
     # the operand-rounded references on the first 65,536 rows
     n = 65536
-    sub = {p: tuple(t[:n] if t.dim() < 3 else t[:, :n] for t in outs[p]) for p in ("bf16", "fp8")}
+    sub = {p: tuple(t[:n] if t.dim() < 3 else t[:, :n] for t in outs[p]) for p in ("bf16", "fp8", "fp8w")}
     checks = ([(p + "@op", p, *ROUNDING[p]) for p in sub]
               + [(p + "@format", fullsize.OracleRounded(*ROUNDING[p]), None, None) for p in sub])
     errs = fullsize.all_rows(params, X[:n], fetcher(sub), checks, chunk=4096, say=_say)
@@ -142,6 +144,7 @@ def test_wide200_every_row_fp32_bf16_fp8(tmp_path):
 FP64_GATES = {
     "bf16": {"logit_abs": 2e-2, "agg_l1": 1e-2, "step_l1": 2.5e-2, "argmax": 0.999},
     "fp8": {"logit_abs": 2e-2, "agg_l1": 0.1, "step_l1": 0.4, "argmax": 0.999},
+    "fp8w": {"logit_abs": 2e-2, "agg_l1": 0.1, "step_l1": 0.4, "argmax": 0.999},
     "int8": {"logit_abs": 2e-2, "agg_l1": 0.06, "step_l1": 0.3, "argmax": 0.999},
     "mxfp8": {"logit_abs": 2e-2, "agg_l1": 0.1, "step_l1": 0.5, "argmax": 0.999},
     "mxfp8_e5m2": {"logit_abs": 5e-2, "agg_l1": 0.2, "step_l1": 0.85, "argmax": 0.999},

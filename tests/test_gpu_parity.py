@@ -145,7 +145,20 @@ def test_bf16_parity(tmp_path, name, B):
     assert e["agg_l1"] <= 1e-2 and e["step_l1"] <= 2e-2, e
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "int8"] + MX_FORMATS)
+@pytest.mark.parametrize("name,B", [("hr35", 256), ("adult108", 3000), ("wide200", 400)])
+def test_fp8_weights_parity(tmp_path, name, B):
+    """E4M3 weights (one scale per output channel) with BF16 GEMM inputs: against FP64 on
+    the same operands (E4M3 weights, bf16-rounded inputs) with the BF16 kernel gates, and
+    against plain FP64 with the logit and argmax gates of the target."""
+    params, X = synth.workload(name, rows=B)
+    _say(f"case fp8 weights {name} B={B}")
+    with load(params, tmp_path, "fp8w") as m:
+        got = run(m, X)
+    e = check_reduced(got, params, X, "e4m3", "bf16", f"fp8w {name}", tol=(2e-3, 1.5e-2, 2e-2))
+    assert e["logit_abs"] <= 2e-2 and e["argmax"] >= 0.999, e
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp8w", "int8"] + MX_FORMATS)
 def test_optional_step_masks_and_empty_batch(tmp_path, prec):
     params, X = synth.workload("adult108", rows=777)
     _say(f"case masks_step NULL {prec}")
@@ -159,7 +172,7 @@ def test_optional_step_masks_and_empty_batch(tmp_path, prec):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "int8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "int8"])
 def test_rows_independent_and_deterministic(tmp_path, prec):
     """A row's outputs are bit-identical whatever batch it is in and on every run."""
     params, X = synth.workload("adult108", rows=1000)
@@ -176,7 +189,7 @@ def test_rows_independent_and_deterministic(tmp_path, prec):
             np.testing.assert_array_equal(part[2], full[2][:, lo_:hi_])
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8", "int8"] + MX_FORMATS)
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp8w", "int8"] + MX_FORMATS)
 def test_nonfinite_row_is_contained(tmp_path, prec):
     """A NaN or Inf in a row changes nothing in the other rows; in the scaled formats the
     row (or block) scale is taken from that row alone."""
