@@ -573,7 +573,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
-        "data": "synthetic (seeded Adult-shaped rows and Xavier-uniform weights; no dataset)",
+        "data": "synthetic (seeded " + {"hr": "HR-shaped", "adult": "Adult-shaped", "wide": "200-feature",
+                                        "wide512": "512-feature N(0,1)"}[w["data"]]
+                + " rows and Xavier-uniform weights; no dataset)",
         "config": {"workload": name, "rows": rows, "D": cfg.D, "n_d": cfg.n_d, "n_a": cfg.n_a,
                    "n_steps": cfg.n_steps, "n_shared": cfg.n_shared, "n_indep": cfg.n_indep,
                    "n_out": cfg.n_out, "gamma": cfg.gamma, "masks_step": True,

@@ -635,6 +635,14 @@ __device__ __forceinline__ void mma_tile_f8(const unsigned char* fr, const BOp<2
 // 1 KiB fragment holds four K tiles of codes (byte j of a lane: tile 4 kb + j / 4, feature
 // 4 q + j % 4); each half (two tiles) is widened to eight BF16 values, exactly, and feeds
 // one 16x16x32 BF16 MFMA with the matching tile pair of the BF16 operand.
+__device__ __forceinline__ s8 widen_e4m3x8(uint32_t lo, uint32_t hi) {
+  uint32_t w[4] = {__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false)),
+                   __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true)),
+                   __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false)),
+                   __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true))};
+  return __builtin_bit_cast(s8, w);
+}
+
 template <int KT, int R>
 __device__ __forceinline__ void mma_tile_w8(const unsigned char* fr, const BOp<9, KT, R>& b, f4 (&acc)[R],
                                             int lane) {
@@ -646,13 +654,7 @@ __device__ __forceinline__ void mma_tile_w8(const unsigned char* fr, const BOp<9
     for (int hf = 0; hf < 2; ++hf) {
       const int t0 = 4 * kb + 2 * hf, t1 = t0 + 1;
       if (t0 < KT) {
-        uint32_t w[4];
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-          w[2 * d] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(a[2 * hf + d], 1.0f, false));
-          w[2 * d + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(a[2 * hf + d], 1.0f, true));
-        }
-        const s8 aw = __builtin_bit_cast(s8, w);
+        const s8 aw = widen_e4m3x8(a[2 * hf], a[2 * hf + 1]);
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) {
           uint32_t q[4] = {b.v[rb][t0][0], b.v[rb][t0][1], t1 < KT ? b.v[rb][t1 < KT ? t1 : 0][0] : 0u,
@@ -1304,14 +1306,29 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
     const unsigned char* buf = ws.ptr();
     for (int q = 0; q < nkb; ++q) {
       f4 bf = {0.f, 0.f, 0.f, 0.f};
-      s8 bb = {};
-      load_kblock<PREC, SRC_F32>(src, kb0 + q, KT, lane, bf, bb);
+      s8 bb = {}, bb2 = {};
+      if constexpr (is_fp8w(PREC)) {
+        // an E4M3 k-block spans two BF16 k-blocks of the input (one past the input's
+        // last reads as zero)
+        const int k2 = 2 * (kb0 + q);
+        load_kblock<1, SRC_F32>(src, k2, KT, lane, bf, bb);
+        if (k2 + 1 < kblocks(1, KT)) load_kblock<1, SRC_F32>(src, k2 + 1, KT, lane, bf, bb2);
+      } else {
+        load_kblock<PREC, SRC_F32>(src, kb0 + q, KT, lane, bf, bb);
+      }
 #pragma unroll
       for (int p = 0; p < OPW; ++p) {
         const int pr = wave * OPW + p;
         const unsigned char* fv = buf + ((size_t)(pr * 2 + 0) * nkb + q) * kFrag + lane * 16;
         const unsigned char* fg = buf + ((size_t)(pr * 2 + 1) * nkb + q) * kFrag + lane * 16;
-        if constexpr (PREC == 0) {
+        if constexpr (is_fp8w(PREC)) {
+          const i4 a = *reinterpret_cast<const i4*>(fv);
+          const i4 c = *reinterpret_cast<const i4*>(fg);
+          av[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(a[0], a[1]), bb, av[p], 0, 0, 0);
+          ag[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(c[0], c[1]), bb, ag[p], 0, 0, 0);
+          av[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(a[2], a[3]), bb2, av[p], 0, 0, 0);
+          ag[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(c[2], c[3]), bb2, ag[p], 0, 0, 0);
+        } else if constexpr (PREC == 0) {
           const f4 a = *reinterpret_cast<const f4*>(fv);
           const f4 c = *reinterpret_cast<const f4*>(fg);
 #pragma unroll
@@ -1333,11 +1350,23 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
         const int pr = wave * OPW + p;
         const f4 sv = *reinterpret_cast<const f4*>(sft + pr * 32 + 4 * g);
         const f4 sg = *reinterpret_cast<const f4*>(sft + pr * 32 + 16 + 4 * g);
+        if constexpr (is_fp8w(PREC)) {
+          // channel scales after all shifts; the gate's scale and shift carry -log2(e)
+          const f4 cv = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 4 * g);
+          const f4 cg = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 16 + 4 * g);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float v = av[p][i] + sv[i];
-          const float sgm = sigmoid_fast(ag[p][i] + sg[i]);
-          h[p][i] = first ? v * sgm : __builtin_fmaf(v, sgm, h[p][i]) * kSqrtHalf;
+          for (int i = 0; i < 4; ++i) {
+            const float v = __builtin_fmaf(av[p][i], cv[i], sv[i]);
+            const float sgm = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(__builtin_fmaf(ag[p][i], cg[i], sg[i])));
+            h[p][i] = first ? v * sgm : __builtin_fmaf(v, sgm, h[p][i]) * kSqrtHalf;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float v = av[p][i] + sv[i];
+            const float sgm = sigmoid_fast(ag[p][i] + sg[i]);
+            h[p][i] = first ? v * sgm : __builtin_fmaf(v, sgm, h[p][i]) * kSqrtHalf;
+          }
         }
       }
     }
@@ -1494,14 +1523,15 @@ tabnet_wide_kernel(FwdArgs A) {
   for (int s = 1; s <= A.n_steps; ++s) {
     // ---- attentive transformer on this wave's feature tiles ----
     {
+      constexpr int KB2 = kblocks(1, KTA);            // BF16 k-blocks of the input
       f4 bf[PREC == 0 ? KTA : 1];
-      s8 bb[PREC == 0 ? 1 : KBA];
+      s8 bb[PREC == 0 ? 1 : KB2];
       if constexpr (PREC == 0) {
 #pragma unroll
         for (int t = 0; t < KTA; ++t) bf[t] = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + t) * 64 + lane) * 16);
       } else {
 #pragma unroll
-        for (int kb = 0; kb < KBA; ++kb) {
+        for (int kb = 0; kb < KB2; ++kb) {
           const f4 a = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + 2 * kb) * 64 + lane) * 16);
           f4 c = {0.f, 0.f, 0.f, 0.f};
           if (2 * kb + 1 < KTA) c = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + 2 * kb + 1) * 64 + lane) * 16);
@@ -1520,7 +1550,19 @@ tabnet_wide_kernel(FwdArgs A) {
           const int t = j * PL.tpc + q;      // compile-time after unrolling
           const unsigned char* unit = buf + (size_t)(wave * PL.tpc + q) * PL.att_unit;
           f4 z = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
-          if constexpr (PREC == 0) {
+          if constexpr (is_fp8w(PREC)) {
+            f4 a8 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KBA; ++kb) {
+              const i4 a = *reinterpret_cast<const i4*>(unit + kb * kFrag + lane * 16);
+              a8 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(a[0], a[1]), bb[2 * kb], a8, 0, 0, 0);
+              if (2 * kb + 1 < KB2)
+                a8 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(a[2], a[3]), bb[2 * kb + 1], a8, 0, 0, 0);
+            }
+            const f4 cs = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[i] = __builtin_fmaf(a8[i], cs[i], z[i]);
+          } else if constexpr (PREC == 0) {
 #pragma unroll
             for (int kt = 0; kt < KTA; ++kt) {
               const f4 a = *reinterpret_cast<const f4*>(unit + kt * kFrag + lane * 16);
@@ -1763,7 +1805,8 @@ static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_
                                        TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
                                        TABNET_SHAPES(7) TABNET_SHAPES(8) TABNET_SHAPES(9)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
-                                           TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)};
+                                           TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)
+                                               TABNET_WIDE_SHAPE(9, 32, 8, 4, 4, 2)};
 
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
   for (const auto& e : kKernels)

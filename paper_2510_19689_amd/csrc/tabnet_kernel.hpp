@@ -137,8 +137,9 @@ struct Plan {
   // over the W waves of a workgroup.  A feature-transformer layer streams K slices of sk
   // k-blocks; a slice chunk holds, for every output tile pair, [value fragments][gate
   // fragments] of those k-blocks, and the layer's last slice adds the shifts of all pairs
-  // ([pair][16 value | 16 gate] floats).  An attentive chunk holds, for every wave, tpc of
-  // its feature tiles as [fragments][16 shifts] units of att_unit bytes.
+  // ([pair][16 value | 16 gate] floats; with channel scales then the scales the same way).
+  // An attentive chunk holds, for every wave, tpc of its feature tiles as [fragments][16
+  // shifts] (with channel scales: then [16 scales]) units of att_unit bytes.
   int wide = 0;
   int W = 0, tpw = 0, sk = 0, tpc = 0, att_unit = 0;
 };
@@ -167,7 +168,7 @@ constexpr int kWideSliceKib = 32;
 // [w NT / W, (w + 1) NT / W) of every feature-transformer layer.
 constexpr int wide_tpw(int DT, int W) { return (cdiv(DT, W) + 1) / 2 * 2; }
 constexpr int wide_slice_bytes(int prec, int NT, int nkb, bool last) {
-  return NT * 2 * nkb * kFrag + (last ? NT * 128 : 0);
+  return NT * 2 * nkb * kFrag + (last ? NT * 128 * (has_channel_scales(prec) ? 2 : 1) : 0);
 }
 constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   Plan p{};
@@ -176,7 +177,7 @@ constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   p.tpw = wide_tpw(DT, W);
   constexpr int kib = kWideSliceKib;
   p.sk = kib / (2 * NT) < 1 ? 1 : kib / (2 * NT);   // k-blocks per slice
-  p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64;
+  p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64 * (has_channel_scales(prec) ? 2 : 1);
   int tpc = p.tpw;
   while (tpc > 1 && (W * tpc * p.att_unit > kib * 1024 + NT * 128 || p.tpw % tpc != 0)) --tpc;
   p.tpc = tpc;

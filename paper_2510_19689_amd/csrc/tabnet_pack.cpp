@@ -521,10 +521,14 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   const int N = c.n_d + c.n_a;
   std::vector<double> Wf, bf;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
-  const int kbn = precision == TABNET_FP32 ? 1 : 2;   // K tiles per k-block
+  // K tiles per k-block: FP32 one, BF16 two, E4M3 weights four (widened in the kernel)
+  const bool w8 = precision == TABNET_FP8_WEIGHTS;
+  const int kbn = precision == TABNET_FP32 ? 1 : (w8 ? 4 : 2);
+  std::vector<double> sc;
   std::vector<std::vector<ChunkRec>> ft_chunks, att_chunks;
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
+    if (w8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
     const int KT = (L->cols + 15) / 16;
     const int K = L->cols;
     const int KB = (KT + kbn - 1) / kbn;
@@ -546,6 +550,12 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
           emit_vals(bf, nv, 16 * pr, 0.f, &out->wts);
           emit_vals(bf, nv, N + 16 * pr, 0.f, &out->wts);
         }
+      if (kb1 == KB && w8)   // then the channel scales, in the same order
+        for (int pr = 0; pr < sh.NT; ++pr) {
+          const int nv = std::min(16, N - 16 * pr);
+          emit_vals(sc, nv, 16 * pr, 1.f, &out->wts);
+          emit_vals(sc, nv, N + 16 * pr, 1.f, &out->wts);
+        }
       chunks.push_back(ChunkRec{at, (int32_t)((int64_t)out->wts.size() - at), 0});
     }
     ft_chunks.push_back(chunks);
@@ -553,6 +563,7 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   const int KTA = sh.NT - sh.KA0;
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
+    if (w8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
     align();
     out->att_off.push_back((int64_t)out->wts.size());
     std::vector<ChunkRec> chunks;
@@ -567,6 +578,7 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
               [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
               &out->wts);
           emit_vals(bf, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 0.f, &out->wts);
+          if (w8) emit_vals(sc, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 1.f, &out->wts);
         }
       chunks.push_back(ChunkRec{at, (int32_t)((int64_t)out->wts.size() - at), 0});
     }
