@@ -49,8 +49,8 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP toolchain is required to build libtabnet")
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, obj: str, defines=()) -> None:
+    cmd = [hipcc(), *COMMON, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -81,6 +81,19 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(f"built {LIB} and {TEST_LIB}")
     return LIB
+
+
+def build_variant(defines, out: str) -> str:
+    """Link a product library at `out` whose kernel source is compiled with the given
+    preprocessor definitions (the tile sweep's candidate builds); the other sources are
+    compiled as for libtabnet.so."""
+    with tempfile.TemporaryDirectory(prefix="tabnet_variant_") as tmp:
+        objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
+        with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+            list(ex.map(lambda so: _compile(so[0], so[1], defines if so[0] == "tabnet_kernel.hip" else ()),
+                        zip(SOURCES, objs)))
+        _link(objs, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -90,7 +90,8 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   tabnet_status st = parse_model(img.data(), img.size(), &m, &err);
   if (st != TABNET_OK) return fail(st, "tabnet_load: " + err);
   const Shape sh = shape_of(m.cfg);
-  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);   // kernel prec = tabnet_precision
+  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false, m.cfg.D, m.cfg.n_out,
+                                     m.cfg.n_d);   // kernel prec = tabnet_precision
   if (!k) {
     char msg[256];
     std::snprintf(msg, sizeof msg,
@@ -203,7 +204,8 @@ tabnet_status tabnet_set_embeddings(tabnet_handle* h, int32_t n_cols, const int3
           if (f < D && meta[4 * (size_t)f] == 16 * ct + l % 16) colbits[(size_t)ct * 64 + l] |= 1ull << (4 * t + i);
         }
   if (base > 0 && !tables) return fail(TABNET_E_INVALID, "tabnet_set_embeddings: NULL tables");
-  const KernelEntry* k = find_kernel(h->precision, h->shape.DT, h->shape.NT, h->shape.KA0, true);
+  const KernelEntry* k = find_kernel(h->precision, h->shape.DT, h->shape.NT, h->shape.KA0, true, D, h->cfg.n_out,
+                                     h->cfg.n_d, h->kernel);
   if (!k) return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: no compiled raw-row kernel for this shape");
   if (kernel_lds_bytes(k, D, h->cfg.n_out, h->cfg.n_d, n_cols, 0) > (size_t)kMaxLdsBytes)
     return fail(TABNET_E_UNSUPPORTED, "tabnet_set_embeddings: the raw-row kernel needs more LDS than a workgroup has");

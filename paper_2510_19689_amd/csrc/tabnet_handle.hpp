@@ -10,7 +10,8 @@
 
 namespace tabnet {
 struct KernelEntry;
-const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw);
+const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int D, int n_out, int n_d,
+                               const KernelEntry* twin = nullptr);
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
 hipError_t prepare_kernel(const KernelEntry* k);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);

@@ -69,7 +69,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   if (st != TABNET_OK) return st;
   if (precision < TABNET_FP32 || precision > TABNET_FP8_WEIGHTS) return TABNET_E_INVALID;
   const Shape sh = shape_of(m.cfg);
-  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false);
+  const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false, m.cfg.D, m.cfg.n_out, m.cfg.n_d);
   if (!k) return TABNET_E_UNSUPPORTED;
   Packed pk;
   pack_model(m, precision, *kernel_plan(k), &pk);

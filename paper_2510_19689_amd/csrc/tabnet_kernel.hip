@@ -1798,20 +1798,61 @@ struct KernelEntry {
   TABNET_SHAPE(P, 3, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 1, 0, 1, 4)  \
   TABNET_SHAPE(P, 4, 2, 1, 1, 4)  \
-  TABNET_SHAPE(P, 7, 4, 2, 1, 8)  \
-  TABNET_SHAPE(P, 13, 8, 4, 1, 4)
+  TABNET_SHAPE(P, 7, 4, 2, 1, 8)
+// The 200-feature shape: eight waves per workgroup (two per SIMD, the register state
+// partly spilled) beat four (one per SIMD, no spill) by 8-16% in FP32, BF16, both FP8
+// forms and MXFP4 (paper_2510_19689_amd/tile_sweep.py), so those take eight, with four
+// as the fallback for models whose final map leaves too little LDS (many outputs) or
+// whose raw rows do not fit beside eight staging areas.  INT8 and the 8- and 6-bit MX
+// forms, which spill far more at two waves per SIMD, take four.
+#define TABNET_SHAPE_200(P) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
+#define TABNET_SHAPE_200_W8(P) TABNET_SHAPE(P, 13, 8, 4, 1, 8) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
-static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPES(1) TABNET_SHAPES(2) TABNET_SHAPES(3)
-                                       TABNET_SHAPES(4) TABNET_SHAPES(5) TABNET_SHAPES(6)
-                                       TABNET_SHAPES(7) TABNET_SHAPES(8) TABNET_SHAPES(9)
+#ifdef TABNET_TILE_SWEEP
+// A tile-sweep build (paper_2510_19689_amd/tile_sweep.py) compiles only the candidate
+// tiling it times, given as one TABNET_SHAPE or TABNET_WIDE_SHAPE entry.
+static const KernelEntry kKernels[] = {TABNET_TILE_SWEEP};
+#else
+static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) TABNET_SHAPES(1) TABNET_SHAPE_200_W8(1)
+                                       TABNET_SHAPES(2) TABNET_SHAPE_200_W8(2) TABNET_SHAPES(3) TABNET_SHAPE_200(3)
+                                       TABNET_SHAPES(4) TABNET_SHAPE_200(4) TABNET_SHAPES(5) TABNET_SHAPE_200_W8(5)
+                                       TABNET_SHAPES(6) TABNET_SHAPE_200(6) TABNET_SHAPES(7) TABNET_SHAPE_200(7)
+                                       TABNET_SHAPES(8) TABNET_SHAPE_200(8) TABNET_SHAPES(9) TABNET_SHAPE_200_W8(9)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)
                                                TABNET_WIDE_SHAPE(9, 32, 8, 4, 4, 2)};
+#endif
 
-const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw) {
-  for (const auto& e : kKernels)
-    if (e.prec == prec && e.DT == DT && e.NT == NT && e.KA0 == KA0 && e.raw == raw) return &e;
-  return nullptr;
+size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
+
+// The forward kernel of a model: the first compiled entry of its shape whose LDS holds the
+// model (D, n_out, n_d) and whose raw-row twin (same tiling) holds it too without embedding
+// tables; else the first that holds the model; else the first entry of the shape, whose
+// LDS check then refuses the model.  With `twin`: the entry of the twin's tiling (R, W) and
+// `raw`, so that a raw-row kernel shares the weight chunking of the handle's forward kernel.
+const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int D, int n_out, int n_d,
+                               const KernelEntry* twin) {
+  auto shape_of = [&](const KernelEntry& e, bool r) {
+    return e.prec == prec && e.DT == DT && e.NT == NT && e.KA0 == KA0 && e.raw == r;
+  };
+  auto fits = [&](const KernelEntry& e) { return kernel_lds_bytes(&e, D, n_out, n_d, 0, 0) <= (size_t)kMaxLdsBytes; };
+  if (twin) {
+    for (const auto& e : kKernels)
+      if (shape_of(e, raw) && e.R == twin->R && e.W == twin->W) return &e;
+    return nullptr;
+  }
+  const KernelEntry *first = nullptr, *first_fit = nullptr;
+  for (const auto& e : kKernels) {
+    if (!shape_of(e, raw)) continue;
+    if (!first) first = &e;
+    if (!fits(e)) continue;
+    if (!first_fit) first_fit = &e;
+    const KernelEntry* r = nullptr;
+    for (const auto& e2 : kKernels)
+      if (shape_of(e2, true) && e2.R == e.R && e2.W == e.W) r = &e2;
+    if (raw || !r || fits(*r)) return &e;
+  }
+  return first_fit ? first_fit : first;
 }
 
 // LDS of one workgroup: the two weight buffers, the per-wave mask staging areas, the

@@ -123,10 +123,11 @@ constexpr GemmPlan gemm_plan(int unit, int nunits, int target) {
 
 // Bytes of one LDS weight buffer for a workgroup of W waves of R 16-row blocks: at most
 // kChunkTarget, and small enough that the two buffers fit beside the per-wave mask
-// staging areas (W * 16 R rows of up to 16 DT features) with 4 KiB left for the final
-// map and the raw-row maps.
+// staging areas (W * 16 R rows of up to 16 DT features) with 8 KiB left for the final
+// map and the raw-row maps (4 D feature descriptors and an n_out x n_d map: 5.7 KiB at
+// D = 208, n_d = 79 and 8 outputs).
 constexpr int chunk_target(int DT, int R, int W) {
-  const int room = (kMaxLdsBytes - W * 16 * R * 16 * DT * 4 - 4096) / 2 / 1024 * 1024;
+  const int room = (kMaxLdsBytes - W * 16 * R * 16 * DT * 4 - 8192) / 2 / 1024 * 1024;
   return room < kChunkTarget ? (room < 8192 ? 8192 : room) : kChunkTarget;
 }
 

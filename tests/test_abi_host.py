@@ -189,51 +189,82 @@ def test_int8_weight_coding_matches_oracle(L):
     assert (z == 0).all() and (sc == 1.0).all()
 
 
-def test_packed_sizes(L):
-    """Packed bytes follow the documented unit layout: a GLU layer is NT units of
-    [value fragments][gate fragments][32 shifts], an attentive layer DT units of
-    [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32), per pair
-    of K tiles (BF16, an odd last tile padded) or per four K tiles (INT8); E4M3 and INT8
-    units add one scale per output; every GEMM starts 256-byte aligned.
-    The chunk count is the number of weight-stream pieces of at most T bytes (balanced,
-    one unit if a unit is larger) over pass 0, then per step attentive + pass, where T is
-    40 KiB or less: the two LDS buffers must fit beside the staging areas of the
-    workgroup's waves (8 waves of 16 rows for the Adult-shaped kernel, 4 for the others)
-    with 4 KiB to spare, in whole KiB."""
-    def cdiv(a, b):
-        return -(-a // b)
+def _cdiv(a, b):
+    return -(-a // b)
+
+
+def expected_packing(cfg, prec, W):
+    """Packed bytes and chunk count of a model for a kernel of W waves (see test_packed_sizes)."""
+    cdiv = _cdiv
 
     def chunks(unit, n, target):
         upc = cdiv(n, cdiv(unit * n, target))
         upc = min(upc, max(1, target // unit))
         return cdiv(n, upc)
 
+    DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
+    sh_k, ind_k = synth.layer_in_dims(cfg)
+    ks = sh_k + ind_k * (cfg.n_steps + 1)
+    target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 8192) // 2 // 1024 * 1024))
+    per = {0: 1, 1: 2, 2: 4, 3: 4, 9: 4}.get(prec, 8)     # K tiles per k-block (8 for every MX format)
+    # MX: elements (8-, 4- and 6-bit) + scales
+    kbb = {4: 2 * 1024 + 256, 7: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256, 8: 1536 + 256}.get(prec, 1024)
+    kbytes = (lambda KT: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
+    ex = 2 if prec in (2, 3, 9) else 1     # E4M3, INT8 and FP8-weight units also carry one scale per output
+    glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}
+    att_unit = kbytes(NT - KA0) + 64 * ex
+    nbytes = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
+    first = chunks(2 * kbytes(DT) + 128 * ex, NT, target)
+    mid = chunks(2 * kbytes(NT) + 128 * ex, NT, target)
+    nl = cfg.n_shared + cfg.n_indep
+    nch = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT, target)
+    return nbytes, nch
+
+
+def packed_sizes(L, cfg, prec):
+    raw = synth.to_bytes(synth.make_params(cfg, 1))
+    wb, nch = ctypes.c_int64(), ctypes.c_int64()
+    assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == 0
+    return wb.value, nch.value
+
+
+def test_packed_sizes(L):
+    """Packed bytes follow the documented unit layout: a GLU layer is NT units of
+    [value fragments][gate fragments][32 shifts], an attentive layer DT units of
+    [fragments][16 shifts]; a fragment is 1 KiB per 16-wide K tile (FP32), per pair
+    of K tiles (BF16, an odd last tile padded) or per four K tiles (E4M3, INT8); E4M3,
+    INT8 and FP8-weight units add one scale per output; every GEMM starts 256-byte aligned.
+    The chunk count is the number of weight-stream pieces of at most T bytes (balanced,
+    one unit if a unit is larger) over pass 0, then per step attentive + pass, where T is
+    40 KiB or less: the two LDS buffers must fit beside the staging areas of the
+    workgroup's waves (8 waves of 16 rows for the Adult-shaped kernel and for the
+    200-feature kernel in FP32, BF16, both FP8 forms and MXFP4; 4 for the others) with
+    8 KiB to spare, in whole KiB."""
     for name in ("hr35", "adult108", "wide200"):
         cfg = synth.WORKLOADS[name]["cfg"]
-        p = synth.make_params(cfg, 1)
-        raw = synth.to_bytes(p)
-        DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
-        W = 8 if DT == 7 else 4
-        target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 4096) // 2 // 1024 * 1024))
-        sh_k, ind_k = synth.layer_in_dims(cfg)
-        ks = sh_k + ind_k * (cfg.n_steps + 1)
-        for prec in range(9):
-            per = {0: 1, 1: 2, 2: 4, 3: 4}.get(prec, 8)     # K tiles per k-block (8 for every MX format)
-            # MX: elements (8-, 4- and 6-bit) + scales
-            kbb = {4: 2 * 1024 + 256, 7: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256, 8: 1536 + 256}.get(prec, 1024)
-            kbytes = (lambda KT, per=per, kbb=kbb: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
-            ex = 2 if prec in (2, 3) else 1     # E4M3 and INT8 units also carry one scale per output
-            glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}
-            att_unit = kbytes(NT - KA0) + 64 * ex
-            exp = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
-            first = chunks(2 * kbytes(DT) + 128 * ex, NT, target)
-            mid = chunks(2 * kbytes(NT) + 128 * ex, NT, target)
-            nl = cfg.n_shared + cfg.n_indep
-            exp_chunks = (cfg.n_steps + 1) * (first + (nl - 1) * mid) + cfg.n_steps * chunks(att_unit, DT, target)
-            wb, nch = ctypes.c_int64(), ctypes.c_int64()
-            assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == 0
-            assert wb.value == exp, (name, prec, wb.value, exp)
-            assert nch.value == exp_chunks, (name, prec, nch.value, exp_chunks)
+        DT = _cdiv(cfg.D, 16)
+        for prec in range(10):
+            W = 8 if DT == 7 or (DT == 13 and prec in (0, 1, 2, 5, 9)) else 4
+            assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W), (name, prec)
+
+
+@pytest.mark.parametrize("prec,n_out,W", [(0, 3, 8), (0, 18, 8), (0, 19, 4), (0, 64, 4), (1, 64, 8), (9, 64, 8),
+                                          (3, 3, 4)])
+def test_200_feature_tiling_falls_back_to_four_waves(L, prec, n_out, W):
+    """The 200-feature shape runs eight waves per workgroup in FP32, BF16, both FP8 forms
+    and MXFP4 where the LDS holds the two weight buffers, eight staging areas of 16 rows x
+    D floats and the final map (n_out x n_d floats), and the raw-row twin of that kernel
+    fits too (4 D feature descriptors more, the map padded to 16 bytes); otherwise four.
+    D = 200, n_d = 64.  In FP32 a buffer holds one first-layer unit of 2 x 13 K tiles x
+    1 KiB + 128 bytes (26,752 bytes), so eight waves leave room for a map of up to 18
+    outputs beside the raw-row twin; in BF16 a buffer is 16,640 bytes (two mid-layer
+    units) and any n_out <= 64 fits."""
+    cfg = synth.TabNetConfig(D=200, n_d=64, n_a=64, n_steps=2, n_shared=1, n_indep=1, n_out=n_out, gamma=1.3)
+    buf = {0: 26752, 1: 16640}.get(prec)
+    if buf is not None:
+        lds_raw = 2 * buf + (8 * 16 * 200 + _cdiv(n_out * 64, 4) * 4) * 4 + 16 * 200
+        assert (lds_raw <= 160 * 1024) == (W == 8)
+    assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W), (prec, n_out)
 
 
 def test_mask_stats_workspace_and_argument_checks(L):
