@@ -857,6 +857,13 @@ template <int PREC, int DT, int NT, int KA0, int R, int W, bool RAW>
 __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   constexpr Plan PL = make_plan(PREC, DT, NT, KA0, chunk_target(DT, R, W));
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
+  // Where a 16-row block's resident state (x, P, the aggregate and M per feature; h and the
+  // decision sums per hidden channel) passes the registers a wave has at W / 4 waves per
+  // SIMD, less room for the GLU's operands, the aggregate mask lives in this wave's staging
+  // area ([16 R rows][D], each lane reading and writing only its own features) and the step
+  // masks leave straight from registers.  Elsewhere the aggregate stays in registers and
+  // the step masks leave through the staging area as whole rows.
+  constexpr bool AGG_LDS = !RAW && (16 * DT + 8 * NT) * R > 512 / (W < 4 ? 1 : W / 4) - 64;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
@@ -903,6 +910,32 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) last_ok[i] = 16 * (DT - 1) + 4 * g + i < D;
   auto feat_ok = [&](int t, int i) { return t < DT - 1 || last_ok[i]; };
+  // this lane's features of tile t of row block rb in the staging area ([16 R rows][D])
+  auto own_get = [&](int rb, int t, float (&m)[4]) {
+    const float* sr = stage + (16 * rb + rl) * D + 16 * t + 4 * g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m[i] = 0.f;
+    if ((D & 3) == 0) {
+      if (feat_ok(t, 0)) {
+        const f4 q = *reinterpret_cast<const f4*>(sr);
+        m[0] = q[0]; m[1] = q[1]; m[2] = q[2]; m[3] = q[3];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (feat_ok(t, i)) m[i] = sr[i];
+    }
+  };
+  auto own_put = [&](int rb, int t, const float (&m)[4]) {
+    float* sr = stage + (16 * rb + rl) * D + 16 * t + 4 * g;
+    if ((D & 3) == 0) {
+      if (feat_ok(t, 0)) *reinterpret_cast<f4*>(sr) = f4{m[0], m[1], m[2], m[3]};
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (feat_ok(t, i)) sr[i] = m[i];
+    }
+  };
 
   WeightStream<W, PL.buf> ws;
   ws.lds = smem;
@@ -970,14 +1003,19 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   }
   ws.end();
 
-  float P[R][DT][4], agg[R][DT][4], M[R][DT][4];
+  float P[R][DT][4], agg[AGG_LDS ? 1 : R][AGG_LDS ? 1 : DT][4], M[R][DT][4];
   float h[R][NT][4], acc[R][NT][4];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) {
 #pragma unroll
     for (int t = 0; t < DT; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { P[rb][t][i] = 1.f; agg[rb][t][i] = 0.f; }
+      for (int i = 0; i < 4; ++i) { P[rb][t][i] = 1.f; if constexpr (!AGG_LDS) agg[rb][t][i] = 0.f; }
+    if constexpr (AGG_LDS) {
+      const float z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < DT; ++t) own_put(rb, t, z);
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -1141,6 +1179,25 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
         for (int rb = 0; rb < R; ++rb) reduce_columns<DT>(M[rb], A.colbits, C, stage + 16 * rb * C, lane);
         lds_wave_sync();
         stage_out(stage, A.masks_step + (int64_t)(s - 1) * step_stride + wrow0 * C, live_rows * C, lane);
+      } else if constexpr (AGG_LDS) {
+        // each lane stores its own 16-byte pieces (D % 4 == 0) or floats; ordinary stores, so
+        // that L2 joins the pieces of a line before it writes the line back
+#pragma unroll
+        for (int rb = 0; rb < R; ++rb) {
+          if (!live[rb]) continue;
+          float* dr = A.masks_step + (int64_t)(s - 1) * step_stride + (wrow0 + 16 * rb + rl) * D + 4 * g;
+#pragma unroll
+          for (int t = 0; t < DT; ++t) {
+            if (vec4) {
+              if (feat_ok(t, 0))
+                *reinterpret_cast<f4*>(dr + 16 * t) = f4{M[rb][t][0], M[rb][t][1], M[rb][t][2], M[rb][t][3]};
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (feat_ok(t, i)) dr[16 * t + i] = M[rb][t][i];
+            }
+          }
+        }
       } else {
 #pragma unroll
         for (int rb = 0; rb < R; ++rb) {
@@ -1186,10 +1243,21 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
           ep[i] += r;
         }
       const float eta = row_sum((ep[0] + ep[1]) + (ep[2] + ep[3]));
+      if constexpr (AGG_LDS) {
 #pragma unroll
-      for (int t = 0; t < DT; ++t)
+        for (int t = 0; t < DT; ++t) {
+          float a[4];
+          own_get(rb, t, a);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) agg[rb][t][i] += eta * M[rb][t][i];
+          for (int i = 0; i < 4; ++i) a[i] += eta * M[rb][t][i];
+          own_put(rb, t, a);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < DT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) agg[rb][t][i] += eta * M[rb][t][i];
+      }
     }
   }
 
@@ -1211,10 +1279,20 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       if (live[rb] && g == (o & 3)) A.logits[row * A.n_out + o] = part;
     }
     float den = 0.f;
+    if constexpr (AGG_LDS) {
 #pragma unroll
-    for (int t = 0; t < DT; ++t)
+      for (int t = 0; t < DT; ++t) {
+        float a[4];
+        own_get(rb, t, a);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) den += agg[rb][t][i];
+        for (int i = 0; i < 4; ++i) den += a[i];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < DT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) den += agg[rb][t][i];
+    }
     den = row_sum(den);
     const float inv = den > 0.f ? 1.0f / den : 0.f;
     if constexpr (RAW) {
@@ -1223,6 +1301,15 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) agg[rb][t][i] *= inv;
       reduce_columns<DT>(agg[rb], A.colbits, C, stage + 16 * rb * C, lane);
+    } else if constexpr (AGG_LDS) {
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        float a[4];
+        own_get(rb, t, a);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] *= inv;
+        own_put(rb, t, a);
+      }
     } else {
       float* sr = stage + (16 * rb + rl) * D + 4 * g;
       if (vec4) {
