@@ -864,6 +864,10 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   // masks leave straight from registers.  Elsewhere the aggregate stays in registers and
   // the step masks leave through the staging area as whole rows.
   constexpr bool AGG_LDS = !RAW && (16 * DT + 8 * NT) * R > 512 / (W < 4 ? 1 : W / 4) - 64;
+  // There, FP32 and both FP8 forms also read x again from X before each pass instead of
+  // keeping it (their spills shrink from 600-720 to 320-380 bytes per lane, and the 200-feature
+  // forward gains 2-12%); BF16 and MXFP4, whose spills are smaller, lose 10% that way.
+  constexpr bool X_AGAIN = AGG_LDS && (PREC == 0 || PREC == 2 || PREC == 9);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const int64_t B = A.B_dev != nullptr ? *A.B_dev : A.B;
@@ -1004,7 +1008,9 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   ws.end();
 
   float P[R][DT][4], agg[AGG_LDS ? 1 : R][AGG_LDS ? 1 : DT][4], M[R][DT][4];
-  float h[R][NT][4], acc[R][NT][4];
+  // decision sums: only tiles [0, KA0] can hold decision channels (n_d < 16 (KA0 + 1))
+  constexpr int KD = KA0 + 1 < NT ? KA0 + 1 : NT;
+  float h[R][NT][4], acc[R][KD][4];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) {
 #pragma unroll
@@ -1017,7 +1023,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       for (int t = 0; t < DT; ++t) own_put(rb, t, z);
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < KD; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[rb][t][i] = 0.f;
   }
@@ -1227,14 +1233,45 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       for (int t = 0; t < DT; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) P[rb][t][i] *= A.gamma - M[rb][t][i];
-    build_b(u, [&](int rb, int t, int i) { return M[rb][t][i] * x[rb][t][i]; });
+    if constexpr (X_AGAIN) {
+      // x again from X and the input affine map (L2), so that it is not live across the
+      // feature transformer: the same values as in the prologue
+      float xs[R][DT][4];
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const f4 sc = *reinterpret_cast<const f4*>(A.in_affine + 16 * t + 4 * g);
+        const f4 sh = *reinterpret_cast<const f4*>(A.in_affine + 16 * DT + 16 * t + 4 * g);
+#pragma unroll
+        for (int rb = 0; rb < R; ++rb) {
+          float v[4] = {0.f, 0.f, 0.f, 0.f};
+          const float* xr = A.X + (wrow0 + 16 * rb + rl) * D + 16 * t + 4 * g;
+          if (live[rb]) {
+            if (vec4) {
+              if (feat_ok(t, 0)) {
+                const f4 q = *reinterpret_cast<const f4*>(xr);
+                v[0] = q[0]; v[1] = q[1]; v[2] = q[2]; v[3] = q[3];
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (feat_ok(t, i)) v[i] = xr[i];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) xs[rb][t][i] = v[i] * sc[i] + sh[i];
+        }
+      }
+      build_b(u, [&](int rb, int t, int i) { return M[rb][t][i] * xs[rb][t][i]; });
+    } else {
+      build_b(u, [&](int rb, int t, int i) { return M[rb][t][i] * x[rb][t][i]; });
+    }
     // ---- feature transformer pass s, decision aggregation ----
     ft_pass<PREC, DT, NT, KA0, R>(ws, L, u, h, lane);
 #pragma unroll
     for (int rb = 0; rb < R; ++rb) {
       float ep[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int t = 0; t < KD; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool dec = 16 * t + 4 * g + i < n_d;
@@ -1269,7 +1306,7 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
       const float* wf = wfin_s + o * n_d;
       float part = 0.f;
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+      for (int t = 0; t < KD; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = 16 * t + 4 * g + i;
