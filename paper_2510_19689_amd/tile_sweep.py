@@ -42,6 +42,9 @@ FAMILIES = {
     "wide512": dict(workload="wide512", rows=65536, shape=(1, 32, 8, 4), wide=True, product=(4, 2),
                     candidates=[(2, 1), (2, 2), (2, 3), (4, 1), (4, 2), (4, 3)]),
 }
+# the 200-feature shape on the split-feature kernel
+FAMILIES["wide200_split"] = dict(workload="wide200", rows=262144, shape=(1, 13, 8, 4), wide=True, product=None,
+                                 candidates=[(2, 1), (2, 2), (2, 4), (4, 1), (4, 2)])
 # the 200-feature shape in the other precisions: one or two waves per SIMD
 PREC_CODES = {"fp32": 0, "fp8": 2, "int8": 3, "mxfp8": 4, "mxfp4": 5, "mxfp6": 6, "mxfp8_e5m2": 7,
               "mxfp6_e3m2": 8, "fp8w": 9}
@@ -154,8 +157,9 @@ def run_all(families=None) -> None:
             print(f"[sweep] {name} {t}: {res[t]}", file=sys.stderr, flush=True)
         ref1 = _time(product, wl, rows, os.path.join(tmp, f"{name}_product2.npz"), prec)
         a, b = ("R", "W") if not fam["wide"] else ("W", "RG")
-        print(f"\n{name} ({wl}, {rows:,} rows, {prec}, step masks on); product tiling {a}={fam['product'][0]}, "
-              f"{b}={fam['product'][1]}: {ref0.get('us', float('nan')):.1f} us before the candidates, "
+        prod = f"{a}={fam['product'][0]}, {b}={fam['product'][1]}" if fam["product"] else "another kernel"
+        print(f"\n{name} ({wl}, {rows:,} rows, {prec}, step masks on); product tiling {prod}: "
+              f"{ref0.get('us', float('nan')):.1f} us before the candidates, "
               f"{ref1.get('us', float('nan')):.1f} us after\n")
         print(f"| {a} | {b} | us per launch | all outputs bit-equal to the product's | max diff, first 1,024 rows |")
         print("|---|---|---|---|---|")
@@ -164,7 +168,7 @@ def run_all(families=None) -> None:
                 print(f"| {t[0]} | {t[1]} | failed: {r['error'][:80]} | | |")
                 continue
             same = "yes" if r["sha"] == ref0.get("sha") else "no"
-            mark = " (product)" if t == tuple(fam["product"]) else ""
+            mark = " (product)" if fam["product"] and t == tuple(fam["product"]) else ""
             print(f"| {t[0]} | {t[1]}{mark} | {r['us']:.1f} | {same} | {r.get('maxdiff', float('nan')):.3g} |")
         sys.stdout.flush()
 
