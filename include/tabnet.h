@@ -127,7 +127,8 @@ typedef struct tabnet_handle tabnet_handle;
  * fewer positions holds the rest.  The kernel forms blocks from pairs of 16-channel
  * tiles, so a model whose attention half neither starts a tile (n_d % 16 == 0) nor fits
  * the tile pair it starts in (n_d % 16 + n_a <= 32) is TABNET_E_UNSUPPORTED in these
- * formats.  Same kernel coverage and non-finite behaviour as TABNET_INT8 otherwise.
+ * formats.  Non-finite behaviour as TABNET_INT8.  The split-feature kernel (the 512-feature
+ * shape) has a TABNET_MXFP4 entry; the 8- and 6-bit MX forms are TABNET_E_UNSUPPORTED there.
  */
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out);
 

@@ -528,6 +528,29 @@ __device__ __forceinline__ void mma_tile_mx(const unsigned char* fr, const BOp<P
   }
 }
 
+// One k-block of an MX GEMM for one output tile: `f` points at the k-block's elements and
+// scales (kbytes(PREC) bytes), `kb` selects the B operand's k-block.
+template <int PREC, int KT>
+__device__ __forceinline__ f4 mma_kblock_mx(const unsigned char* f, const BOp<PREC, KT, 1>& b, int kb, f4 acc,
+                                            int lane) {
+  constexpr int FMT = PREC == 4 ? 0 : (PREC == 7 ? 1 : (PREC == 6 ? 2 : (PREC == 8 ? 3 : 4)));
+  constexpr int ND = is_mx8(PREC) ? 8 : (is_mx6(PREC) ? 6 : 4);
+  constexpr int EL = kbytes(PREC) - kMxScaleBytes;
+  const i4 lo = *reinterpret_cast<const i4*>(f + lane * 16);
+  i4 hi = {0, 0, 0, 0};
+  if constexpr (is_mx8(PREC)) hi = *reinterpret_cast<const i4*>(f + kFrag + lane * 16);
+  if constexpr (is_mx6(PREC)) {
+    const uint2 m = *reinterpret_cast<const uint2*>(f + kFrag + lane * 8);
+    hi = i4{(int)m.x, (int)m.y, 0, 0};
+  }
+  const i8v a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  const int sa = *reinterpret_cast<const int*>(f + EL + lane * 4);
+  i8v bb;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bb[j] = j < ND ? (int)b.v[0][kb][j < ND ? j : 0] : 0;
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bb, acc, FMT, FMT, 0, sa, 0, (int)b.sc[0][kb]);
+}
+
 // Fill a GEMM's B operand from src(rb, t, i), the input of row block rb at the lane's
 // feature 16 t + 4 g + i.
 template <int PREC, int KT, int R, class F>
@@ -1386,7 +1409,9 @@ struct WideGeom {
   static constexpr int TPW = wide_tpw(DT, W);     // feature tiles per wave
   static constexpr int DTP = TPW * W;             // padded feature tiles
   static constexpr int OPW = NT / W;              // output tile pairs per wave
-  static constexpr int UKB = PREC == 0 ? DTP : DTP / 2;   // k-blocks of u
+  // u in LDS: FP32 tiles (FP32, and MX, whose waves code every block of the row themselves)
+  // or BF16 k-blocks
+  static constexpr int UKB = PREC == 0 || is_mx(PREC) ? DTP : DTP / 2;
   static constexpr int UBYTES = UKB * kFrag;
 };
 
@@ -1417,6 +1442,7 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
                                                float (&h)[NT / W][4], bool first, int lane, int wave) {
   constexpr int OPW = NT / W;
   constexpr int KB = kblocks(PREC, KT);
+  constexpr int FB = kbytes(PREC);   // weight bytes of one output tile's k-block
   const int g = lane >> 4;
   f4 av[OPW], ag[OPW];
 #pragma unroll
@@ -1424,6 +1450,10 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
     av[p] = f4{0.f, 0.f, 0.f, 0.f};
     ag[p] = f4{0.f, 0.f, 0.f, 0.f};
   }
+  // MX: every wave codes the whole layer input (FP32 tiles in LDS) into OCP blocks itself
+  BOp<PREC, KT, 1> bm;
+  if constexpr (is_mx(PREC))
+    build_b(bm, [&](int, int t, int i) { return reinterpret_cast<const float*>(src + ((size_t)t * 64 + lane) * 16)[i]; });
   for (int kb0 = 0; kb0 < KB; kb0 += sk) {
     const int nkb = KB - kb0 < sk ? KB - kb0 : sk;
     ws.begin();
@@ -1437,15 +1467,18 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
         const int k2 = 2 * (kb0 + q);
         load_kblock<1, SRC_F32>(src, k2, KT, lane, bf, bb);
         if (k2 + 1 < kblocks(1, KT)) load_kblock<1, SRC_F32>(src, k2 + 1, KT, lane, bf, bb2);
-      } else {
+      } else if constexpr (!is_mx(PREC)) {
         load_kblock<PREC, SRC_F32>(src, kb0 + q, KT, lane, bf, bb);
       }
 #pragma unroll
       for (int p = 0; p < OPW; ++p) {
         const int pr = wave * OPW + p;
-        const unsigned char* fv = buf + ((size_t)(pr * 2 + 0) * nkb + q) * kFrag + lane * 16;
-        const unsigned char* fg = buf + ((size_t)(pr * 2 + 1) * nkb + q) * kFrag + lane * 16;
-        if constexpr (is_fp8w(PREC)) {
+        const unsigned char* fv = buf + ((size_t)(pr * 2 + 0) * nkb + q) * FB + lane * 16;
+        const unsigned char* fg = buf + ((size_t)(pr * 2 + 1) * nkb + q) * FB + lane * 16;
+        if constexpr (is_mx(PREC)) {
+          av[p] = mma_kblock_mx<PREC, KT>(fv - lane * 16, bm, kb0 + q, av[p], lane);
+          ag[p] = mma_kblock_mx<PREC, KT>(fg - lane * 16, bm, kb0 + q, ag[p], lane);
+        } else if constexpr (is_fp8w(PREC)) {
           const i4 a = *reinterpret_cast<const i4*>(fv);
           const i4 c = *reinterpret_cast<const i4*>(fg);
           av[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(widen_e4m3x8(a[0], a[1]), bb, av[p], 0, 0, 0);
@@ -1468,7 +1501,7 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
     }
     if (kb0 + nkb == KB) {
       // shifts of every pair follow the fragments of the layer's last slice
-      const float* sft = reinterpret_cast<const float*>(buf + (size_t)NT * 2 * nkb * kFrag);
+      const float* sft = reinterpret_cast<const float*>(buf + (size_t)NT * 2 * nkb * FB);
 #pragma unroll
       for (int p = 0; p < OPW; ++p) {
         const int pr = wave * OPW + p;
@@ -1507,7 +1540,7 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
 template <int PREC, int TPW>
 __device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[TPW][4], const float (&x)[TPW][4],
                                           int wave, int lane) {
-  if constexpr (PREC == 0) {
+  if constexpr (PREC == 0 || is_mx(PREC)) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
       *reinterpret_cast<f4*>(u_s + ((size_t)(wave * TPW + t) * 64 + lane) * 16) =
@@ -1648,9 +1681,18 @@ tabnet_wide_kernel(FwdArgs A) {
     // ---- attentive transformer on this wave's feature tiles ----
     {
       constexpr int KB2 = kblocks(1, KTA);            // BF16 k-blocks of the input
+      constexpr int FBA = kbytes(PREC);
       f4 bf[PREC == 0 ? KTA : 1];
-      s8 bb[PREC == 0 ? 1 : KB2];
-      if constexpr (PREC == 0) {
+      s8 bb[PREC == 0 || is_mx(PREC) ? 1 : KB2];
+      BOp<PREC, KTA, 1> bma;   // MX: the attention half a = h[n_d, n_d + n_a) in OCP blocks
+      if constexpr (is_mx(PREC)) {
+        const int n_att_end = n_d + A.n_a;
+        build_b(bma, [&](int, int t, int i) {
+          const int ch = 16 * (KA0 + t) + 4 * g + i;
+          const float v = reinterpret_cast<const float*>(h_s + ((size_t)(KA0 + t) * 64 + lane) * 16)[i];
+          return ch >= n_d && ch < n_att_end ? v : 0.f;
+        });
+      } else if constexpr (PREC == 0) {
 #pragma unroll
         for (int t = 0; t < KTA; ++t) bf[t] = *reinterpret_cast<const f4*>(h_s + ((size_t)(KA0 + t) * 64 + lane) * 16);
       } else {
@@ -1673,8 +1715,11 @@ tabnet_wide_kernel(FwdArgs A) {
         for (int q = 0; q < PL.tpc; ++q) {
           const int t = j * PL.tpc + q;      // compile-time after unrolling
           const unsigned char* unit = buf + (size_t)(wave * PL.tpc + q) * PL.att_unit;
-          f4 z = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 16 * g);
-          if constexpr (is_fp8w(PREC)) {
+          f4 z = *reinterpret_cast<const f4*>(unit + KBA * FBA + 16 * g);
+          if constexpr (is_mx(PREC)) {
+#pragma unroll
+            for (int kb = 0; kb < KBA; ++kb) z = mma_kblock_mx<PREC, KTA>(unit + kb * FBA, bma, kb, z, lane);
+          } else if constexpr (is_fp8w(PREC)) {
             f4 a8 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < KBA; ++kb) {
@@ -1944,7 +1989,8 @@ static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) T
                                        TABNET_SHAPES(8) TABNET_SHAPE_200(8) TABNET_SHAPES(9) TABNET_SHAPE_200_W8(9)
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)
-                                               TABNET_WIDE_SHAPE(9, 32, 8, 4, 4, 2)};
+                                               TABNET_WIDE_SHAPE(9, 32, 8, 4, 4, 2)
+                                                   TABNET_WIDE_SHAPE(5, 32, 8, 4, 4, 2)};
 #endif
 
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
@@ -1989,7 +2035,7 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
     // and start areas; the final map and the open-row flags
     const int wf = k->plan.W;
     const int dtp = wide_tpw(k->DT, wf) * wf;
-    const size_t ub = (size_t)(k->prec == 0 ? dtp : dtp / 2) * kFrag;
+    const size_t ub = (size_t)(k->prec == 0 || is_mx(k->prec) ? dtp : dtp / 2) * kFrag;
     const size_t group = ub + (size_t)k->NT * kFrag + (size_t)wf * 16 * 8 * 4;
     return 2 * (size_t)k->plan.buf + (size_t)k->R * group + (size_t)n_out * n_d * 4 + 2 * (size_t)k->R * 4;
   }

@@ -162,14 +162,14 @@ constexpr Plan make_plan(int prec, int DT, int NT, int KA0, int target) {
   return Plan{first, mid, att, buf};
 }
 
-// Fragment bytes of one K slice of the split-feature kernel, in KiB (plus the shifts).
+// Weight bytes of one K slice of the split-feature kernel, in KiB (plus the shifts).
 constexpr int kWideSliceKib = 32;
 // Split-feature plan: wave w owns feature tiles [w tpw, (w + 1) tpw) of the padded row
 // (tpw even, so that BF16 tile pairs never straddle waves) and output tile pairs
 // [w NT / W, (w + 1) NT / W) of every feature-transformer layer.
 constexpr int wide_tpw(int DT, int W) { return (cdiv(DT, W) + 1) / 2 * 2; }
 constexpr int wide_slice_bytes(int prec, int NT, int nkb, bool last) {
-  return NT * 2 * nkb * kFrag + (last ? NT * 128 * (has_channel_scales(prec) ? 2 : 1) : 0);
+  return NT * 2 * nkb * kbytes(prec) + (last ? NT * 128 * (has_channel_scales(prec) ? 2 : 1) : 0);
 }
 constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   Plan p{};
@@ -177,8 +177,9 @@ constexpr Plan make_wide_plan(int prec, int DT, int NT, int KA0, int W) {
   p.W = W;
   p.tpw = wide_tpw(DT, W);
   constexpr int kib = kWideSliceKib;
-  p.sk = kib / (2 * NT) < 1 ? 1 : kib / (2 * NT);   // k-blocks per slice
-  p.att_unit = kblocks(prec, NT - KA0) * kFrag + 64 * (has_channel_scales(prec) ? 2 : 1);
+  const int sk = kib * 1024 / (2 * NT * kbytes(prec));
+  p.sk = sk < 1 ? 1 : sk;   // k-blocks per slice
+  p.att_unit = kblocks(prec, NT - KA0) * kbytes(prec) + 64 * (has_channel_scales(prec) ? 2 : 1);
   int tpc = p.tpw;
   while (tpc > 1 && (W * tpc * p.att_unit > kib * 1024 + NT * 128 || p.tpw % tpc != 0)) --tpc;
   p.tpc = tpc;

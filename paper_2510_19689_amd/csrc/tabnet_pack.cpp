@@ -521,9 +521,10 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   const int N = c.n_d + c.n_a;
   std::vector<double> Wf, bf;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
-  // K tiles per k-block: FP32 one, BF16 two, E4M3 weights four (widened in the kernel)
+  // K tiles per k-block: FP32 one, BF16 two, E4M3 weights four (widened in the kernel), MX
+  // eight
   const bool w8 = precision == TABNET_FP8_WEIGHTS;
-  const int kbn = precision == TABNET_FP32 ? 1 : (w8 ? 4 : 2);
+  const int kbn = ktiles_per_block(precision);
   std::vector<double> sc;
   std::vector<std::vector<ChunkRec>> ft_chunks, att_chunks;
   for (const LayerRaw* L : ft) {

@@ -8,7 +8,8 @@ and argmax 99.9 % against FP64; against an FP64 forward on the same bf16-rounded
 BF16 inputs: logits 2e-2 and argmax against FP64; against FP64 on the same operands (E4M3
 weights with their channel scales, bf16-rounded inputs) logits 2e-3, aggregate L1 1.5e-2
 and step L1 2e-2 per row (the format alone moves a step mask by up to 0.12 in L1 on the
-512-feature model, so these gates are set against the rounded operands)."""
+512-feature model, so these gates are set against the rounded operands).  MXFP4: the
+register kernel's row-by-row gates against FP64 on MX operands (check_mx_rows)."""
 import os
 
 import numpy as np
@@ -109,6 +110,36 @@ def test_fp8_weights_matches_oracle(B, tmp_path):
     assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
 
 
+def check_mx_rows(got, params, X, tag):
+    """MXFP4 against FP64 on the same MX operands, row by row (the gates of the register
+    kernel's MXFP4 path: 90% of rows within 1e-5 in step-mask L1 and logits, every row within
+    0.4 step L1, 0.2 aggregate L1 and 2e-2 in the logits), and against plain FP64 (logits
+    6e-2, argmax)."""
+    lo, ag, ms = got
+    rlo, rag, rms = oracle.forward(params, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="mxfp4", acts="mxfp4")
+    step = np.abs(ms - qms).sum(-1).max(0)
+    agg = np.abs(ag - qag).sum(-1)
+    logit = np.abs(lo - qlo).max(1)
+    _say(tag, "vs mxfp4-operand fp64: step L1 p50/max", np.median(step), step.max(), "agg L1 max", agg.max(),
+         "logits max", logit.max(), "rows moved", float((step > 1e-5).mean()), "| vs fp64 logits",
+         np.abs(lo - rlo).max())
+    assert np.isfinite(lo).all() and np.isfinite(ag).all()
+    assert (step <= 1e-5).mean() >= 0.9 and (logit <= 1e-5).mean() >= 0.9
+    assert step.max() <= 0.4 and agg.max() <= 0.2 and logit.max() <= 2e-2
+    assert np.abs(lo - rlo).max() <= 6e-2 and (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.99
+
+
+@pytest.mark.parametrize("B", [33, 300])
+def test_mxfp4_matches_oracle(B, tmp_path):
+    _say(f"case wide mxfp4 B={B}")
+    params, m = load(WIDE, 1005, "mxfp4", tmp_path)
+    X = synth.make_inputs("wide512", B, 2005)
+    with m:
+        got = run(m, X)
+    check_mx_rows(got, params, X, f"mxfp4 B={B}")
+
+
 def random_wide(k):
     """Seeded configuration k of the split-feature kernel's family (D = 497..512, n_d + n_a =
     113..128, 64 <= n_d < 80): 1-10 steps, 0-3 shared and 0-3 step layers (at least one),
@@ -152,7 +183,7 @@ def test_random_wide_configurations(k, tmp_path):
     assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "mxfp4"])
 def test_full_size_sampled(prec, tmp_path):
     """The 512-feature workload at its full batch (65,536 rows, 10 steps, step masks on), in
     the launch configuration of `bench.py --workload wide512`: invariants on every row on
@@ -190,6 +221,8 @@ def test_full_size_sampled(prec, tmp_path):
         assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.995
         assert np.abs(lo - qlo).max() <= 1e-3
         assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+    elif prec == "mxfp4":
+        check_mx_rows((lo, ag, ms), params, X[idx], "mxfp4 full size sampled")
     else:
         qlo, qag, qms = oracle.forward(params, X[idx], weights="e4m3", acts="bf16")
         _say(prec, "vs rounded: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
@@ -200,7 +233,7 @@ def test_full_size_sampled(prec, tmp_path):
         assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "mxfp4"])
 def test_rows_independent_optional_masks_empty(prec, tmp_path):
     _say(f"case wide rows independent {prec}")
     params, m = load(WIDE, 1005, prec, tmp_path)
@@ -222,9 +255,10 @@ def test_rows_independent_optional_masks_empty(prec, tmp_path):
     assert nomask[2] is None and empty[0].shape == (0, 2)
 
 
-@pytest.mark.parametrize("prec", ["fp8", "int8", "mxfp8", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp8", "int8", "mxfp8", "mxfp6"])
 def test_other_formats_wide_are_refused(prec, tmp_path):
-    """Formats without a split-feature kernel (coded GEMM inputs, MX blocks) are refused."""
+    """Formats without a split-feature kernel (row-coded GEMM inputs, the 8- and 6-bit MX
+    forms) are refused."""
     path = str(tmp_path / "w.tnw")
     synth.write_weights(synth.make_params(WIDE, 1005), path)
     with pytest.raises(tb.TabNetError) as e:
