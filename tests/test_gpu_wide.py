@@ -10,6 +10,7 @@ weights with their channel scales, bf16-rounded inputs) logits 2e-3, aggregate L
 and step L1 2e-2 per row (the format alone moves a step mask by up to 0.12 in L1 on the
 512-feature model, so these gates are set against the rounded operands).  MXFP4: the
 register kernel's row-by-row gates against FP64 on MX operands (check_mx_rows)."""
+import dataclasses
 import os
 
 import numpy as np
@@ -181,6 +182,42 @@ def test_random_wide_configurations(k, tmp_path):
          "step L1", np.abs(ms - qms).sum(-1).max())
     assert np.abs(lo - qlo).max() <= 1e-3
     assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_random_wide_mxfp4(k, tmp_path):
+    """MXFP4 on seeded random models of the split-feature family with n_d = 64, so that the
+    attention half starts a tile as MX blocks need: D = 497..512 leaves the first layer's
+    last MX block partial for every D but 512 (k = 0 takes D = 497, a last block of 17
+    positions).  Per-row gates against FP64 on MX operands as for the 512-feature model;
+    the masks sum to one.  The same model with n_d = 72 (an attention half that neither
+    starts a tile nor fits the tile pair it starts in) is refused."""
+    cfg, B = random_wide(k)
+    N = cfg.n_d + cfg.n_a
+    cfg = dataclasses.replace(cfg, D=497 if k == 0 else cfg.D, n_d=64, n_a=N - 64)
+    B = max(B, 64)
+    X = synth.make_normal_inputs(B, cfg.D, 9600 + k)
+    _say(f"case wide random mxfp4 {k}: {cfg} B={B}")
+    params, m = load(cfg, 9100 + k, "mxfp4", tmp_path)
+    with m:
+        lo, ag, ms = run(m, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="mxfp4", acts="mxfp4")
+    step = np.abs(ms - qms).sum(-1).max(0)
+    agg = np.abs(ag - qag).sum(-1)
+    logit = np.abs(lo - qlo).max(1)
+    _say(k, "mxfp4 vs mxfp4-operand fp64: step L1 max", step.max(), "agg L1 max", agg.max(), "logits max",
+         logit.max(), "rows moved", float((step > 1e-5).mean()))
+    assert np.isfinite(lo).all() and np.isfinite(ag).all() and np.isfinite(ms).all()
+    assert (step <= 1e-5).mean() >= 0.9 and (logit <= 1e-5).mean() >= 0.9
+    assert step.max() <= 0.4 and agg.max() <= 0.2 and logit.max() <= 2e-2
+    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=2e-5)
+    np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
+    bad = dataclasses.replace(cfg, n_d=72, n_a=N - 72)
+    path = str(tmp_path / "bad.tnw")
+    synth.write_weights(synth.make_params(bad, 1), path)
+    with pytest.raises(tb.TabNetError) as ei:
+        tb.Model(path, "mxfp4")
+    assert ei.value.status == tb.E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "mxfp4"])
