@@ -128,7 +128,9 @@ typedef struct tabnet_handle tabnet_handle;
  * tiles, so a model whose attention half neither starts a tile (n_d % 16 == 0) nor fits
  * the tile pair it starts in (n_d % 16 + n_a <= 32) is TABNET_E_UNSUPPORTED in these
  * formats.  Non-finite behaviour as TABNET_INT8.  The split-feature kernel (the 512-feature
- * shape) has a TABNET_MXFP4 entry; the 8- and 6-bit MX forms are TABNET_E_UNSUPPORTED there.
+ * shape) has entries for all five MX forms; in the two 8-bit forms its weight slices leave
+ * LDS for a final map of n_out x n_d <= 508 floats only (7 outputs at n_d = 64), and a
+ * larger model is TABNET_E_UNSUPPORTED there.
  */
 tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_handle** out);
 

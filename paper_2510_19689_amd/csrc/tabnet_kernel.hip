@@ -1990,7 +1990,11 @@ static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) T
                                        TABNET_WIDE_SHAPE(0, 32, 8, 4, 4, 2)
                                            TABNET_WIDE_SHAPE(1, 32, 8, 4, 4, 2)
                                                TABNET_WIDE_SHAPE(9, 32, 8, 4, 4, 2)
-                                                   TABNET_WIDE_SHAPE(5, 32, 8, 4, 4, 2)};
+                                                   TABNET_WIDE_SHAPE(5, 32, 8, 4, 4, 2)
+                                                       TABNET_WIDE_SHAPE(4, 32, 8, 4, 4, 2)
+                                                           TABNET_WIDE_SHAPE(7, 32, 8, 4, 4, 2)
+                                                               TABNET_WIDE_SHAPE(6, 32, 8, 4, 4, 2)
+                                                                   TABNET_WIDE_SHAPE(8, 32, 8, 4, 4, 2)};
 #endif
 
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);

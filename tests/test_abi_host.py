@@ -267,6 +267,55 @@ def test_200_feature_tiling_falls_back_to_four_waves(L, prec, n_out, W):
     assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W), (prec, n_out)
 
 
+def expected_wide_packing(cfg, prec, W=4):
+    """Packed bytes and chunk count of a model on the split-feature kernel (W waves per
+    16-row group).  A feature-transformer layer is cut into K slices of sk k-blocks, sk the
+    largest count whose NT x 2 fragments fit in 32 KiB (at least one); a slice holds the
+    value then gate fragments of every output tile over its k-blocks, and the layer's last
+    slice adds 2 x 16 shifts per tile (and 2 x 16 channel scales with FP8 weights).  An
+    attentive layer is cut into tpw / tpc chunks of W x tpc feature tiles: tpw = the tiles
+    per wave (ceil(DT / W) rounded up to even), tpc the largest divisor of tpw whose chunk
+    fits in 32 KiB + NT x 128 bytes; a tile is its fragments over the attention half and 16
+    shifts (+ 16 scales).  Every layer starts 256-byte aligned.  Per forward the chunks run
+    pass 0, then per step the attentive chunks and the pass."""
+    cdiv = _cdiv
+    DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
+    per = {0: 1, 1: 2, 9: 4}.get(prec, 8)
+    kbb = {4: 2304, 7: 2304, 5: 1280, 6: 1792, 8: 1792}.get(prec, 1024)
+    ex = 2 if prec == 9 else 1
+    sk = max(1, 32 * 1024 // (2 * NT * kbb))
+    att_unit = cdiv(NT - KA0, per) * kbb + 64 * ex
+    tpw = (cdiv(DT, W) + 1) // 2 * 2
+    tpc = tpw
+    while tpc > 1 and (W * tpc * att_unit > 32 * 1024 + NT * 128 or tpw % tpc):
+        tpc -= 1
+    sh_k, ind_k = synth.layer_in_dims(cfg)
+    nbytes = 0
+
+    def ft_layer(K):
+        KB = cdiv(cdiv(K, 16), per)
+        return cdiv(NT * 2 * KB * kbb + NT * 128 * ex, 256) * 256, cdiv(KB, sk)
+    for K in sh_k + ind_k * (cfg.n_steps + 1):
+        nbytes += ft_layer(K)[0]
+    nbytes += cfg.n_steps * cdiv((tpw // tpc) * W * tpc * att_unit, 256) * 256
+    pass_chunks = [sum(ft_layer(K)[1] for K in sh_k + ind_k)]
+    nch = (cfg.n_steps + 1) * pass_chunks[0] + cfg.n_steps * (tpw // tpc)
+    return nbytes, nch
+
+
+def test_wide_packed_sizes(L):
+    """The 512-feature model packs in the split-feature layout (expected_wide_packing) in
+    FP32, BF16, FP8 weights and the five MX forms; FP8 on both operands and INT8 have no
+    split-feature kernel and are refused."""
+    cfg = synth.WORKLOADS["wide512"]["cfg"]
+    for prec in (0, 1, 9, 4, 5, 6, 7, 8):
+        assert packed_sizes(L, cfg, prec) == expected_wide_packing(cfg, prec), prec
+    raw = synth.to_bytes(synth.make_params(cfg, 1))
+    wb, nch = ctypes.c_int64(), ctypes.c_int64()
+    for prec in (2, 3):
+        assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
+
+
 def test_mask_stats_workspace_and_argument_checks(L):
     # workspace: 2 D doubles per block of rows; a block is a multiple of 16 x (1024 // D)
     # rows (16 row loads in flight per thread) and there are at most 1024 blocks

@@ -394,9 +394,9 @@ def test_mx_parity(tmp_path, name, B, fmt):
 
 
 @pytest.mark.parametrize("fmt", MX_FORMATS)
-def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
-    """A row's outputs do not depend on its sub-batch; the 512-feature model loads in MXFP4
-    (split-feature kernel) and is refused in the 8- and 6-bit MX forms."""
+def test_mx_rows_independent_and_wide_loads(tmp_path, fmt):
+    """A row's outputs do not depend on its sub-batch; the 512-feature model loads in every
+    MX form (split-feature kernel)."""
     params, X = synth.workload("adult108", rows=300)
     _say(f"case {fmt} row independence")
     with load(params, tmp_path, fmt) as m:
@@ -409,13 +409,8 @@ def test_mx_rows_independent_and_unsupported_wide(tmp_path, fmt):
     cfg = synth.WORKLOADS["wide512"]["cfg"]
     path = str(tmp_path / "w.tnw")
     synth.write_weights(synth.make_params(cfg, 3), path)
-    if fmt == "mxfp4":
-        with tb.Model(path, fmt) as m:
-            assert m.config.D == 512
-        return
-    with pytest.raises(tb.TabNetError) as ei:
-        tb.Model(path, fmt)
-    assert ei.value.status == tb.E_UNSUPPORTED
+    with tb.Model(path, fmt) as m:
+        assert m.config.D == 512
 
 
 # per-row gates of each scaled format against FP64 on its own operands (see the tests above)

@@ -8,8 +8,8 @@ and argmax 99.9 % against FP64; against an FP64 forward on the same bf16-rounded
 BF16 inputs: logits 2e-2 and argmax against FP64; against FP64 on the same operands (E4M3
 weights with their channel scales, bf16-rounded inputs) logits 2e-3, aggregate L1 1.5e-2
 and step L1 2e-2 per row (the format alone moves a step mask by up to 0.12 in L1 on the
-512-feature model, so these gates are set against the rounded operands).  MXFP4: the
-register kernel's row-by-row gates against FP64 on MX operands (check_mx_rows)."""
+512-feature model, so these gates are set against the rounded operands).  The five MX
+forms: the register kernel's row-by-row gates against FP64 on MX operands (check_mx_rows)."""
 import dataclasses
 import os
 
@@ -111,34 +111,77 @@ def test_fp8_weights_matches_oracle(B, tmp_path):
     assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
 
 
-def check_mx_rows(got, params, X, tag):
-    """MXFP4 against FP64 on the same MX operands, row by row (the gates of the register
-    kernel's MXFP4 path: 90% of rows within 1e-5 in step-mask L1 and logits, every row within
-    0.4 step L1, 0.2 aggregate L1 and 2e-2 in the logits), and against plain FP64 (logits
-    6e-2, argmax)."""
+# Gates of the MX forms on the split-feature kernel: against FP64 on the same MX operands
+# row by row, those of the register kernel's MX paths (worst row: step L1, aggregate L1,
+# logits; typical: share of rows within a bound in step L1 and logits), and against plain
+# FP64 the logits a quarter above each format's own error on the 512-feature model (oracle
+# on MX operands against plain FP64, the larger over the 300 rows of the small-batch tests
+# and the 256 sampled rows of the full batch: 1.27e-2 MXFP8, 3.28e-2 E5M2, 1.25e-2 MXFP6,
+# 3.48e-2 E3M2, 3.68e-2 MXFP4; argmax unchanged).  The instruction sums
+# exactly in FP32 only in the E2M1 and E2M3 forms; the E4M3, E5M2 and E3M2 forms are off
+# at the 1e-6 level, which over this model's 8-10 steps moves the typical row by 1e-5 or
+# more, so those forms take the median row within 1e-4 (on a random 8-step model E3M2 left
+# 25% of rows above 1e-5 at a worst step L1 of 3.6e-5).
+WIDE_MX = {"mxfp8": dict(worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4), fp64=1.6e-2),
+           "mxfp8_e5m2": dict(worst=(0.2, 0.1, 1e-2), typical=(0.5, 1e-4), fp64=4.1e-2),
+           "mxfp6": dict(worst=(0.1, 0.05, 5e-3), typical=(0.9, 1e-5), fp64=1.6e-2),
+           "mxfp6_e3m2": dict(worst=(0.2, 0.1, 1e-2), typical=(0.5, 1e-4), fp64=4.4e-2),
+           "mxfp4": dict(worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5), fp64=6e-2)}
+
+
+def check_mx_rows(got, params, X, tag, fmt, plain=True):
+    """An MX form against FP64 on the same MX operands, row by row, and (plain) against
+    plain FP64 (logits, argmax on 99% of rows), with the gates of WIDE_MX; the masks sum to
+    one."""
+    gate = WIDE_MX[fmt]
     lo, ag, ms = got
-    rlo, rag, rms = oracle.forward(params, X)
-    qlo, qag, qms = oracle.forward(params, X, weights="mxfp4", acts="mxfp4")
+    qlo, qag, qms = oracle.forward(params, X, weights=fmt, acts=fmt)
     step = np.abs(ms - qms).sum(-1).max(0)
     agg = np.abs(ag - qag).sum(-1)
     logit = np.abs(lo - qlo).max(1)
-    _say(tag, "vs mxfp4-operand fp64: step L1 p50/max", np.median(step), step.max(), "agg L1 max", agg.max(),
-         "logits max", logit.max(), "rows moved", float((step > 1e-5).mean()), "| vs fp64 logits",
-         np.abs(lo - rlo).max())
-    assert np.isfinite(lo).all() and np.isfinite(ag).all()
-    assert (step <= 1e-5).mean() >= 0.9 and (logit <= 1e-5).mean() >= 0.9
-    assert step.max() <= 0.4 and agg.max() <= 0.2 and logit.max() <= 2e-2
-    assert np.abs(lo - rlo).max() <= 6e-2 and (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.99
+    frac, bound = gate["typical"]
+    _say(tag, f"vs {fmt}-operand fp64: step L1 p50/max", np.median(step), step.max(), "agg L1 max", agg.max(),
+         "logits max", logit.max(), f"rows within {bound}", float((step <= bound).mean()))
+    assert np.isfinite(lo).all() and np.isfinite(ag).all() and np.isfinite(ms).all()
+    assert (step <= bound).mean() >= frac and (logit <= bound).mean() >= frac
+    w = gate["worst"]
+    assert step.max() <= w[0] and agg.max() <= w[1] and logit.max() <= w[2]
+    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=2e-5)
+    np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
+    if plain:
+        rlo = oracle.forward(params, X)[0]
+        _say(tag, "vs fp64 logits", np.abs(lo - rlo).max())
+        assert np.abs(lo - rlo).max() <= gate["fp64"] and (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.99
 
 
+@pytest.mark.parametrize("fmt", list(WIDE_MX))
 @pytest.mark.parametrize("B", [33, 300])
-def test_mxfp4_matches_oracle(B, tmp_path):
-    _say(f"case wide mxfp4 B={B}")
-    params, m = load(WIDE, 1005, "mxfp4", tmp_path)
+def test_mx_matches_oracle(B, fmt, tmp_path):
+    _say(f"case wide {fmt} B={B}")
+    params, m = load(WIDE, 1005, fmt, tmp_path)
     X = synth.make_inputs("wide512", B, 2005)
     with m:
         got = run(m, X)
-    check_mx_rows(got, params, X, f"mxfp4 B={B}")
+    check_mx_rows(got, params, X, f"{fmt} B={B}", fmt)
+
+
+def test_mxfp8_lds_limit(tmp_path):
+    """MXFP8 k-blocks are 2,304 bytes per output tile, so a weight slice holds one k-block
+    of all 16 tiles (36,864 bytes plus the shifts) and the 512-feature model needs 162,320
+    bytes of LDS with a final map of 2 x 64 floats: 7 outputs fit, 8 (163,856 bytes) do not
+    and are refused; MXFP6 takes 8."""
+    for fmt, n_out, ok in (("mxfp8", 7, True), ("mxfp8", 8, False), ("mxfp8_e5m2", 8, False), ("mxfp6", 8, True)):
+        cfg = dataclasses.replace(WIDE, n_out=n_out)
+        path = str(tmp_path / f"{fmt}_{n_out}.tnw")
+        synth.write_weights(synth.make_params(cfg, 4), path)
+        _say(f"case wide LDS limit {fmt} n_out={n_out}")
+        if ok:
+            with tb.Model(path, fmt) as m:
+                assert m.config.n_out == n_out
+        else:
+            with pytest.raises(tb.TabNetError) as ei:
+                tb.Model(path, fmt)
+            assert ei.value.status == tb.E_UNSUPPORTED
 
 
 def random_wide(k):
@@ -184,43 +227,35 @@ def test_random_wide_configurations(k, tmp_path):
     assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
 
 
-@pytest.mark.parametrize("k", range(4))
-def test_random_wide_mxfp4(k, tmp_path):
-    """MXFP4 on seeded random models of the split-feature family with n_d = 64, so that the
-    attention half starts a tile as MX blocks need: D = 497..512 leaves the first layer's
-    last MX block partial for every D but 512 (k = 0 takes D = 497, a last block of 17
-    positions).  Per-row gates against FP64 on MX operands as for the 512-feature model;
-    the masks sum to one.  The same model with n_d = 72 (an attention half that neither
-    starts a tile nor fits the tile pair it starts in) is refused."""
-    cfg, B = random_wide(k)
+@pytest.mark.parametrize("k", range(8))
+def test_random_wide_mx(k, tmp_path):
+    """The MX forms on seeded random models of the split-feature family with n_d = 64, so
+    that the attention half starts a tile as MX blocks need (random_wide(k % 4) with n_d set
+    to 64; k < 4 in MXFP4, then MXFP8, its E5M2 form, MXFP6 and its E3M2 form): D =
+    497..512 leaves the first layer's last MX block partial for every D but 512 (k = 0 takes
+    D = 497, a last block of 17 positions).  The per-row gates of WIDE_MX against FP64 on MX
+    operands; the masks sum to one.  The same model with n_d = 72 (an attention half that
+    neither starts a tile nor fits the tile pair it starts in) is refused."""
+    fmt = "mxfp4" if k < 4 else ["mxfp8", "mxfp8_e5m2", "mxfp6", "mxfp6_e3m2"][k - 4]
+    cfg, B = random_wide(k % 4)
     N = cfg.n_d + cfg.n_a
     cfg = dataclasses.replace(cfg, D=497 if k == 0 else cfg.D, n_d=64, n_a=N - 64)
     B = max(B, 64)
     X = synth.make_normal_inputs(B, cfg.D, 9600 + k)
-    _say(f"case wide random mxfp4 {k}: {cfg} B={B}")
-    params, m = load(cfg, 9100 + k, "mxfp4", tmp_path)
+    _say(f"case wide random {fmt} {k}: {cfg} B={B}")
+    params, m = load(cfg, 9100 + k, fmt, tmp_path)
     with m:
-        lo, ag, ms = run(m, X)
-    qlo, qag, qms = oracle.forward(params, X, weights="mxfp4", acts="mxfp4")
-    step = np.abs(ms - qms).sum(-1).max(0)
-    agg = np.abs(ag - qag).sum(-1)
-    logit = np.abs(lo - qlo).max(1)
-    _say(k, "mxfp4 vs mxfp4-operand fp64: step L1 max", step.max(), "agg L1 max", agg.max(), "logits max",
-         logit.max(), "rows moved", float((step > 1e-5).mean()))
-    assert np.isfinite(lo).all() and np.isfinite(ag).all() and np.isfinite(ms).all()
-    assert (step <= 1e-5).mean() >= 0.9 and (logit <= 1e-5).mean() >= 0.9
-    assert step.max() <= 0.4 and agg.max() <= 0.2 and logit.max() <= 2e-2
-    np.testing.assert_allclose(ms.sum(-1), 1.0, atol=2e-5)
-    np.testing.assert_allclose(ag.sum(-1), 1.0, atol=2e-5)
+        got = run(m, X)
+    check_mx_rows(got, params, X, f"random {k} {fmt}", fmt, plain=False)
     bad = dataclasses.replace(cfg, n_d=72, n_a=N - 72)
     path = str(tmp_path / "bad.tnw")
     synth.write_weights(synth.make_params(bad, 1), path)
     with pytest.raises(tb.TabNetError) as ei:
-        tb.Model(path, "mxfp4")
+        tb.Model(path, fmt)
     assert ei.value.status == tb.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_MX])
 def test_full_size_sampled(prec, tmp_path):
     """The 512-feature workload at its full batch (65,536 rows, 10 steps, step masks on), in
     the launch configuration of `bench.py --workload wide512`: invariants on every row on
@@ -258,8 +293,8 @@ def test_full_size_sampled(prec, tmp_path):
         assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.995
         assert np.abs(lo - qlo).max() <= 1e-3
         assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
-    elif prec == "mxfp4":
-        check_mx_rows((lo, ag, ms), params, X[idx], "mxfp4 full size sampled")
+    elif prec in WIDE_MX:
+        check_mx_rows((lo, ag, ms), params, X[idx], f"{prec} full size sampled", prec)
     else:
         qlo, qag, qms = oracle.forward(params, X[idx], weights="e4m3", acts="bf16")
         _say(prec, "vs rounded: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
@@ -270,7 +305,7 @@ def test_full_size_sampled(prec, tmp_path):
         assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", "mxfp4"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_MX])
 def test_rows_independent_optional_masks_empty(prec, tmp_path):
     _say(f"case wide rows independent {prec}")
     params, m = load(WIDE, 1005, prec, tmp_path)
@@ -292,10 +327,10 @@ def test_rows_independent_optional_masks_empty(prec, tmp_path):
     assert nomask[2] is None and empty[0].shape == (0, 2)
 
 
-@pytest.mark.parametrize("prec", ["fp8", "int8", "mxfp8", "mxfp6"])
+@pytest.mark.parametrize("prec", ["fp8", "int8"])
 def test_other_formats_wide_are_refused(prec, tmp_path):
-    """Formats without a split-feature kernel (row-coded GEMM inputs, the 8- and 6-bit MX
-    forms) are refused."""
+    """Formats without a split-feature kernel (GEMM inputs coded with one scale per row,
+    which would need the row's maximum over every wave's features) are refused."""
     path = str(tmp_path / "w.tnw")
     synth.write_weights(synth.make_params(WIDE, 1005), path)
     with pytest.raises(tb.TabNetError) as e:
