@@ -110,9 +110,9 @@ typedef struct tabnet_handle tabnet_handle;
  * products are exact INT32 sums on the integer matrix cores, dequantised by
  * sigma_n * step before the folded shift is added; everything else stays in FP32.
  * A row that holds a non-finite value gets unspecified outputs (other rows are not
- * affected).  E4M3 and INT8 have entries for the register-resident kernel shapes only: a
- * model served by the split-feature kernel (the 512-feature shape) is TABNET_E_UNSUPPORTED
- * in these formats.
+ * affected).  Both run on every compiled shape, the split-feature kernel (the 512-feature
+ * shape) included: there every wave reads the whole GEMM input from LDS and takes the
+ * row's scale itself.
  *
  * TABNET_MXFP8 / TABNET_MXFP8_E5M2 / TABNET_MXFP6 / TABNET_MXFP6_E3M2 / TABNET_MXFP4 put
  * both operands of every GEMM in an OCP microscaling format: along K, blocks of 32 values

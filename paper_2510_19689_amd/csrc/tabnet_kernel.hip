@@ -551,6 +551,44 @@ __device__ __forceinline__ f4 mma_kblock_mx(const unsigned char* f, const BOp<PR
   return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bb, acc, FMT, FMT, 0, sa, 0, (int)b.sc[0][kb]);
 }
 
+// One k-block (four K tiles) of a GEMM with row-coded inputs for one output tile: `f`
+// points at the k-block's 1 KiB fragment of weight codes, `kb` selects the B operand's
+// tiles.  E4M3: two 16x16x32 FP8 MFMAs (bytes 0-7 and 8-15 of each lane).  INT8: one
+// 16x16x64 MFMA whose INT32 sums are carried in the bits of `acc`.
+template <int PREC, int KT>
+__device__ __forceinline__ f4 mma_kblock_rc(const unsigned char* f, const BOp<PREC, KT, 1>& b, int kb, f4 acc,
+                                            int lane) {
+  const i4 a = *reinterpret_cast<const i4*>(f + lane * 16);
+  if constexpr (PREC == 3) {
+    uint32_t q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * kb + j;
+      q[j] = t < KT ? b.v[0][t < KT ? t : 0] : 0u;
+    }
+    return __builtin_bit_cast(f4, __builtin_amdgcn_mfma_i32_16x16x64_i8(a, __builtin_bit_cast(i4, q),
+                                                                         __builtin_bit_cast(i4, acc), 0, 0, 0));
+  } else {
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      const int t0 = 4 * kb + 2 * hf, t1 = t0 + 1;
+      if (t0 < KT) {
+        const long ah = (long)(((uint64_t)(uint32_t)a[2 * hf + 1] << 32) | (uint32_t)a[2 * hf]);
+        const uint32_t lo = b.v[0][t0 < KT ? t0 : 0];
+        const uint32_t hi = t1 < KT ? b.v[0][t1 < KT ? t1 : 0] : 0u;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ah, (long)(((uint64_t)hi << 32) | lo), acc, 0, 0, 0);
+      }
+    }
+    return acc;
+  }
+}
+
+// INT32 sums held in the bits of an FP32 accumulator, as FP32 values.
+__device__ __forceinline__ f4 i32_sums(f4 acc) {
+  const i4 q = __builtin_bit_cast(i4, acc);
+  return f4{(float)q[0], (float)q[1], (float)q[2], (float)q[3]};
+}
+
 // Fill a GEMM's B operand from src(rb, t, i), the input of row block rb at the lane's
 // feature 16 t + 4 g + i.
 template <int PREC, int KT, int R, class F>
@@ -1411,7 +1449,7 @@ struct WideGeom {
   static constexpr int OPW = NT / W;              // output tile pairs per wave
   // u in LDS: FP32 tiles (FP32, and MX, whose waves code every block of the row themselves)
   // or BF16 k-blocks
-  static constexpr int UKB = PREC == 0 || is_mx(PREC) ? DTP : DTP / 2;
+  static constexpr int UKB = PREC == 0 || is_mx(PREC) || row_coded(PREC) ? DTP : DTP / 2;
   static constexpr int UBYTES = UKB * kFrag;
 };
 
@@ -1450,9 +1488,10 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
     av[p] = f4{0.f, 0.f, 0.f, 0.f};
     ag[p] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  // MX: every wave codes the whole layer input (FP32 tiles in LDS) into OCP blocks itself
+  // MX and the row-coded formats: every wave codes the whole layer input (FP32 tiles in
+  // LDS) itself, into OCP blocks or with the row's scale (the maximum over all of K)
   BOp<PREC, KT, 1> bm;
-  if constexpr (is_mx(PREC))
+  if constexpr (is_mx(PREC) || row_coded(PREC))
     build_b(bm, [&](int, int t, int i) { return reinterpret_cast<const float*>(src + ((size_t)t * 64 + lane) * 16)[i]; });
   for (int kb0 = 0; kb0 < KB; kb0 += sk) {
     const int nkb = KB - kb0 < sk ? KB - kb0 : sk;
@@ -1467,7 +1506,7 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
         const int k2 = 2 * (kb0 + q);
         load_kblock<1, SRC_F32>(src, k2, KT, lane, bf, bb);
         if (k2 + 1 < kblocks(1, KT)) load_kblock<1, SRC_F32>(src, k2 + 1, KT, lane, bf, bb2);
-      } else if constexpr (!is_mx(PREC)) {
+      } else if constexpr (!is_mx(PREC) && !row_coded(PREC)) {
         load_kblock<PREC, SRC_F32>(src, kb0 + q, KT, lane, bf, bb);
       }
 #pragma unroll
@@ -1478,6 +1517,9 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
         if constexpr (is_mx(PREC)) {
           av[p] = mma_kblock_mx<PREC, KT>(fv - lane * 16, bm, kb0 + q, av[p], lane);
           ag[p] = mma_kblock_mx<PREC, KT>(fg - lane * 16, bm, kb0 + q, ag[p], lane);
+        } else if constexpr (row_coded(PREC)) {
+          av[p] = mma_kblock_rc<PREC, KT>(fv - lane * 16, bm, kb0 + q, av[p], lane);
+          ag[p] = mma_kblock_rc<PREC, KT>(fg - lane * 16, bm, kb0 + q, ag[p], lane);
         } else if constexpr (is_fp8w(PREC)) {
           const i4 a = *reinterpret_cast<const i4*>(fv);
           const i4 c = *reinterpret_cast<const i4*>(fg);
@@ -1507,14 +1549,27 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
         const int pr = wave * OPW + p;
         const f4 sv = *reinterpret_cast<const f4*>(sft + pr * 32 + 4 * g);
         const f4 sg = *reinterpret_cast<const f4*>(sft + pr * 32 + 16 + 4 * g);
-        if constexpr (is_fp8w(PREC)) {
-          // channel scales after all shifts; the gate's scale and shift carry -log2(e)
-          const f4 cv = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 4 * g);
-          const f4 cg = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 16 + 4 * g);
+        if constexpr (has_channel_scales(PREC)) {
+          // channel scales after all shifts; the gate's scale and shift carry -log2(e); the
+          // row-coded formats scale by (channel scale) x (row scale)
+          f4 cv = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 4 * g);
+          f4 cg = *reinterpret_cast<const f4*>(sft + NT * 32 + pr * 32 + 16 + 4 * g);
+          f4 qv = av[p], qg = ag[p];
+          if constexpr (PREC == 3) {
+            qv = i32_sums(qv);
+            qg = i32_sums(qg);
+          }
+          if constexpr (row_coded(PREC)) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              cv[i] *= bm.rscale(0);
+              cg[i] *= bm.rscale(0);
+            }
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float v = __builtin_fmaf(av[p][i], cv[i], sv[i]);
-            const float sgm = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(__builtin_fmaf(ag[p][i], cg[i], sg[i])));
+            const float v = __builtin_fmaf(qv[i], cv[i], sv[i]);
+            const float sgm = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(__builtin_fmaf(qg[i], cg[i], sg[i])));
             h[p][i] = first ? v * sgm : __builtin_fmaf(v, sgm, h[p][i]) * kSqrtHalf;
           }
         } else {
@@ -1540,7 +1595,7 @@ __device__ __forceinline__ void glu_layer_wide(WS& ws, const unsigned char* src,
 template <int PREC, int TPW>
 __device__ __forceinline__ void publish_u(unsigned char* u_s, const float (&m)[TPW][4], const float (&x)[TPW][4],
                                           int wave, int lane) {
-  if constexpr (PREC == 0 || is_mx(PREC)) {
+  if constexpr (PREC == 0 || is_mx(PREC) || row_coded(PREC)) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
       *reinterpret_cast<f4*>(u_s + ((size_t)(wave * TPW + t) * 64 + lane) * 16) =
@@ -1683,9 +1738,11 @@ tabnet_wide_kernel(FwdArgs A) {
       constexpr int KB2 = kblocks(1, KTA);            // BF16 k-blocks of the input
       constexpr int FBA = kbytes(PREC);
       f4 bf[PREC == 0 ? KTA : 1];
-      s8 bb[PREC == 0 || is_mx(PREC) ? 1 : KB2];
-      BOp<PREC, KTA, 1> bma;   // MX: the attention half a = h[n_d, n_d + n_a) in OCP blocks
-      if constexpr (is_mx(PREC)) {
+      s8 bb[PREC == 0 || is_mx(PREC) || row_coded(PREC) ? 1 : KB2];
+      // MX and the row-coded formats: the attention half a = h[n_d, n_d + n_a) in OCP
+      // blocks, or coded with the scale of its own channels
+      BOp<PREC, KTA, 1> bma;
+      if constexpr (is_mx(PREC) || row_coded(PREC)) {
         const int n_att_end = n_d + A.n_a;
         build_b(bma, [&](int, int t, int i) {
           const int ch = 16 * (KA0 + t) + 4 * g + i;
@@ -1719,6 +1776,14 @@ tabnet_wide_kernel(FwdArgs A) {
           if constexpr (is_mx(PREC)) {
 #pragma unroll
             for (int kb = 0; kb < KBA; ++kb) z = mma_kblock_mx<PREC, KTA>(unit + kb * FBA, bma, kb, z, lane);
+          } else if constexpr (row_coded(PREC)) {
+            f4 qa = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KBA; ++kb) qa = mma_kblock_rc<PREC, KTA>(unit + kb * kFrag, bma, kb, qa, lane);
+            if constexpr (PREC == 3) qa = i32_sums(qa);
+            const f4 cs = *reinterpret_cast<const f4*>(unit + KBA * kFrag + 64 + 16 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[i] = __builtin_fmaf(qa[i], cs[i] * bma.rscale(0), z[i]);
           } else if constexpr (is_fp8w(PREC)) {
             f4 a8 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1994,7 +2059,9 @@ static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) T
                                                        TABNET_WIDE_SHAPE(4, 32, 8, 4, 4, 2)
                                                            TABNET_WIDE_SHAPE(7, 32, 8, 4, 4, 2)
                                                                TABNET_WIDE_SHAPE(6, 32, 8, 4, 4, 2)
-                                                                   TABNET_WIDE_SHAPE(8, 32, 8, 4, 4, 2)};
+                                                                   TABNET_WIDE_SHAPE(8, 32, 8, 4, 4, 2)
+                                                                       TABNET_WIDE_SHAPE(2, 32, 8, 4, 4, 2)
+                                                                           TABNET_WIDE_SHAPE(3, 32, 8, 4, 4, 2)};
 #endif
 
 size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, int tab_lds_len);
@@ -2039,7 +2106,7 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
     // and start areas; the final map and the open-row flags
     const int wf = k->plan.W;
     const int dtp = wide_tpw(k->DT, wf) * wf;
-    const size_t ub = (size_t)(k->prec == 0 || is_mx(k->prec) ? dtp : dtp / 2) * kFrag;
+    const size_t ub = (size_t)(k->prec == 0 || is_mx(k->prec) || row_coded(k->prec) ? dtp : dtp / 2) * kFrag;
     const size_t group = ub + (size_t)k->NT * kFrag + (size_t)wf * 16 * 8 * 4;
     return 2 * (size_t)k->plan.buf + (size_t)k->R * group + (size_t)n_out * n_d * 4 + 2 * (size_t)k->R * 4;
   }

@@ -521,15 +521,18 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   const int N = c.n_d + c.n_a;
   std::vector<double> Wf, bf;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
-  // K tiles per k-block: FP32 one, BF16 two, E4M3 weights four (widened in the kernel), MX
-  // eight
-  const bool w8 = precision == TABNET_FP8_WEIGHTS;
+  // K tiles per k-block: FP32 one, BF16 two, E4M3 and INT8 four (E4M3 weights with BF16
+  // inputs are widened in the kernel), MX eight
+  const bool w8 = precision == TABNET_FP8_WEIGHTS || precision == TABNET_FP8_E4M3;   // E4M3 weight codes
+  const bool i8 = precision == TABNET_INT8;
+  const bool cs = w8 || i8;   // one scale per output channel
   const int kbn = ktiles_per_block(precision);
   std::vector<double> sc;
   std::vector<std::vector<ChunkRec>> ft_chunks, att_chunks;
   for (const LayerRaw* L : ft) {
     fold_layer(*L, c.bn_eps, &Wf, &bf);
     if (w8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
+    if (i8) quantize_rows_int8(&Wf, &bf, L->rows, L->cols, N, &sc);
     const int KT = (L->cols + 15) / 16;
     const int K = L->cols;
     const int KB = (KT + kbn - 1) / kbn;
@@ -551,7 +554,7 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
           emit_vals(bf, nv, 16 * pr, 0.f, &out->wts);
           emit_vals(bf, nv, N + 16 * pr, 0.f, &out->wts);
         }
-      if (kb1 == KB && w8)   // then the channel scales, in the same order
+      if (kb1 == KB && cs)   // then the channel scales, in the same order
         for (int pr = 0; pr < sh.NT; ++pr) {
           const int nv = std::min(16, N - 16 * pr);
           emit_vals(sc, nv, 16 * pr, 1.f, &out->wts);
@@ -565,6 +568,7 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   for (const auto& L : m.att) {
     fold_layer(L, c.bn_eps, &Wf, &bf);
     if (w8) quantize_rows_e4m3(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
+    if (i8) quantize_rows_int8(&Wf, &bf, L.rows, L.cols, L.rows, &sc);
     align();
     out->att_off.push_back((int64_t)out->wts.size());
     std::vector<ChunkRec> chunks;
@@ -579,7 +583,7 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
               [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
               &out->wts);
           emit_vals(bf, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 0.f, &out->wts);
-          if (w8) emit_vals(sc, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 1.f, &out->wts);
+          if (cs) emit_vals(sc, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 1.f, &out->wts);
         }
       chunks.push_back(ChunkRec{at, (int32_t)((int64_t)out->wts.size() - at), 0});
     }

@@ -272,7 +272,8 @@ def expected_wide_packing(cfg, prec, W=4):
     16-row group).  A feature-transformer layer is cut into K slices of sk k-blocks, sk the
     largest count whose NT x 2 fragments fit in 32 KiB (at least one); a slice holds the
     value then gate fragments of every output tile over its k-blocks, and the layer's last
-    slice adds 2 x 16 shifts per tile (and 2 x 16 channel scales with FP8 weights).  An
+    slice adds 2 x 16 shifts per tile (and 2 x 16 channel scales in the E4M3 and INT8
+    formats).  An
     attentive layer is cut into tpw / tpc chunks of W x tpc feature tiles: tpw = the tiles
     per wave (ceil(DT / W) rounded up to even), tpc the largest divisor of tpw whose chunk
     fits in 32 KiB + NT x 128 bytes; a tile is its fragments over the attention half and 16
@@ -280,9 +281,9 @@ def expected_wide_packing(cfg, prec, W=4):
     pass 0, then per step the attentive chunks and the pass."""
     cdiv = _cdiv
     DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
-    per = {0: 1, 1: 2, 9: 4}.get(prec, 8)
+    per = {0: 1, 1: 2, 2: 4, 3: 4, 9: 4}.get(prec, 8)
     kbb = {4: 2304, 7: 2304, 5: 1280, 6: 1792, 8: 1792}.get(prec, 1024)
-    ex = 2 if prec == 9 else 1
+    ex = 2 if prec in (2, 3, 9) else 1
     sk = max(1, 32 * 1024 // (2 * NT * kbb))
     att_unit = cdiv(NT - KA0, per) * kbb + 64 * ex
     tpw = (cdiv(DT, W) + 1) // 2 * 2
@@ -305,15 +306,10 @@ def expected_wide_packing(cfg, prec, W=4):
 
 def test_wide_packed_sizes(L):
     """The 512-feature model packs in the split-feature layout (expected_wide_packing) in
-    FP32, BF16, FP8 weights and the five MX forms; FP8 on both operands and INT8 have no
-    split-feature kernel and are refused."""
+    every precision."""
     cfg = synth.WORKLOADS["wide512"]["cfg"]
-    for prec in (0, 1, 9, 4, 5, 6, 7, 8):
+    for prec in range(10):
         assert packed_sizes(L, cfg, prec) == expected_wide_packing(cfg, prec), prec
-    raw = synth.to_bytes(synth.make_params(cfg, 1))
-    wb, nch = ctypes.c_int64(), ctypes.c_int64()
-    for prec in (2, 3):
-        assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
 
 
 def test_mask_stats_workspace_and_argument_checks(L):

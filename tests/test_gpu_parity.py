@@ -339,15 +339,15 @@ def test_int8_parity(tmp_path, name, B):
     assert e["argmax"] >= 0.995, e
 
 
-def test_int8_unsupported_shape_and_round_trip(tmp_path):
-    """INT8 has no split-feature entry: the 512-feature model is refused at load."""
+def test_int8_wide_loads_and_round_trip(tmp_path):
+    """The 512-feature model loads in INT8 (split-feature kernel), and a handle reports
+    its precision."""
     cfg = synth.WORKLOADS["wide512"]["cfg"]
     params = synth.make_params(cfg, 3)
     path = str(tmp_path / "w.tnw")
     synth.write_weights(params, path)
-    with pytest.raises(tb.TabNetError) as ei:
-        tb.Model(path, "int8")
-    assert ei.value.status == tb.E_UNSUPPORTED
+    with tb.Model(path, "int8") as m:
+        assert tb.lib().tabnet_get_precision(m._h) == tb.INT8
     params, X = synth.workload("hr35", rows=40)
     with load(params, tmp_path, "int8") as m:
         assert tb.lib().tabnet_get_precision(m._h) == tb.INT8

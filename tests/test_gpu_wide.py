@@ -9,7 +9,8 @@ BF16 inputs: logits 2e-2 and argmax against FP64; against FP64 on the same opera
 weights with their channel scales, bf16-rounded inputs) logits 2e-3, aggregate L1 1.5e-2
 and step L1 2e-2 per row (the format alone moves a step mask by up to 0.12 in L1 on the
 512-feature model, so these gates are set against the rounded operands).  The five MX
-forms: the register kernel's row-by-row gates against FP64 on MX operands (check_mx_rows)."""
+forms, FP8 on both operands and INT8: the register kernel's row-by-row gates against FP64
+on the same coded operands (check_mx_rows)."""
 import dataclasses
 import os
 
@@ -127,20 +128,27 @@ WIDE_MX = {"mxfp8": dict(worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4), fp64=1.6e
            "mxfp6": dict(worst=(0.1, 0.05, 5e-3), typical=(0.9, 1e-5), fp64=1.6e-2),
            "mxfp6_e3m2": dict(worst=(0.2, 0.1, 1e-2), typical=(0.5, 1e-4), fp64=4.4e-2),
            "mxfp4": dict(worst=(0.4, 0.2, 2e-2), typical=(0.9, 1e-5), fp64=6e-2)}
+# The row-coded formats (GEMM inputs coded with one scale per row, weights with one per
+# output channel): the register kernel's row gates, and against plain FP64 the logits a
+# quarter above the format's own error on the same rows (9.4e-3 E4M3, 2.9e-3 INT8).
+WIDE_RC = {"fp8": dict(worst=(0.1, 0.05, 5e-3), typical=(0.5, 1e-4), fp64=1.2e-2, ops="e4m3"),
+           "int8": dict(worst=(2.5e-2, 1e-2, 2e-3), typical=(0.9, 1e-5), fp64=3.6e-3, ops="int8")}
+WIDE_Q = {**WIDE_MX, **WIDE_RC}
 
 
 def check_mx_rows(got, params, X, tag, fmt, plain=True):
-    """An MX form against FP64 on the same MX operands, row by row, and (plain) against
-    plain FP64 (logits, argmax on 99% of rows), with the gates of WIDE_MX; the masks sum to
-    one."""
-    gate = WIDE_MX[fmt]
+    """An MX or row-coded format against FP64 on the same operands, row by row, and (plain)
+    against plain FP64 (logits, argmax on 99% of rows), with the gates of WIDE_Q; the
+    masks sum to one."""
+    gate = WIDE_Q[fmt]
+    ops = gate.get("ops", fmt)
     lo, ag, ms = got
-    qlo, qag, qms = oracle.forward(params, X, weights=fmt, acts=fmt)
+    qlo, qag, qms = oracle.forward(params, X, weights=ops, acts=ops)
     step = np.abs(ms - qms).sum(-1).max(0)
     agg = np.abs(ag - qag).sum(-1)
     logit = np.abs(lo - qlo).max(1)
     frac, bound = gate["typical"]
-    _say(tag, f"vs {fmt}-operand fp64: step L1 p50/max", np.median(step), step.max(), "agg L1 max", agg.max(),
+    _say(tag, f"vs {ops}-operand fp64: step L1 p50/max", np.median(step), step.max(), "agg L1 max", agg.max(),
          "logits max", logit.max(), f"rows within {bound}", float((step <= bound).mean()))
     assert np.isfinite(lo).all() and np.isfinite(ag).all() and np.isfinite(ms).all()
     assert (step <= bound).mean() >= frac and (logit <= bound).mean() >= frac
@@ -154,7 +162,7 @@ def check_mx_rows(got, params, X, tag, fmt, plain=True):
         assert np.abs(lo - rlo).max() <= gate["fp64"] and (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.99
 
 
-@pytest.mark.parametrize("fmt", list(WIDE_MX))
+@pytest.mark.parametrize("fmt", list(WIDE_Q))
 @pytest.mark.parametrize("B", [33, 300])
 def test_mx_matches_oracle(B, fmt, tmp_path):
     _say(f"case wide {fmt} B={B}")
@@ -255,7 +263,7 @@ def test_random_wide_mx(k, tmp_path):
     assert ei.value.status == tb.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_MX])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_Q])
 def test_full_size_sampled(prec, tmp_path):
     """The 512-feature workload at its full batch (65,536 rows, 10 steps, step masks on), in
     the launch configuration of `bench.py --workload wide512`: invariants on every row on
@@ -293,7 +301,7 @@ def test_full_size_sampled(prec, tmp_path):
         assert (lo.argmax(1) == rlo.argmax(1)).mean() >= 0.995
         assert np.abs(lo - qlo).max() <= 1e-3
         assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
-    elif prec in WIDE_MX:
+    elif prec in WIDE_Q:
         check_mx_rows((lo, ag, ms), params, X[idx], f"{prec} full size sampled", prec)
     else:
         qlo, qag, qms = oracle.forward(params, X[idx], weights="e4m3", acts="bf16")
@@ -305,7 +313,7 @@ def test_full_size_sampled(prec, tmp_path):
         assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_MX])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8w", *WIDE_Q])
 def test_rows_independent_optional_masks_empty(prec, tmp_path):
     _say(f"case wide rows independent {prec}")
     params, m = load(WIDE, 1005, prec, tmp_path)
@@ -327,12 +335,18 @@ def test_rows_independent_optional_masks_empty(prec, tmp_path):
     assert nomask[2] is None and empty[0].shape == (0, 2)
 
 
-@pytest.mark.parametrize("prec", ["fp8", "int8"])
-def test_other_formats_wide_are_refused(prec, tmp_path):
-    """Formats without a split-feature kernel (GEMM inputs coded with one scale per row,
-    which would need the row's maximum over every wave's features) are refused."""
-    path = str(tmp_path / "w.tnw")
-    synth.write_weights(synth.make_params(WIDE, 1005), path)
-    with pytest.raises(tb.TabNetError) as e:
-        tb.Model(path, prec)
-    assert e.value.status == tb.E_UNSUPPORTED
+@pytest.mark.parametrize("k", range(4))
+def test_random_wide_row_coded(k, tmp_path):
+    """FP8 on both operands (even k) and INT8 (odd k) on the seeded random models of the
+    split-feature family as drawn (64 <= n_d < 80, so the attention half may start inside a
+    tile: its row scale covers its own channels only), with the gates of WIDE_RC against
+    FP64 on the same coded operands."""
+    fmt = "fp8" if k % 2 == 0 else "int8"
+    cfg, B = random_wide(k)
+    B = max(B, 64)
+    X = synth.make_normal_inputs(B, cfg.D, 9700 + k)
+    _say(f"case wide random {fmt} {k}: {cfg} B={B}")
+    params, m = load(cfg, 9200 + k, fmt, tmp_path)
+    with m:
+        got = run(m, X)
+    check_mx_rows(got, params, X, f"random {k} {fmt}", fmt, plain=False)
