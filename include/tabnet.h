@@ -88,6 +88,14 @@ typedef struct tabnet_handle tabnet_handle;
  * fields out of range, e.g. n_d < 1 or gamma < 1), TABNET_E_UNSUPPORTED (no compiled
  * kernel covers D, n_d + n_a or n_out), TABNET_E_OOM, TABNET_E_HIP.
  *
+ * Shapes.  Every precision has kernels compiled for the shape families of ceil(D / 16),
+ * ceil((n_d + n_a) / 16) and floor(n_d / 16) = (1..4, 1, 0), (4, 2, 1), (7, 4, 2),
+ * (13, 8, 4) and, on the split-feature kernel, (32, 8, 4) (D = 497..512).  Any other model
+ * with D <= 208 and n_d + n_a <= 128 runs in TABNET_FP32 and TABNET_BF16 on a generic
+ * kernel compiled for up to 4, 8 or 13 feature tiles and 1, 2, 4 or 8 hidden tiles (the
+ * padding is masked or carried as zeros; embedded rows only, so tabnet_set_embeddings
+ * refuses such a model); the other precisions refuse it.
+ *
  * TABNET_FP8_E4M3 puts both operands of every GEMM in E4M3 with one FP32 scale per
  * vector: each weight row as q = E4M3(W'_n / sigma_n) with sigma_n = max_k |W'_nk| / 448,
  * and each GEMM input row (coded in the kernel) as E4M3(u / s_r) with s_r = max_k |u_k| / 448,

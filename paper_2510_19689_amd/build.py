@@ -26,6 +26,8 @@ TEST_LIB = os.path.join(HERE, "libtabnet_test.so")
 # hooks (include/tabnet_internal.h) and the serving runtime's CPU stand-in device.
 SOURCES = [
     "tabnet_kernel.hip",
+    "tabnet_generic_fp32.hip",
+    "tabnet_generic_bf16.hip",
     "tabnet_stats.hip",
     "tabnet_pack.cpp",
     "tabnet_api.cpp",
@@ -85,13 +87,14 @@ def build(verbose: bool = False) -> str:
 
 def build_variant(defines, out: str) -> str:
     """Link a product library at `out` whose kernel source is compiled with the given
-    preprocessor definitions (the tile sweep's candidate builds); the other sources are
-    compiled as for libtabnet.so."""
+    preprocessor definitions (the tile sweep's candidate builds, which carry no generic
+    entries); the other sources are compiled as for libtabnet.so."""
+    srcs = [s for s in SOURCES if not s.startswith("tabnet_generic_")]
     with tempfile.TemporaryDirectory(prefix="tabnet_variant_") as tmp:
-        objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
-        with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = [os.path.join(tmp, s + ".o") for s in srcs]
+        with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
             list(ex.map(lambda so: _compile(so[0], so[1], defines if so[0] == "tabnet_kernel.hip" else ()),
-                        zip(SOURCES, objs)))
+                        zip(srcs, objs)))
         _link(objs, out)
     return out
 

@@ -120,7 +120,7 @@ tabnet_status tabnet_load(const char* path, int precision, int device, tabnet_ha
   if (e != hipSuccess) return fail(TABNET_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
 
   Packed pk;
-  pack_model(m, precision, *kernel_plan(k), &pk);
+  pack_model(m, precision, *kernel_plan(k), kernel_shape(k), &pk);
   tabnet_handle* h = new tabnet_handle();
   h->cfg = m.cfg;
   h->precision = precision;

@@ -16,6 +16,8 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
 hipError_t prepare_kernel(const KernelEntry* k);
 hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t stream);
 const Plan* kernel_plan(const KernelEntry* k);
+// (DT, NT, KA0) the kernel is compiled for: the model's own, or larger for a generic kernel
+Shape kernel_shape(const KernelEntry* k);
 }  // namespace tabnet
 
 struct tabnet_handle {

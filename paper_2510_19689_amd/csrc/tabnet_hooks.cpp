@@ -72,7 +72,7 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
   const KernelEntry* k = find_kernel(precision, sh.DT, sh.NT, sh.KA0, false, m.cfg.D, m.cfg.n_out, m.cfg.n_d);
   if (!k) return TABNET_E_UNSUPPORTED;
   Packed pk;
-  pack_model(m, precision, *kernel_plan(k), &pk);
+  pack_model(m, precision, *kernel_plan(k), kernel_shape(k), &pk);
   *wts_bytes = (int64_t)pk.wts.size();
   *n_chunks = (int64_t)pk.chunks.size();
   return TABNET_OK;

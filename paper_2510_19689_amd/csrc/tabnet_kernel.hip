@@ -1,6 +1,7 @@
 // Fused TabNet inference kernel for gfx950.  Layout and data flow: tabnet_kernel.hpp.
 #include <hip/hip_runtime.h>
 
+#include "tabnet_handle.hpp"
 #include "tabnet_kernel.hpp"
 
 namespace tabnet {
@@ -914,7 +915,11 @@ __device__ __forceinline__ void reduce_columns(const float (&m)[DT][4], const ui
 }
 
 // ------------------------------------------------------------------------------------
-template <int PREC, int DT, int NT, int KA0, int R, int W, bool RAW>
+// The register-resident forward.  GEN: a kernel compiled for up to DT feature tiles and NT
+// hidden tiles that serves smaller models too (the features past the model's D masked
+// like those of a partial last tile, the hidden channels past n_d + n_a carried as zeros
+// by zero weights and shifts); otherwise DT = ceil(D / 16) exactly.
+template <int PREC, int DT, int NT, int KA0, int R, int W, bool RAW, bool GEN = false>
 __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   constexpr Plan PL = make_plan(PREC, DT, NT, KA0, chunk_target(DT, R, W));
   constexpr int KTA = NT - KA0;   // K tiles of the attentive GEMM (the attention half)
@@ -970,11 +975,13 @@ __global__ void __launch_bounds__(64 * W) tabnet_forward_kernel(FwdArgs A) {
   bool live[R];
 #pragma unroll
   for (int rb = 0; rb < R; ++rb) live[rb] = 16 * rb + rl < live_rows;
-  // Is feature 16 t + 4 g + i a real column?  Only the last tile can be partial.
+  // Is feature 16 t + 4 g + i a real column?  Only the model's last tile can be partial,
+  // and (GEN) the tiles past it are padding.
+  const int dlast = GEN ? (D - 1) >> 4 : DT - 1;
   bool last_ok[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) last_ok[i] = 16 * (DT - 1) + 4 * g + i < D;
-  auto feat_ok = [&](int t, int i) { return t < DT - 1 || last_ok[i]; };
+  for (int i = 0; i < 4; ++i) last_ok[i] = 16 * dlast + 4 * g + i < D;
+  auto feat_ok = [&](int t, int i) { return GEN ? t < dlast || (t == dlast && last_ok[i]) : t < DT - 1 || last_ok[i]; };
   // this lane's features of tile t of row block rb in the staging area ([16 R rows][D])
   auto own_get = [&](int rb, int t, float (&m)[4]) {
     const float* sr = stage + (16 * rb + rl) * D + 16 * t + 4 * g;
@@ -2013,6 +2020,7 @@ struct KernelEntry {
   bool raw;                  // embeds raw rows and writes masks per raw column
   void (*fn)(FwdArgs);
   Plan plan;                 // plan.wide: split-feature kernel, 16 rows per workgroup
+  bool gen = false;          // serves models of up to 16 DT features and 16 NT hidden channels
 };
 
 #define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                                 \
@@ -2040,13 +2048,38 @@ struct KernelEntry {
 // whose raw rows do not fit beside eight staging areas.  INT8 and the 8- and 6-bit MX
 // forms, which spill far more at two waves per SIMD, take four.
 #define TABNET_SHAPE_200(P) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
+// Generic entries (FP32 and BF16, embedded rows): for a model outside the exact families,
+// the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16) with KA0 =
+// floor(n_d / 16), for D <= 208 and n_d + n_a <= 128.  They are compiled in translation
+// units of their own (tabnet_generic_*.hip) so that the build runs them in parallel.
+#define TABNET_GENERIC(P, DT, NT, KA0, W)                                                             \
+  {P, DT, NT, KA0, 1, W, false, tabnet_forward_kernel<P, DT, NT, KA0, 1, W, false, true>,            \
+   make_plan(P, DT, NT, KA0, chunk_target(DT, 1, W)), true},
+#define TABNET_GENERIC_NT(P, DT, W)                                                                   \
+  TABNET_GENERIC(P, DT, 1, 0, W) TABNET_GENERIC(P, DT, 2, 0, W) TABNET_GENERIC(P, DT, 2, 1, W)      \
+  TABNET_GENERIC(P, DT, 4, 0, W) TABNET_GENERIC(P, DT, 4, 1, W) TABNET_GENERIC(P, DT, 4, 2, W)      \
+  TABNET_GENERIC(P, DT, 4, 3, W) TABNET_GENERIC(P, DT, 8, 0, W) TABNET_GENERIC(P, DT, 8, 1, W)      \
+  TABNET_GENERIC(P, DT, 8, 2, W) TABNET_GENERIC(P, DT, 8, 3, W) TABNET_GENERIC(P, DT, 8, 4, W)      \
+  TABNET_GENERIC(P, DT, 8, 5, W) TABNET_GENERIC(P, DT, 8, 6, W) TABNET_GENERIC(P, DT, 8, 7, W)
+// eight waves per workgroup; at DT = 13 four where the LDS does not hold eight staging areas
+#define TABNET_GENERIC_SET(P)                                                                         \
+  TABNET_GENERIC_NT(P, 4, 8) TABNET_GENERIC_NT(P, 8, 8) TABNET_GENERIC_NT(P, 13, 8) TABNET_GENERIC_NT(P, 13, 4)
+
+#ifndef TABNET_GENERIC_TU
 #define TABNET_SHAPE_200_W8(P) TABNET_SHAPE(P, 13, 8, 4, 1, 8) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 
 #ifdef TABNET_TILE_SWEEP
 // A tile-sweep build (paper_2510_19689_amd/tile_sweep.py) compiles only the candidate
-// tiling it times, given as one TABNET_SHAPE or TABNET_WIDE_SHAPE entry.
+// tiling it times, given as one TABNET_SHAPE or TABNET_WIDE_SHAPE entry, and no generic
+// entries.
 static const KernelEntry kKernels[] = {TABNET_TILE_SWEEP};
+static const KernelEntry* const kGenericTables[] = {nullptr};
+static const int* const kGenericCountPtrs[] = {nullptr};
 #else
+extern const KernelEntry kGenericFp32[], kGenericBf16[];
+extern const int kGenericFp32Count, kGenericBf16Count;
+static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16};
+static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count};
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) TABNET_SHAPES(1) TABNET_SHAPE_200_W8(1)
                                        TABNET_SHAPES(2) TABNET_SHAPE_200_W8(2) TABNET_SHAPES(3) TABNET_SHAPE_200(3)
                                        TABNET_SHAPES(4) TABNET_SHAPE_200(4) TABNET_SHAPES(5) TABNET_SHAPE_200_W8(5)
@@ -2069,8 +2102,11 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
 // The forward kernel of a model: the first compiled entry of its shape whose LDS holds the
 // model (D, n_out, n_d) and whose raw-row twin (same tiling) holds it too without embedding
 // tables; else the first that holds the model; else the first entry of the shape, whose
-// LDS check then refuses the model.  With `twin`: the entry of the twin's tiling (R, W) and
-// `raw`, so that a raw-row kernel shares the weight chunking of the handle's forward kernel.
+// LDS check then refuses the model.  A shape with no exact entry takes the first generic
+// entry (FP32, BF16; embedded rows) with its KA0 and at least its DT and NT that holds the
+// model, the smallest DT and then NT first.  With `twin`: the entry of the twin's tiling
+// (R, W) and `raw`, so that a raw-row kernel shares the weight chunking of the handle's
+// forward kernel (a generic kernel has no raw-row twin).
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int D, int n_out, int n_d,
                                const KernelEntry* twin) {
   auto shape_of = [&](const KernelEntry& e, bool r) {
@@ -2092,6 +2128,19 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int 
     for (const auto& e2 : kKernels)
       if (shape_of(e2, true) && e2.R == e.R && e2.W == e.W) r = &e2;
     if (raw || !r || fits(*r)) return &e;
+  }
+  if (!first && !raw) {
+    const KernelEntry* gen_first = nullptr;
+    for (size_t ti = 0; ti < sizeof(kGenericTables) / sizeof(kGenericTables[0]); ++ti) {
+      if (!kGenericTables[ti]) continue;
+      for (int j = 0; j < *kGenericCountPtrs[ti]; ++j) {
+        const KernelEntry& e = kGenericTables[ti][j];
+        if (e.prec != prec || e.KA0 != KA0 || e.DT < DT || e.NT < NT) continue;
+        if (!gen_first) gen_first = &e;
+        if (fits(e)) return &e;
+      }
+    }
+    return gen_first;
   }
   return first_fit ? first_fit : first;
 }
@@ -2131,6 +2180,8 @@ hipError_t launch_forward(const KernelEntry* k, const FwdArgs& a, hipStream_t st
 }
 
 const Plan* kernel_plan(const KernelEntry* k) { return &k->plan; }
+Shape kernel_shape(const KernelEntry* k) { return Shape{k->DT, k->NT, k->KA0}; }
 int kernel_waves(const KernelEntry* k) { return k->W; }
+#endif  // TABNET_GENERIC_TU
 
 }  // namespace tabnet

@@ -603,9 +603,8 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
 
 }  // namespace
 
-void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out) {
+void pack_model(const ModelRaw& m, int precision, const Plan& plan, const Shape& sh, Packed* out) {
   const tabnet_config& c = m.cfg;
-  const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
   const bool fp8 = precision == TABNET_FP8_E4M3 || precision == TABNET_FP8_WEIGHTS;
   const bool i8 = precision == TABNET_INT8;
@@ -628,11 +627,17 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
     return;
   }
   // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]
-  for (const LayerRaw* L : ft) {
+  // over the kernel's tiles (a generic kernel's extra feature tiles and hidden channels are
+  // zero weights and shifts)
+  for (size_t li = 0; li < ft.size(); ++li) {
+    const LayerRaw* L = ft[li];
+    // the first layer of a pass reads the D features: the first shared layer, or without
+    // shared layers the first step layer of each pass
+    const bool reads_d = c.n_shared > 0 ? li == 0 : (li - (size_t)c.n_shared) % (size_t)c.n_indep == 0;
     fold_layer(*L, c.bn_eps, &Wf, &bf);
     if (fp8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, N, &sc);     // rows [N, 2N): the gates
     if (i8) quantize_rows_int8(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
-    const int KT = (L->cols + 15) / 16;   // the first layer of a pass reads D features, the others N
+    const int KT = reads_d ? sh.DT : sh.NT;
     const int K = L->cols;
     align();
     out->ft_off.push_back((int64_t)out->wts.size());
@@ -643,7 +648,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
             Wf, L->cols, KT, precision,
             [&](int i) { const int ch = 16 * mt + i; return ch < N ? half * N + ch : -1; },
             [&](int kin) { return kin < K ? kin : -1; }, &out->wts);
-      const int nv = std::min(16, N - 16 * mt);
+      const int nv = std::max(0, std::min(16, N - 16 * mt));
       emit_vals(bf, nv, 16 * mt, 0.f, &out->wts);
       emit_vals(bf, nv, N + 16 * mt, 0.f, &out->wts);
       if (fp8 || i8) {
@@ -667,8 +672,8 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out)
           [&](int i) { const int d = 16 * mt + i; return d < c.D ? d : -1; },
           [&](int kin) { const int ch = 16 * sh.KA0 + kin; return (ch >= c.n_d && ch < N) ? ch - c.n_d : -1; },
           &out->wts);
-      emit_vals(bf, std::min(16, c.D - 16 * mt), 16 * mt, 0.f, &out->wts);
-      if (fp8 || i8) emit_vals(sc, std::min(16, c.D - 16 * mt), 16 * mt, 1.f, &out->wts);
+      emit_vals(bf, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 0.f, &out->wts);
+      if (fp8 || i8) emit_vals(sc, std::max(0, std::min(16, c.D - 16 * mt)), 16 * mt, 1.f, &out->wts);
     }
   }
   align();

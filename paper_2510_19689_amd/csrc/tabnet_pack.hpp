@@ -75,7 +75,8 @@ struct Packed {
   std::vector<int64_t> ft_off;      // per unique feature-transformer layer
   std::vector<int64_t> att_off;     // per step
 };
-// Packs the model for `precision` in the chunk layout of `plan` (the kernel's plan).
-void pack_model(const ModelRaw& m, int precision, const Plan& plan, Packed* out);
+// Packs the model for `precision` in the chunk layout of `plan` (the kernel's plan) and
+// the kernel's tiles `sh` (the model's own shape, or larger for a generic kernel).
+void pack_model(const ModelRaw& m, int precision, const Plan& plan, const Shape& sh, Packed* out);
 
 }  // namespace tabnet

@@ -193,8 +193,11 @@ def _cdiv(a, b):
     return -(-a // b)
 
 
-def expected_packing(cfg, prec, W):
-    """Packed bytes and chunk count of a model for a kernel of W waves (see test_packed_sizes)."""
+def expected_packing(cfg, prec, W, shape=None):
+    """Packed bytes and chunk count of a model for a kernel of W waves (see test_packed_sizes),
+    compiled for the model's own (DT, NT, KA0) or for `shape` (a generic kernel: the first
+    layer of a pass then spans DT K tiles, the others NT, and the attentive GEMM DT output
+    tiles)."""
     cdiv = _cdiv
 
     def chunks(unit, n, target):
@@ -202,7 +205,7 @@ def expected_packing(cfg, prec, W):
         upc = min(upc, max(1, target // unit))
         return cdiv(n, upc)
 
-    DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
+    DT, NT, KA0 = shape or (cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16)
     sh_k, ind_k = synth.layer_in_dims(cfg)
     ks = sh_k + ind_k * (cfg.n_steps + 1)
     target = min(40960, max(8192, (160 * 1024 - W * 16 * 16 * DT * 4 - 8192) // 2 // 1024 * 1024))
@@ -211,7 +214,8 @@ def expected_packing(cfg, prec, W):
     kbb = {4: 2 * 1024 + 256, 7: 2 * 1024 + 256, 5: 1024 + 256, 6: 1536 + 256, 8: 1536 + 256}.get(prec, 1024)
     kbytes = (lambda KT: cdiv(KT, per) * kbb)   # bytes of a tile's k-blocks
     ex = 2 if prec in (2, 3, 9) else 1     # E4M3, INT8 and FP8-weight units also carry one scale per output
-    glu_unit = {k: 2 * kbytes(cdiv(k, 16)) + 128 * ex for k in set(ks)}
+    assert shape is None or cfg.D != cfg.N
+    glu_unit = {k: 2 * kbytes(DT if k == cfg.D else NT) + 128 * ex for k in set(ks)}
     att_unit = kbytes(NT - KA0) + 64 * ex
     nbytes = sum(cdiv(NT * glu_unit[k], 256) * 256 for k in ks) + cfg.n_steps * cdiv(DT * att_unit, 256) * 256
     first = chunks(2 * kbytes(DT) + 128 * ex, NT, target)
@@ -265,6 +269,33 @@ def test_200_feature_tiling_falls_back_to_four_waves(L, prec, n_out, W):
         lds_raw = 2 * buf + (8 * 16 * 200 + _cdiv(n_out * 64, 4) * 4) * 4 + 16 * 200
         assert (lds_raw <= 160 * 1024) == (W == 8)
     assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W), (prec, n_out)
+
+
+@pytest.mark.parametrize("D,n_d,n_a,shape,W", [(150, 48, 48, (13, 8, 3), 8), (100, 20, 20, (8, 4, 1), 8),
+                                               (50, 24, 24, (4, 4, 1), 8), (20, 8, 40, (4, 4, 0), 8),
+                                               (180, 70, 50, (13, 8, 4), 8)])
+def test_generic_kernel_packing(L, D, n_d, n_a, shape, W):
+    """A model outside the exact shape families runs on a generic kernel in FP32 and BF16:
+    the smallest compiled DT (4, 8 or 13) and NT (1, 2, 4 or 8) that hold its features and
+    hidden channels, with its own KA0; the weights are packed to that kernel's tiles.  The
+    other precisions and raw rows have no generic entries (refused)."""
+    cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=3, n_shared=2, n_indep=1, n_out=3, gamma=1.5)
+    for prec in (0, 1):
+        assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W, shape), (prec, shape)
+    raw = synth.to_bytes(synth.make_params(cfg, 1))
+    wb, nch = ctypes.c_int64(), ctypes.c_int64()
+    for prec in (2, 3, 4, 9):
+        assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
+
+
+def test_generic_kernel_limits(L):
+    """Past the generic range (D > 208 outside the split-feature family, or more than 128
+    hidden channels) a model is refused."""
+    wb, nch = ctypes.c_int64(), ctypes.c_int64()
+    for D, n_d, n_a in ((300, 32, 32), (100, 80, 64)):
+        cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=2, n_shared=1, n_indep=1, n_out=2, gamma=1.5)
+        raw = synth.to_bytes(synth.make_params(cfg, 1))
+        assert L.tabnet_hook_packed_sizes(raw, len(raw), 1, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
 
 
 def expected_wide_packing(cfg, prec, W=4):

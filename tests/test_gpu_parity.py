@@ -493,3 +493,62 @@ def test_scaled_formats_small_shapes(tmp_path, k, fmt):
     with load(params, tmp_path, fmt) as m:
         got = run(m, X)
     check_rows_on_rounded(got, params, X, oracle_fmt, f"{fmt} small {k}", worst=worst, typical=typical)
+
+
+# Models between the exact shape families, served by the generic kernels (FP32 and BF16,
+# compiled for up to 16 DT features and 16 NT hidden channels, DT in {4, 8, 13}, NT in
+# {1, 2, 4, 8}): named cases, then seeded random ones drawn outside FAMILIES.
+GENERIC = [dict(D=150, n_d=48, n_a=48, n_steps=4, n_shared=2, n_indep=2, n_out=2, gamma=1.3),
+           dict(D=100, n_d=20, n_a=20, n_steps=3, n_shared=1, n_indep=1, n_out=3, gamma=1.5),
+           dict(D=50, n_d=24, n_a=24, n_steps=5, n_shared=2, n_indep=0, n_out=2, gamma=1.2),
+           dict(D=20, n_d=8, n_a=40, n_steps=2, n_shared=0, n_indep=2, n_out=5, gamma=1.8),
+           dict(D=180, n_d=70, n_a=50, n_steps=6, n_shared=0, n_indep=3, n_out=4, gamma=1.6)]
+
+
+def in_family(cfg):
+    return any(d0 <= cfg.D <= d1 and N0 <= cfg.N <= N1 and nd0 <= cfg.n_d <= nd1
+               for (d0, d1), (N0, N1), (nd0, nd1) in FAMILIES)
+
+
+def random_generic(k):
+    """Seeded model k outside the exact families: D 1-208, n_d + n_a 2-128, 1-6 steps, 0-3
+    shared and 0-3 step layers (at least one), 1-8 outputs, gamma in [1, 2); 1-259 rows."""
+    rng = np.random.default_rng(5500 + k)
+    while True:
+        D = int(rng.integers(1, 209))
+        N = int(rng.integers(2, 129))
+        n_d = int(rng.integers(1, N))
+        n_sh, n_ind = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        if n_sh + n_ind == 0:
+            n_ind = 1
+        cfg = TabNetConfig(D=D, n_d=n_d, n_a=N - n_d, n_steps=int(rng.integers(1, 7)), n_shared=n_sh,
+                           n_indep=n_ind, n_out=int(rng.integers(1, 9)), gamma=float(rng.uniform(1.0, 2.0)))
+        B = int(rng.integers(1, 260))
+        if not in_family(cfg):
+            return cfg, B
+
+
+@pytest.mark.parametrize("k", range(len(GENERIC) + 8))
+def test_generic_shapes(tmp_path, k):
+    """Models outside the exact shape families run on the generic kernels: FP32 against
+    FP64 with the small models' gates (check_fp32_tight), BF16 against FP64 on bf16-rounded
+    operands (check_reduced); a row's outputs do not depend on its sub-batch."""
+    if k < len(GENERIC):
+        cfg, B = TabNetConfig(**GENERIC[k]), 300
+    else:
+        cfg, B = random_generic(k)
+    assert not in_family(cfg)
+    params = synth.make_params(cfg, 8800 + k)
+    X = synth.make_normal_inputs(B, cfg.D, seed=8900 + k)
+    _say(f"case generic shape {k}: {cfg} B={B}")
+    ref = oracle.forward(params, X)
+    with load(params, tmp_path, "fp32", "a") as m:
+        got = run(m, X)
+        check_fp32_tight(got, ref, f"generic {k} fp32", cfg)
+        lo_, hi_ = B // 3, min(B, B // 3 + 17)
+        part = run(m, X[lo_:hi_])
+        np.testing.assert_array_equal(part[0], got[0][lo_:hi_])
+        np.testing.assert_array_equal(part[1], got[1][lo_:hi_])
+        np.testing.assert_array_equal(part[2], got[2][:, lo_:hi_])
+    with load(params, tmp_path, "bf16", "b") as m:
+        check_reduced(run(m, X), params, X, "bf16", "bf16", f"generic {k} bf16")
