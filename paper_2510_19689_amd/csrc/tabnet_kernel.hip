@@ -2050,7 +2050,7 @@ struct KernelEntry {
 #define TABNET_SHAPE_200(P) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
 // Generic entries (FP32 and BF16, embedded rows): for a model outside the exact families,
 // the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16) with KA0 =
-// floor(n_d / 16), for D <= 208 and n_d + n_a <= 128.  They are compiled in translation
+// floor(n_d / 16), for D <= 512 and n_d + n_a <= 128 (register-resident up to D = 208).  They are compiled in translation
 // units of their own (tabnet_generic_*.hip) so that the build runs them in parallel.
 #define TABNET_GENERIC(P, DT, NT, KA0, W)                                                             \
   {P, DT, NT, KA0, 1, W, false, tabnet_forward_kernel<P, DT, NT, KA0, 1, W, false, true>,            \
@@ -2061,9 +2061,15 @@ struct KernelEntry {
   TABNET_GENERIC(P, DT, 4, 3, W) TABNET_GENERIC(P, DT, 8, 0, W) TABNET_GENERIC(P, DT, 8, 1, W)      \
   TABNET_GENERIC(P, DT, 8, 2, W) TABNET_GENERIC(P, DT, 8, 3, W) TABNET_GENERIC(P, DT, 8, 4, W)      \
   TABNET_GENERIC(P, DT, 8, 5, W) TABNET_GENERIC(P, DT, 8, 6, W) TABNET_GENERIC(P, DT, 8, 7, W)
+// Wider models (D <= 512) on the split-feature kernel compiled for 32 feature tiles and 8
+// hidden tiles, which masks its features by the runtime D already.
+#define TABNET_GENERIC_WIDE(P, KA0)                                                                   \
+  {P, 32, 8, KA0, 2, 8, false, tabnet_wide_kernel<P, 32, 8, KA0, 4, 2>, make_wide_plan(P, 32, 8, KA0, 4), true},
 // eight waves per workgroup; at DT = 13 four where the LDS does not hold eight staging areas
 #define TABNET_GENERIC_SET(P)                                                                         \
-  TABNET_GENERIC_NT(P, 4, 8) TABNET_GENERIC_NT(P, 8, 8) TABNET_GENERIC_NT(P, 13, 8) TABNET_GENERIC_NT(P, 13, 4)
+  TABNET_GENERIC_NT(P, 4, 8) TABNET_GENERIC_NT(P, 8, 8) TABNET_GENERIC_NT(P, 13, 8) TABNET_GENERIC_NT(P, 13, 4) \
+  TABNET_GENERIC_WIDE(P, 0) TABNET_GENERIC_WIDE(P, 1) TABNET_GENERIC_WIDE(P, 2) TABNET_GENERIC_WIDE(P, 3)         \
+  TABNET_GENERIC_WIDE(P, 4) TABNET_GENERIC_WIDE(P, 5) TABNET_GENERIC_WIDE(P, 6) TABNET_GENERIC_WIDE(P, 7)
 
 #ifndef TABNET_GENERIC_TU
 #define TABNET_SHAPE_200_W8(P) TABNET_SHAPE(P, 13, 8, 4, 1, 8) TABNET_SHAPE(P, 13, 8, 4, 1, 4)

@@ -514,10 +514,9 @@ void quantize_rows_e4m3(std::vector<double>* Wf, std::vector<double>* bf, int ro
 
 // Split-feature layout (see Plan): feature-transformer layers as K slices holding every
 // output pair, attentive layers as chunks holding tpc feature tiles of every wave.
-void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::vector<const LayerRaw*>& ft,
-               Packed* out) {
+void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const Shape& sh,
+               const std::vector<const LayerRaw*>& ft, Packed* out) {
   const tabnet_config& c = m.cfg;
-  const Shape sh = shape_of(c);
   const int N = c.n_d + c.n_a;
   std::vector<double> Wf, bf;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
@@ -529,11 +528,14 @@ void pack_wide(const ModelRaw& m, int precision, const Plan& plan, const std::ve
   const int kbn = ktiles_per_block(precision);
   std::vector<double> sc;
   std::vector<std::vector<ChunkRec>> ft_chunks, att_chunks;
-  for (const LayerRaw* L : ft) {
+  for (size_t li = 0; li < ft.size(); ++li) {
+    const LayerRaw* L = ft[li];
+    // the first layer of a pass reads the D features (over the kernel's feature tiles)
+    const bool reads_d = c.n_shared > 0 ? li == 0 : (li - (size_t)c.n_shared) % (size_t)c.n_indep == 0;
     fold_layer(*L, c.bn_eps, &Wf, &bf);
     if (w8) quantize_rows_e4m3(&Wf, &bf, L->rows, L->cols, N, &sc);   // rows [N, 2N): the gates
     if (i8) quantize_rows_int8(&Wf, &bf, L->rows, L->cols, N, &sc);
-    const int KT = (L->cols + 15) / 16;
+    const int KT = reads_d ? sh.DT : sh.NT;
     const int K = L->cols;
     const int KB = (KT + kbn - 1) / kbn;
     align();
@@ -623,7 +625,7 @@ void pack_model(const ModelRaw& m, int precision, const Plan& plan, const Shape&
   std::vector<double> Wf, bf, sc;
   auto align = [&]() { out->wts.resize(align256(out->wts.size()), 0); };
   if (plan.wide) {
-    pack_wide(m, precision, plan, ft, out);
+    pack_wide(m, precision, plan, sh, ft, out);
     return;
   }
   // GLU layers: unit mt = [value tile fragments][gate tile fragments][value shifts][gate shifts]

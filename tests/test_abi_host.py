@@ -289,16 +289,16 @@ def test_generic_kernel_packing(L, D, n_d, n_a, shape, W):
 
 
 def test_generic_kernel_limits(L):
-    """Past the generic range (D > 208 outside the split-feature family, or more than 128
-    hidden channels) a model is refused."""
+    """Past the generic range (D > 512 or more than 128 hidden channels) a model is
+    refused."""
     wb, nch = ctypes.c_int64(), ctypes.c_int64()
-    for D, n_d, n_a in ((300, 32, 32), (100, 80, 64)):
+    for D, n_d, n_a in ((600, 32, 32), (100, 80, 64), (300, 100, 40)):
         cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=2, n_shared=1, n_indep=1, n_out=2, gamma=1.5)
         raw = synth.to_bytes(synth.make_params(cfg, 1))
         assert L.tabnet_hook_packed_sizes(raw, len(raw), 1, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
 
 
-def expected_wide_packing(cfg, prec, W=4):
+def expected_wide_packing(cfg, prec, W=4, shape=None):
     """Packed bytes and chunk count of a model on the split-feature kernel (W waves per
     16-row group).  A feature-transformer layer is cut into K slices of sk k-blocks, sk the
     largest count whose NT x 2 fragments fit in 32 KiB (at least one); a slice holds the
@@ -311,7 +311,7 @@ def expected_wide_packing(cfg, prec, W=4):
     shifts (+ 16 scales).  Every layer starts 256-byte aligned.  Per forward the chunks run
     pass 0, then per step the attentive chunks and the pass."""
     cdiv = _cdiv
-    DT, NT, KA0 = cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16
+    DT, NT, KA0 = shape or (cdiv(cfg.D, 16), cdiv(cfg.N, 16), cfg.n_d // 16)
     per = {0: 1, 1: 2, 2: 4, 3: 4, 9: 4}.get(prec, 8)
     kbb = {4: 2304, 7: 2304, 5: 1280, 6: 1792, 8: 1792}.get(prec, 1024)
     ex = 2 if prec in (2, 3, 9) else 1
@@ -325,7 +325,7 @@ def expected_wide_packing(cfg, prec, W=4):
     nbytes = 0
 
     def ft_layer(K):
-        KB = cdiv(cdiv(K, 16), per)
+        KB = cdiv((DT if K == cfg.D else NT) if shape else cdiv(K, 16), per)
         return cdiv(NT * 2 * KB * kbb + NT * 128 * ex, 256) * 256, cdiv(KB, sk)
     for K in sh_k + ind_k * (cfg.n_steps + 1):
         nbytes += ft_layer(K)[0]
@@ -333,6 +333,16 @@ def expected_wide_packing(cfg, prec, W=4):
     pass_chunks = [sum(ft_layer(K)[1] for K in sh_k + ind_k)]
     nch = (cfg.n_steps + 1) * pass_chunks[0] + cfg.n_steps * (tpw // tpc)
     return nbytes, nch
+
+
+@pytest.mark.parametrize("D,n_d,n_a", [(300, 48, 48), (209, 8, 8), (480, 120, 8), (512, 20, 100)])
+def test_generic_wide_packing(L, D, n_d, n_a):
+    """Models past 208 features outside the split-feature family run in FP32 and BF16 on a
+    generic split-feature kernel compiled for 32 feature tiles and 8 hidden tiles with their
+    own KA0, packed to that kernel's tiles (expected_wide_packing)."""
+    cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=3, n_shared=2, n_indep=1, n_out=3, gamma=1.5)
+    for prec in (0, 1):
+        assert packed_sizes(L, cfg, prec) == expected_wide_packing(cfg, prec, 4, (32, 8, n_d // 16)), (prec, D)
 
 
 def test_wide_packed_sizes(L):

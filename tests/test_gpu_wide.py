@@ -350,3 +350,64 @@ def test_random_wide_row_coded(k, tmp_path):
     with m:
         got = run(m, X)
     check_mx_rows(got, params, X, f"random {k} {fmt}", fmt, plain=False)
+
+
+# Models past 208 features outside the split-feature family, served by the generic
+# split-feature kernels (FP32, BF16; 32 feature tiles, 8 hidden tiles, every KA0).
+GENERIC_WIDE = [dict(D=300, n_d=48, n_a=48, n_steps=4, n_shared=2, n_indep=2, n_out=2, gamma=1.3),
+                dict(D=400, n_d=20, n_a=60, n_steps=6, n_shared=1, n_indep=2, n_out=3, gamma=1.5),
+                dict(D=209, n_d=8, n_a=8, n_steps=3, n_shared=0, n_indep=2, n_out=1, gamma=1.9),
+                dict(D=512, n_d=110, n_a=18, n_steps=10, n_shared=2, n_indep=2, n_out=4, gamma=1.2)]
+
+
+def random_generic_wide(k):
+    """Seeded model k with 209-512 features outside the split-feature family: n_d + n_a
+    2-128, 1-10 steps, 0-3 shared and 0-3 step layers (at least one), 1-8 outputs, gamma in
+    [1, 2); 1-199 rows."""
+    rng = np.random.default_rng(8600 + k)
+    while True:
+        D = int(rng.integers(209, 513))
+        N = int(rng.integers(2, 129))
+        n_d = int(rng.integers(1, N))
+        n_sh, n_ind = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        if n_sh + n_ind == 0:
+            n_ind = 1
+        cfg = TabNetConfig(D=D, n_d=n_d, n_a=N - n_d, n_steps=int(rng.integers(1, 11)), n_shared=n_sh,
+                           n_indep=n_ind, n_out=int(rng.integers(1, 9)), gamma=float(rng.uniform(1.0, 2.0)))
+        if not (D >= 497 and N >= 113 and 64 <= n_d < 80):
+            return cfg, int(rng.integers(1, 200))
+
+
+@pytest.mark.parametrize("k", range(len(GENERIC_WIDE) + 4))
+def test_generic_wide_shapes(k, tmp_path):
+    """FP32 with the split-feature gates (logits 1e-4 relative, masks 1e-5 times the prior's
+    growth), BF16 against FP64 on bf16-rounded operands (logits 1e-3, mask L1 per row 5e-3),
+    and row independence across sub-batches."""
+    if k < len(GENERIC_WIDE):
+        cfg, B = TabNetConfig(**GENERIC_WIDE[k]), 150
+    else:
+        cfg, B = random_generic_wide(k)
+    X = synth.make_normal_inputs(B, cfg.D, 9800 + k)
+    _say(f"case generic wide {k}: {cfg} B={B}")
+    params, m = load(cfg, 9300 + k, "fp32", tmp_path, "a")
+    with m:
+        lo, ag, ms = run(m, X)
+        lo_, hi_ = B // 3, min(B, B // 3 + 17)
+        part = run(m, X[lo_:hi_])
+    np.testing.assert_array_equal(part[0], lo[lo_:hi_])
+    np.testing.assert_array_equal(part[1], ag[lo_:hi_])
+    np.testing.assert_array_equal(part[2], ms[:, lo_:hi_])
+    rlo, rag, rms = oracle.forward(params, X)
+    rel = (np.abs(lo - rlo).max(1) / np.maximum(np.abs(rlo).max(1), 1e-2)).max()
+    mt = 1e-5 * max(1.0, cfg.gamma ** (cfg.n_steps - 1) / 2)
+    _say(k, "fp32 logit_rel", rel, "agg", np.abs(ag - rag).max(), "step", np.abs(ms - rms).max(), "mask gate", mt)
+    assert rel <= 1e-4
+    assert np.abs(ag - rag).max() <= mt and np.abs(ms - rms).max() <= mt
+    _, m = load(cfg, 9300 + k, "bf16", tmp_path, "b")
+    with m:
+        lo, ag, ms = run(m, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="bf16", acts="bf16")
+    _say(k, "bf16 vs rounded: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
+         "step L1", np.abs(ms - qms).sum(-1).max())
+    assert np.abs(lo - qlo).max() <= 1e-3
+    assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
