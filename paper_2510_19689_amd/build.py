@@ -28,6 +28,8 @@ SOURCES = [
     "tabnet_kernel.hip",
     "tabnet_generic_fp32.hip",
     "tabnet_generic_bf16.hip",
+    "tabnet_generic_fp8w.hip",
+    "tabnet_generic_int8.hip",
     "tabnet_stats.hip",
     "tabnet_pack.cpp",
     "tabnet_api.cpp",

@@ -1,6 +1,5 @@
-// BF16 generic entries of the register-resident forward: kernels compiled for up to 16 DT
-// feature tiles and 16 NT hidden channels that serve the models between the exact shape
-// families (tabnet_kernel.hip, TABNET_GENERIC_SET).  A translation unit of its own so that
+// BF16 generic entries of the forward: kernels compiled for larger feature and hidden
+// tiles that serve the models between the exact shape families (tabnet_kernel.hip, TABNET_GENERIC_SET).  A translation unit of its own so that
 // the build compiles them beside the main kernels.
 #define TABNET_GENERIC_TU
 #include "tabnet_kernel.hip"

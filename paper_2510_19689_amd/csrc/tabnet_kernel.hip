@@ -1454,8 +1454,8 @@ struct WideGeom {
   static constexpr int TPW = wide_tpw(DT, W);     // feature tiles per wave
   static constexpr int DTP = TPW * W;             // padded feature tiles
   static constexpr int OPW = NT / W;              // output tile pairs per wave
-  // u in LDS: FP32 tiles (FP32, and MX, whose waves code every block of the row themselves)
-  // or BF16 k-blocks
+  // u in LDS: FP32 tiles (FP32, and the MX and row-coded formats, whose waves code the whole
+  // row themselves) or BF16 k-blocks
   static constexpr int UKB = PREC == 0 || is_mx(PREC) || row_coded(PREC) ? DTP : DTP / 2;
   static constexpr int UBYTES = UKB * kFrag;
 };
@@ -2020,7 +2020,7 @@ struct KernelEntry {
   bool raw;                  // embeds raw rows and writes masks per raw column
   void (*fn)(FwdArgs);
   Plan plan;                 // plan.wide: split-feature kernel, 16 rows per workgroup
-  bool gen = false;          // serves models of up to 16 DT features and 16 NT hidden channels
+  bool gen = false;          // generic: also serves models with fewer features or hidden channels
 };
 
 #define TABNET_SHAPE(P, DT, NT, KA0, R, W)                                                                 \
@@ -2048,10 +2048,11 @@ struct KernelEntry {
 // whose raw rows do not fit beside eight staging areas.  INT8 and the 8- and 6-bit MX
 // forms, which spill far more at two waves per SIMD, take four.
 #define TABNET_SHAPE_200(P) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
-// Generic entries (FP32 and BF16, embedded rows): for a model outside the exact families,
-// the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16) with KA0 =
-// floor(n_d / 16), for D <= 512 and n_d + n_a <= 128 (register-resident up to D = 208).  They are compiled in translation
-// units of their own (tabnet_generic_*.hip) so that the build runs them in parallel.
+// Generic entries (FP32, BF16, FP8 weights, INT8; embedded rows): for a model outside the
+// exact families, the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16)
+// with KA0 = floor(n_d / 16), for D <= 512 and n_d + n_a <= 128 (register-resident up to
+// D = 208).  They are compiled in translation units of their own (tabnet_generic_*.hip) so
+// that the build runs them in parallel.
 #define TABNET_GENERIC(P, DT, NT, KA0, W)                                                             \
   {P, DT, NT, KA0, 1, W, false, tabnet_forward_kernel<P, DT, NT, KA0, 1, W, false, true>,            \
    make_plan(P, DT, NT, KA0, chunk_target(DT, 1, W)), true},
@@ -2082,10 +2083,11 @@ static const KernelEntry kKernels[] = {TABNET_TILE_SWEEP};
 static const KernelEntry* const kGenericTables[] = {nullptr};
 static const int* const kGenericCountPtrs[] = {nullptr};
 #else
-extern const KernelEntry kGenericFp32[], kGenericBf16[];
-extern const int kGenericFp32Count, kGenericBf16Count;
-static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16};
-static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count};
+extern const KernelEntry kGenericFp32[], kGenericBf16[], kGenericFp8w[], kGenericInt8[];
+extern const int kGenericFp32Count, kGenericBf16Count, kGenericFp8wCount, kGenericInt8Count;
+static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16, kGenericFp8w, kGenericInt8};
+static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count, &kGenericFp8wCount,
+                                               &kGenericInt8Count};
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) TABNET_SHAPES(1) TABNET_SHAPE_200_W8(1)
                                        TABNET_SHAPES(2) TABNET_SHAPE_200_W8(2) TABNET_SHAPES(3) TABNET_SHAPE_200(3)
                                        TABNET_SHAPES(4) TABNET_SHAPE_200(4) TABNET_SHAPES(5) TABNET_SHAPE_200_W8(5)
@@ -2109,10 +2111,10 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
 // model (D, n_out, n_d) and whose raw-row twin (same tiling) holds it too without embedding
 // tables; else the first that holds the model; else the first entry of the shape, whose
 // LDS check then refuses the model.  A shape with no exact entry takes the first generic
-// entry (FP32, BF16; embedded rows) with its KA0 and at least its DT and NT that holds the
-// model, the smallest DT and then NT first.  With `twin`: the entry of the twin's tiling
-// (R, W) and `raw`, so that a raw-row kernel shares the weight chunking of the handle's
-// forward kernel (a generic kernel has no raw-row twin).
+// entry (FP32, BF16, FP8 weights, INT8; embedded rows) with its KA0 and at least its DT and
+// NT that holds the model, the smallest DT and then NT first.  With `twin`: the entry of
+// the twin's tiling (R, W) and `raw`, so that a raw-row kernel shares the weight chunking of
+// the handle's forward kernel (a generic kernel has no raw-row twin).
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int D, int n_out, int n_d,
                                const KernelEntry* twin) {
   auto shape_of = [&](const KernelEntry& e, bool r) {

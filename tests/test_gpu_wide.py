@@ -382,7 +382,9 @@ def random_generic_wide(k):
 def test_generic_wide_shapes(k, tmp_path):
     """FP32 with the split-feature gates (logits 1e-4 relative, masks 1e-5 times the prior's
     growth), BF16 against FP64 on bf16-rounded operands (logits 1e-3, mask L1 per row 5e-3),
-    and row independence across sub-batches."""
+    FP8 weights against FP64 on E4M3 weights and bf16 inputs (logits 2e-3, aggregate L1
+    1.5e-2, step L1 2e-2), INT8 with the row gates of WIDE_RC, and row independence across
+    sub-batches."""
     if k < len(GENERIC_WIDE):
         cfg, B = TabNetConfig(**GENERIC_WIDE[k]), 150
     else:
@@ -411,3 +413,15 @@ def test_generic_wide_shapes(k, tmp_path):
          "step L1", np.abs(ms - qms).sum(-1).max())
     assert np.abs(lo - qlo).max() <= 1e-3
     assert np.abs(ag - qag).sum(-1).max() <= 5e-3 and np.abs(ms - qms).sum(-1).max() <= 5e-3
+    _, m = load(cfg, 9300 + k, "fp8w", tmp_path, "c")
+    with m:
+        lo, ag, ms = run(m, X)
+    qlo, qag, qms = oracle.forward(params, X, weights="e4m3", acts="bf16")
+    _say(k, "fp8w vs rounded: logits", np.abs(lo - qlo).max(), "agg L1", np.abs(ag - qag).sum(-1).max(),
+         "step L1", np.abs(ms - qms).sum(-1).max())
+    assert np.abs(lo - qlo).max() <= 2e-3
+    assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
+    _, m = load(cfg, 9300 + k, "int8", tmp_path, "d")
+    with m:
+        got = run(m, X)
+    check_mx_rows(got, params, X, f"generic wide {k} int8", "int8", plain=False)
