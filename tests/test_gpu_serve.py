@@ -179,3 +179,39 @@ def test_four_resident_models_mixed_equals_alone(models):
     finally:
         for m in ms_:
             m.close()
+
+
+def test_generic_shape_models_served(tmp_path):
+    """Models outside the exact shape families (generic kernels: D = 150 with n_d = n_a = 48
+    in BF16, D = 300 with n_d = n_a = 40 on the split-feature kernel in INT8) served beside
+    each other: every request equals a tabnet_forward of it alone, bit for bit."""
+    cfgs = [synth.TabNetConfig(D=150, n_d=48, n_a=48, n_steps=4, n_shared=2, n_indep=2, n_out=2, gamma=1.3),
+            synth.TabNetConfig(D=300, n_d=40, n_a=40, n_steps=5, n_shared=2, n_indep=1, n_out=3, gamma=1.5)]
+    paths = []
+    for i, c in enumerate(cfgs):
+        paths.append(str(tmp_path / f"g{i}.tnw"))
+        synth.write_weights(synth.make_params(c, 4400 + i), paths[-1])
+    _say("case serve generic-shape models")
+    with tb.Model(paths[0], "bf16") as m0, tb.Model(paths[1], "int8") as m1:
+        ms_ = [m0, m1]
+        rng = np.random.default_rng(11)
+        pools = [synth.make_normal_inputs(3000, c.D, 4500 + i) for i, c in enumerate(cfgs)]
+        reqs = []
+        with tb.Server(ms_, max_rows_per_launch=1024, slots=3, with_step_masks=True) as s:
+            for k in range(40):
+                m = k % 2
+                c = cfgs[m]
+                rows = int(rng.integers(1, 2000))
+                off = int(rng.integers(0, pools[m].shape[0] - rows))
+                X = np.ascontiguousarray(pools[m][off:off + rows])
+                lo = np.full((rows, c.n_out), np.nan, np.float32)
+                ag = np.full((rows, c.D), np.nan, np.float32)
+                mk = np.full((c.n_steps, rows, c.D), np.nan, np.float32)
+                reqs.append((m, X, lo, ag, mk, s.submit(m, X, lo, ag, mk)))
+            for r in reqs:
+                assert s.wait(r[5]) == tb.OK
+        for m, X, lo, ag, mk, _ in reqs:
+            a_lo, a_ag, a_ms = alone(ms_[m], X)
+            np.testing.assert_array_equal(lo, a_lo)
+            np.testing.assert_array_equal(ag, a_ag)
+            np.testing.assert_array_equal(mk, a_ms)
