@@ -66,6 +66,10 @@ tabnet_status tabnet_hook_packed_sizes(const void* buf, size_t len, int precisio
  * number fail_launch (counted from 0 over the server's launches) fails to launch and
  * launch number fail_wait fails when its completion is waited on; -1 disables either.
  * Stop it with tabnet_serve_stop. */
+/* The serving path's host copy (the scatter and gather of launches): n bytes from src to
+ * dst; from 4 KiB up with non-temporal AVX2 stores where the CPU has them. */
+void tabnet_hook_serve_copy(void* dst, const void* src, size_t n);
+
 tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs, int n_models,
                                            const tabnet_serve_opts* opts, int delay_us, int fail_launch,
                                            int fail_wait, tabnet_server** out);

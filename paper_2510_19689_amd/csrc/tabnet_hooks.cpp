@@ -93,3 +93,5 @@ extern "C" tabnet_status tabnet_hook_serve_start_fake(const tabnet_config* cfgs,
   Executor* ex = make_fake_executor(models, o, delay_us, fail_launch, fail_wait);   // before models is moved
   return start_with(std::move(models), ex, o, out);
 }
+
+extern "C" void tabnet_hook_serve_copy(void* dst, const void* src, size_t n) { tabnet::serve_copy(dst, src, n); }

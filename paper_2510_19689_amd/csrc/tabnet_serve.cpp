@@ -687,4 +687,7 @@ tabnet_status server_stop(ServerImpl* s) {
   return TABNET_OK;
 }
 
+// The serving path's host copy of n bytes (for the test library's hooks).
+void serve_copy(void* dst, const void* src, size_t n) { copy_bytes(dst, src, n); }
+
 }  // namespace tabnet

@@ -76,4 +76,8 @@ tabnet_status start_with(std::vector<ModelInfo> models, Executor* ex, const tabn
                          tabnet_server** out);
 void set_error(const std::string& msg);
 
+// The serving path's host copy of n bytes: streaming stores from 4 KiB up where the CPU
+// has AVX2, memcpy otherwise.
+void serve_copy(void* dst, const void* src, size_t n);
+
 }  // namespace tabnet

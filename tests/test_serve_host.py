@@ -309,3 +309,23 @@ def test_per_model_statistics():
             assert per[0][k] + per[1][k] == tot[k]
         with pytest.raises(tb.TabNetError):
             s.model_stats(2)
+
+
+def test_serve_copy_every_alignment():
+    """The serving path's host copy (streaming stores from 4 KiB up, the destination's head
+    to 32-byte alignment and the tail through memcpy): every destination and source offset
+    within 64 bytes, at sizes around the thresholds (4 KiB, 128-byte blocks, 32-byte steps),
+    copies exactly n bytes and writes nothing outside them."""
+    L = tb.test_lib()
+    L.tabnet_hook_serve_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    L.tabnet_hook_serve_copy.restype = None
+    rng = np.random.default_rng(3)
+    src = rng.integers(0, 256, 1 << 19, dtype=np.uint8)
+    dst = np.empty((1 << 19) + 256, np.uint8)
+    for n in (0, 1, 31, 4095, 4096, 4097, 4096 + 31, 4096 + 127, 4096 + 128 + 33, 12345, 262144 + 77):
+        for d_off in range(64):
+            s_off = int(rng.integers(0, 64))
+            dst.fill(0xA5)
+            L.tabnet_hook_serve_copy(dst.ctypes.data + d_off, src.ctypes.data + s_off, n)
+            np.testing.assert_array_equal(dst[d_off:d_off + n], src[s_off:s_off + n])
+            assert (dst[:d_off] == 0xA5).all() and (dst[d_off + n:] == 0xA5).all(), (n, d_off)
