@@ -94,8 +94,9 @@ typedef struct tabnet_handle tabnet_handle;
  * with D <= 512 and n_d + n_a <= 128 runs in TABNET_FP32, TABNET_BF16, TABNET_FP8_WEIGHTS and
  * TABNET_INT8 on a generic kernel: up to D = 208 the register-resident one compiled for 4, 8 or 13 feature tiles
  * and 1, 2, 4 or 8 hidden tiles, past it the split-feature one compiled for 32 and 8 (the
- * padding is masked or carried as zeros; embedded rows only, so tabnet_set_embeddings
- * refuses such a model); the other precisions refuse it.
+ * padding is masked or carried as zeros); the other precisions refuse it.  Raw rows
+ * (tabnet_set_embeddings) run on such a model in TABNET_FP32 and TABNET_BF16 up to D = 208
+ * and are refused otherwise.
  *
  * TABNET_FP8_E4M3 puts both operands of every GEMM in E4M3 with one FP32 scale per
  * vector: each weight row as q = E4M3(W'_n / sigma_n) with sigma_n = max_k |W'_nk| / 448,

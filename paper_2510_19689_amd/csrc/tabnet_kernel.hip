@@ -2056,6 +2056,19 @@ struct KernelEntry {
 #define TABNET_GENERIC(P, DT, NT, KA0, W)                                                             \
   {P, DT, NT, KA0, 1, W, false, tabnet_forward_kernel<P, DT, NT, KA0, 1, W, false, true>,            \
    make_plan(P, DT, NT, KA0, chunk_target(DT, 1, W)), true},
+// raw-row twins (FP32 and BF16): the embedding gathered in the kernel, masks per raw column
+#define TABNET_GENERIC_RAW(P, DT, NT, KA0, W)                                                         \
+  {P, DT, NT, KA0, 1, W, true, tabnet_forward_kernel<P, DT, NT, KA0, 1, W, true, true>,              \
+   make_plan(P, DT, NT, KA0, chunk_target(DT, 1, W)), true},
+#define TABNET_GENERIC_NT_RAW(P, DT, W)                                                               \
+  TABNET_GENERIC_RAW(P, DT, 1, 0, W) TABNET_GENERIC_RAW(P, DT, 2, 0, W) TABNET_GENERIC_RAW(P, DT, 2, 1, W)      \
+  TABNET_GENERIC_RAW(P, DT, 4, 0, W) TABNET_GENERIC_RAW(P, DT, 4, 1, W) TABNET_GENERIC_RAW(P, DT, 4, 2, W)      \
+  TABNET_GENERIC_RAW(P, DT, 4, 3, W) TABNET_GENERIC_RAW(P, DT, 8, 0, W) TABNET_GENERIC_RAW(P, DT, 8, 1, W)      \
+  TABNET_GENERIC_RAW(P, DT, 8, 2, W) TABNET_GENERIC_RAW(P, DT, 8, 3, W) TABNET_GENERIC_RAW(P, DT, 8, 4, W)      \
+  TABNET_GENERIC_RAW(P, DT, 8, 5, W) TABNET_GENERIC_RAW(P, DT, 8, 6, W) TABNET_GENERIC_RAW(P, DT, 8, 7, W)
+#define TABNET_GENERIC_RAW_SET(P)                                                                     \
+  TABNET_GENERIC_NT_RAW(P, 4, 8) TABNET_GENERIC_NT_RAW(P, 8, 8) TABNET_GENERIC_NT_RAW(P, 13, 8)                 \
+  TABNET_GENERIC_NT_RAW(P, 13, 4)
 #define TABNET_GENERIC_NT(P, DT, W)                                                                   \
   TABNET_GENERIC(P, DT, 1, 0, W) TABNET_GENERIC(P, DT, 2, 0, W) TABNET_GENERIC(P, DT, 2, 1, W)      \
   TABNET_GENERIC(P, DT, 4, 0, W) TABNET_GENERIC(P, DT, 4, 1, W) TABNET_GENERIC(P, DT, 4, 2, W)      \
@@ -2114,7 +2127,8 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
 // entry (FP32, BF16, FP8 weights, INT8; embedded rows) with its KA0 and at least its DT and
 // NT that holds the model, the smallest DT and then NT first.  With `twin`: the entry of
 // the twin's tiling (R, W) and `raw`, so that a raw-row kernel shares the weight chunking of
-// the handle's forward kernel (a generic kernel has no raw-row twin).
+// the handle's forward kernel (generic kernels have raw-row twins in FP32 and BF16, on the
+// register-resident shapes).
 const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int D, int n_out, int n_d,
                                const KernelEntry* twin) {
   auto shape_of = [&](const KernelEntry& e, bool r) {
@@ -2122,8 +2136,18 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int 
   };
   auto fits = [&](const KernelEntry& e) { return kernel_lds_bytes(&e, D, n_out, n_d, 0, 0) <= (size_t)kMaxLdsBytes; };
   if (twin) {
+    // the entry of the twin kernel's own shape and tiling (a generic twin's shape is larger
+    // than the model's)
+    auto same = [&](const KernelEntry& e) {
+      return e.prec == prec && e.raw == raw && e.gen == twin->gen && e.DT == twin->DT && e.NT == twin->NT &&
+             e.KA0 == twin->KA0 && e.R == twin->R && e.W == twin->W;
+    };
     for (const auto& e : kKernels)
-      if (shape_of(e, raw) && e.R == twin->R && e.W == twin->W) return &e;
+      if (same(e)) return &e;
+    for (size_t ti = 0; ti < sizeof(kGenericTables) / sizeof(kGenericTables[0]); ++ti)
+      if (kGenericTables[ti])
+        for (int j = 0; j < *kGenericCountPtrs[ti]; ++j)
+          if (same(kGenericTables[ti][j])) return &kGenericTables[ti][j];
     return nullptr;
   }
   const KernelEntry *first = nullptr, *first_fit = nullptr;
@@ -2143,7 +2167,7 @@ const KernelEntry* find_kernel(int prec, int DT, int NT, int KA0, bool raw, int 
       if (!kGenericTables[ti]) continue;
       for (int j = 0; j < *kGenericCountPtrs[ti]; ++j) {
         const KernelEntry& e = kGenericTables[ti][j];
-        if (e.prec != prec || e.KA0 != KA0 || e.DT < DT || e.NT < NT) continue;
+        if (e.raw || e.prec != prec || e.KA0 != KA0 || e.DT < DT || e.NT < NT) continue;
         if (!gen_first) gen_first = &e;
         if (fits(e)) return &e;
       }

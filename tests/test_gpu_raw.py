@@ -65,8 +65,10 @@ def test_raw_equals_embedded_forward(name, prec, B, tmp_path):
     np.testing.assert_allclose(ms_r, oe.reduce_columns(ms, dims), rtol=0, atol=1e-6)
 
 
-# one model per compiled shape family: (D, n_d, n_a)
-RANDOM_SHAPES = [(13, 5, 6), (30, 8, 8), (47, 4, 10), (60, 20, 12), (104, 40, 24), (205, 70, 58)]
+# one model per compiled shape family: (D, n_d, n_a); then four between the families, on
+# the generic kernels' raw-row twins (FP32 and BF16)
+RANDOM_SHAPES = [(13, 5, 6), (30, 8, 8), (47, 4, 10), (60, 20, 12), (104, 40, 24), (205, 70, 58),
+                 (150, 48, 48), (90, 20, 20), (40, 8, 40), (180, 70, 50)]
 
 
 def random_spec(D, rng):
@@ -90,11 +92,12 @@ def random_spec(D, rng):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("k", range(len(RANDOM_SHAPES)))
 def test_random_embedding_specs(k, prec, tmp_path):
-    """Random embeddings on every compiled shape family: the raw-row logits equal the
-    embedded forward's bit for bit, each column's masks equal the FP32 sum of its features'
-    masks (|d| <= 2e-6: at most 24 values below 1), and in FP32 the raw forward matches the
-    FP64 oracle (logits 1e-4 relative, masks 1e-5 times the widest column and the prior's
-    growth).  A few categorical entries hold invalid levels, which embed to zero."""
+    """Random embeddings on every compiled shape family and on four generic shapes: the
+    raw-row logits equal the embedded forward's bit for bit, each column's masks equal the
+    FP32 sum of its features' masks (|d| <= 2e-6: at most 24 values below 1), and in FP32
+    the raw forward matches the FP64 oracle (logits 1e-4 relative, masks 1e-5 times the
+    widest column and the prior's growth).  A few categorical entries hold invalid levels,
+    which embed to zero."""
     rng = np.random.default_rng(400 + k)
     D, n_d, n_a = RANDOM_SHAPES[k]
     cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=int(rng.integers(1, 6)), n_shared=int(rng.integers(1, 3)),
@@ -240,3 +243,17 @@ def test_all_continuous_wide_layout_is_plain_forward(prec, tmp_path):
         b = to_np(*m.forward(torch.from_numpy(X).cuda()))
     for u, v in zip(a, b):
         np.testing.assert_array_equal(u, v)
+
+
+def test_generic_raw_rows_need_fp32_or_bf16(tmp_path):
+    """A generic-shape model has raw-row kernels in FP32 and BF16 only: in INT8 (which has
+    generic embedded-row kernels) tabnet_set_embeddings is refused."""
+    cfg = synth.TabNetConfig(D=150, n_d=48, n_a=48, n_steps=2, n_shared=1, n_indep=1, n_out=2, gamma=1.3)
+    path = str(tmp_path / "g.tnw")
+    synth.write_weights(synth.make_params(cfg, 8), path)
+    rng = np.random.default_rng(9)
+    cards, dims, tables = random_spec(cfg.D, rng)
+    with tb.Model(path, "int8") as m:
+        with pytest.raises(tb.TabNetError) as ei:
+            m.set_embeddings(cards, dims, tables)
+        assert ei.value.status == tb.E_UNSUPPORTED
