@@ -30,6 +30,8 @@ SOURCES = [
     "tabnet_generic_bf16.hip",
     "tabnet_generic_fp8w.hip",
     "tabnet_generic_int8.hip",
+    "tabnet_generic_fp32_raw.hip",
+    "tabnet_generic_bf16_raw.hip",
     "tabnet_stats.hip",
     "tabnet_pack.cpp",
     "tabnet_api.cpp",

@@ -7,7 +7,7 @@
 namespace tabnet {
 extern const KernelEntry kGenericBf16[];
 extern const int kGenericBf16Count;
-const KernelEntry kGenericBf16[] = {TABNET_GENERIC_SET(1) TABNET_GENERIC_RAW_SET(1)};
+const KernelEntry kGenericBf16[] = {TABNET_GENERIC_SET(1)};
 const int kGenericBf16Count =
     (int)(sizeof(kGenericBf16) / sizeof(kGenericBf16[0]));
 }  // namespace tabnet

@@ -7,7 +7,7 @@
 namespace tabnet {
 extern const KernelEntry kGenericFp32[];
 extern const int kGenericFp32Count;
-const KernelEntry kGenericFp32[] = {TABNET_GENERIC_SET(0) TABNET_GENERIC_RAW_SET(0)};
+const KernelEntry kGenericFp32[] = {TABNET_GENERIC_SET(0)};
 const int kGenericFp32Count =
     (int)(sizeof(kGenericFp32) / sizeof(kGenericFp32[0]));
 }  // namespace tabnet

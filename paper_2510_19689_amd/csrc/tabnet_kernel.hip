@@ -2096,11 +2096,14 @@ static const KernelEntry kKernels[] = {TABNET_TILE_SWEEP};
 static const KernelEntry* const kGenericTables[] = {nullptr};
 static const int* const kGenericCountPtrs[] = {nullptr};
 #else
-extern const KernelEntry kGenericFp32[], kGenericBf16[], kGenericFp8w[], kGenericInt8[];
-extern const int kGenericFp32Count, kGenericBf16Count, kGenericFp8wCount, kGenericInt8Count;
-static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16, kGenericFp8w, kGenericInt8};
-static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count, &kGenericFp8wCount,
-                                               &kGenericInt8Count};
+extern const KernelEntry kGenericFp32[], kGenericBf16[], kGenericFp8w[], kGenericInt8[], kGenericFp32Raw[],
+    kGenericBf16Raw[];
+extern const int kGenericFp32Count, kGenericBf16Count, kGenericFp8wCount, kGenericInt8Count, kGenericFp32RawCount,
+    kGenericBf16RawCount;
+static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16,    kGenericFp8w,
+                                                    kGenericInt8, kGenericFp32Raw, kGenericBf16Raw};
+static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count,    &kGenericFp8wCount,
+                                               &kGenericInt8Count, &kGenericFp32RawCount, &kGenericBf16RawCount};
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) TABNET_SHAPES(1) TABNET_SHAPE_200_W8(1)
                                        TABNET_SHAPES(2) TABNET_SHAPE_200_W8(2) TABNET_SHAPES(3) TABNET_SHAPE_200(3)
                                        TABNET_SHAPES(4) TABNET_SHAPE_200(4) TABNET_SHAPES(5) TABNET_SHAPE_200_W8(5)
