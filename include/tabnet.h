@@ -91,8 +91,8 @@ typedef struct tabnet_handle tabnet_handle;
  * Shapes.  Every precision has kernels compiled for the shape families of ceil(D / 16),
  * ceil((n_d + n_a) / 16) and floor(n_d / 16) = (1..4, 1, 0), (4, 2, 1), (7, 4, 2),
  * (13, 8, 4) and, on the split-feature kernel, (32, 8, 4) (D = 497..512).  Any other model
- * with D <= 512 and n_d + n_a <= 128 runs in TABNET_FP32, TABNET_BF16, TABNET_FP8_WEIGHTS and
- * TABNET_INT8 on a generic kernel: up to D = 208 the register-resident one compiled for 4, 8 or 13 feature tiles
+ * with D <= 512 and n_d + n_a <= 128 runs in TABNET_FP32, TABNET_BF16, TABNET_FP8_WEIGHTS,
+ * TABNET_FP8_E4M3 and TABNET_INT8 on a generic kernel: up to D = 208 the register-resident one compiled for 4, 8 or 13 feature tiles
  * and 1, 2, 4 or 8 hidden tiles, past it the split-feature one compiled for 32 and 8 (the
  * padding is masked or carried as zeros); the other precisions refuse it.  Raw rows
  * (tabnet_set_embeddings) run on such a model in TABNET_FP32 and TABNET_BF16 up to D = 208

@@ -29,6 +29,7 @@ SOURCES = [
     "tabnet_generic_fp32.hip",
     "tabnet_generic_bf16.hip",
     "tabnet_generic_fp8w.hip",
+    "tabnet_generic_fp8.hip",
     "tabnet_generic_int8.hip",
     "tabnet_generic_fp32_raw.hip",
     "tabnet_generic_bf16_raw.hip",

@@ -2048,8 +2048,8 @@ struct KernelEntry {
 // whose raw rows do not fit beside eight staging areas.  INT8 and the 8- and 6-bit MX
 // forms, which spill far more at two waves per SIMD, take four.
 #define TABNET_SHAPE_200(P) TABNET_SHAPE(P, 13, 8, 4, 1, 4)
-// Generic entries (FP32, BF16, FP8 weights, INT8; embedded rows): for a model outside the
-// exact families, the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16)
+// Generic entries (FP32, BF16, both FP8 forms, INT8; embedded rows): for a model outside
+// the exact families, the smallest compiled DT >= ceil(D / 16) and NT >= ceil((n_d + n_a) / 16)
 // with KA0 = floor(n_d / 16), for D <= 512 and n_d + n_a <= 128 (register-resident up to
 // D = 208).  They are compiled in translation units of their own (tabnet_generic_*.hip) so
 // that the build runs them in parallel.
@@ -2096,14 +2096,15 @@ static const KernelEntry kKernels[] = {TABNET_TILE_SWEEP};
 static const KernelEntry* const kGenericTables[] = {nullptr};
 static const int* const kGenericCountPtrs[] = {nullptr};
 #else
-extern const KernelEntry kGenericFp32[], kGenericBf16[], kGenericFp8w[], kGenericInt8[], kGenericFp32Raw[],
-    kGenericBf16Raw[];
-extern const int kGenericFp32Count, kGenericBf16Count, kGenericFp8wCount, kGenericInt8Count, kGenericFp32RawCount,
-    kGenericBf16RawCount;
-static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16,    kGenericFp8w,
+extern const KernelEntry kGenericFp32[], kGenericBf16[], kGenericFp8w[], kGenericFp8[], kGenericInt8[],
+    kGenericFp32Raw[], kGenericBf16Raw[];
+extern const int kGenericFp32Count, kGenericBf16Count, kGenericFp8wCount, kGenericFp8Count, kGenericInt8Count,
+    kGenericFp32RawCount, kGenericBf16RawCount;
+static const KernelEntry* const kGenericTables[] = {kGenericFp32, kGenericBf16,    kGenericFp8w,   kGenericFp8,
                                                     kGenericInt8, kGenericFp32Raw, kGenericBf16Raw};
-static const int* const kGenericCountPtrs[] = {&kGenericFp32Count, &kGenericBf16Count,    &kGenericFp8wCount,
-                                               &kGenericInt8Count, &kGenericFp32RawCount, &kGenericBf16RawCount};
+static const int* const kGenericCountPtrs[] = {&kGenericFp32Count,    &kGenericBf16Count, &kGenericFp8wCount,
+                                               &kGenericFp8Count,     &kGenericInt8Count, &kGenericFp32RawCount,
+                                               &kGenericBf16RawCount};
 static const KernelEntry kKernels[] = {TABNET_SHAPES(0) TABNET_SHAPE_200_W8(0) TABNET_SHAPES(1) TABNET_SHAPE_200_W8(1)
                                        TABNET_SHAPES(2) TABNET_SHAPE_200_W8(2) TABNET_SHAPES(3) TABNET_SHAPE_200(3)
                                        TABNET_SHAPES(4) TABNET_SHAPE_200(4) TABNET_SHAPES(5) TABNET_SHAPE_200_W8(5)
@@ -2127,8 +2128,8 @@ size_t kernel_lds_bytes(const KernelEntry* k, int D, int n_out, int n_d, int C, 
 // model (D, n_out, n_d) and whose raw-row twin (same tiling) holds it too without embedding
 // tables; else the first that holds the model; else the first entry of the shape, whose
 // LDS check then refuses the model.  A shape with no exact entry takes the first generic
-// entry (FP32, BF16, FP8 weights, INT8; embedded rows) with its KA0 and at least its DT and
-// NT that holds the model, the smallest DT and then NT first.  With `twin`: the entry of
+// entry (FP32, BF16, both FP8 forms, INT8; embedded rows) with its KA0 and at least its DT
+// and NT that holds the model, the smallest DT and then NT first.  With `twin`: the entry of
 // the twin's tiling (R, W) and `raw`, so that a raw-row kernel shares the weight chunking of
 // the handle's forward kernel (generic kernels have raw-row twins in FP32 and BF16, on the
 // register-resident shapes).

@@ -275,16 +275,16 @@ def test_200_feature_tiling_falls_back_to_four_waves(L, prec, n_out, W):
                                                (50, 24, 24, (4, 4, 1), 8), (20, 8, 40, (4, 4, 0), 8),
                                                (180, 70, 50, (13, 8, 4), 8)])
 def test_generic_kernel_packing(L, D, n_d, n_a, shape, W):
-    """A model outside the exact shape families runs on a generic kernel in FP32, BF16, FP8
-    weights and INT8: the smallest compiled DT (4, 8 or 13) and NT (1, 2, 4 or 8) that hold
+    """A model outside the exact shape families runs on a generic kernel in FP32, BF16, both
+    FP8 forms and INT8: the smallest compiled DT (4, 8 or 13) and NT (1, 2, 4 or 8) that hold
     its features and hidden channels, with its own KA0; the weights are packed to that
     kernel's tiles.  The other precisions have no generic entries (refused)."""
     cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=3, n_shared=2, n_indep=1, n_out=3, gamma=1.5)
-    for prec in (0, 1, 3, 9):
+    for prec in (0, 1, 2, 3, 9):
         assert packed_sizes(L, cfg, prec) == expected_packing(cfg, prec, W, shape), (prec, shape)
     raw = synth.to_bytes(synth.make_params(cfg, 1))
     wb, nch = ctypes.c_int64(), ctypes.c_int64()
-    for prec in (2, 4, 5, 6):
+    for prec in (4, 5, 6, 7, 8):
         assert L.tabnet_hook_packed_sizes(raw, len(raw), prec, ctypes.byref(wb), ctypes.byref(nch)) == tb.E_UNSUPPORTED
 
 
@@ -337,11 +337,11 @@ def expected_wide_packing(cfg, prec, W=4, shape=None):
 
 @pytest.mark.parametrize("D,n_d,n_a", [(300, 48, 48), (209, 8, 8), (480, 120, 8), (512, 20, 100)])
 def test_generic_wide_packing(L, D, n_d, n_a):
-    """Models past 208 features outside the split-feature family run in FP32, BF16, FP8
-    weights and INT8 on a generic split-feature kernel compiled for 32 feature tiles and 8
+    """Models past 208 features outside the split-feature family run in FP32, BF16, both FP8
+    forms and INT8 on a generic split-feature kernel compiled for 32 feature tiles and 8
     hidden tiles with their own KA0, packed to that kernel's tiles (expected_wide_packing)."""
     cfg = synth.TabNetConfig(D=D, n_d=n_d, n_a=n_a, n_steps=3, n_shared=2, n_indep=1, n_out=3, gamma=1.5)
-    for prec in (0, 1, 3, 9):
+    for prec in (0, 1, 2, 3, 9):
         assert packed_sizes(L, cfg, prec) == expected_wide_packing(cfg, prec, 4, (32, 8, n_d // 16)), (prec, D)
 
 

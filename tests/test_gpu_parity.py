@@ -533,8 +533,8 @@ def test_generic_shapes(tmp_path, k):
     """Models outside the exact shape families run on the generic kernels: FP32 against
     FP64 with the small models' gates (check_fp32_tight), BF16 against FP64 on bf16-rounded
     operands (check_reduced), FP8 weights against FP64 on E4M3 weights and bf16 inputs (the
-    register kernel's FP8-weight gates) and INT8 against FP64 on INT8 operands (its row
-    gates); a row's outputs do not depend on its sub-batch."""
+    register kernel's FP8-weight gates), and FP8 on both operands and INT8 against FP64 on
+    their coded operands (their row gates); a row's outputs do not depend on its sub-batch."""
     if k < len(GENERIC):
         cfg, B = TabNetConfig(**GENERIC[k]), 300
     else:
@@ -556,7 +556,8 @@ def test_generic_shapes(tmp_path, k):
         check_reduced(run(m, X), params, X, "bf16", "bf16", f"generic {k} bf16")
     with load(params, tmp_path, "fp8w", "c") as m:
         check_reduced(run(m, X), params, X, "e4m3", "bf16", f"generic {k} fp8w", tol=(2e-3, 1.5e-2, 2e-2))
-    oracle_fmt, worst, typical = ROW_GATES["int8"]
-    with load(params, tmp_path, "int8", "d") as m:
-        check_rows_on_rounded(run(m, X), params, X, oracle_fmt, f"generic {k} int8", worst=worst,
-                              typical=typical if B >= 50 else (0.0, 1.0))
+    for fmt, tag in (("int8", "d"), ("fp8", "e")):
+        oracle_fmt, worst, typical = ROW_GATES[fmt]
+        with load(params, tmp_path, fmt, tag) as m:
+            check_rows_on_rounded(run(m, X), params, X, oracle_fmt, f"generic {k} {fmt}", worst=worst,
+                                  typical=typical if B >= 50 else (0.0, 1.0))

@@ -383,8 +383,8 @@ def test_generic_wide_shapes(k, tmp_path):
     """FP32 with the split-feature gates (logits 1e-4 relative, masks 1e-5 times the prior's
     growth), BF16 against FP64 on bf16-rounded operands (logits 1e-3, mask L1 per row 5e-3),
     FP8 weights against FP64 on E4M3 weights and bf16 inputs (logits 2e-3, aggregate L1
-    1.5e-2, step L1 2e-2), INT8 with the row gates of WIDE_RC, and row independence across
-    sub-batches."""
+    1.5e-2, step L1 2e-2), FP8 on both operands and INT8 with the row gates of WIDE_RC, and
+    row independence across sub-batches."""
     if k < len(GENERIC_WIDE):
         cfg, B = TabNetConfig(**GENERIC_WIDE[k]), 150
     else:
@@ -421,7 +421,8 @@ def test_generic_wide_shapes(k, tmp_path):
          "step L1", np.abs(ms - qms).sum(-1).max())
     assert np.abs(lo - qlo).max() <= 2e-3
     assert np.abs(ag - qag).sum(-1).max() <= 1.5e-2 and np.abs(ms - qms).sum(-1).max() <= 2e-2
-    _, m = load(cfg, 9300 + k, "int8", tmp_path, "d")
-    with m:
-        got = run(m, X)
-    check_mx_rows(got, params, X, f"generic wide {k} int8", "int8", plain=False)
+    for fmt, tag in (("int8", "d"), ("fp8", "e")):
+        _, m = load(cfg, 9300 + k, fmt, tmp_path, tag)
+        with m:
+            got = run(m, X)
+        check_mx_rows(got, params, X, f"generic wide {k} {fmt}", fmt, plain=False)
