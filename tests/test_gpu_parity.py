@@ -534,7 +534,8 @@ def test_generic_shapes(tmp_path, k):
     FP64 with the small models' gates (check_fp32_tight), BF16 against FP64 on bf16-rounded
     operands (check_reduced), FP8 weights against FP64 on E4M3 weights and bf16 inputs (the
     register kernel's FP8-weight gates), and FP8 on both operands and INT8 against FP64 on
-    their coded operands (their row gates); a row's outputs do not depend on its sub-batch."""
+    their coded operands (their row gates); a row's outputs do not depend on its sub-batch,
+    and without step masks the logits and aggregate masks are unchanged bit for bit."""
     if k < len(GENERIC):
         cfg, B = TabNetConfig(**GENERIC[k]), 300
     else:
@@ -552,6 +553,10 @@ def test_generic_shapes(tmp_path, k):
         np.testing.assert_array_equal(part[0], got[0][lo_:hi_])
         np.testing.assert_array_equal(part[1], got[1][lo_:hi_])
         np.testing.assert_array_equal(part[2], got[2][:, lo_:hi_])
+        nomask = run(m, X, with_steps=False)
+        np.testing.assert_array_equal(nomask[0], got[0])
+        np.testing.assert_array_equal(nomask[1], got[1])
+        assert nomask[2] is None
     with load(params, tmp_path, "bf16", "b") as m:
         check_reduced(run(m, X), params, X, "bf16", "bf16", f"generic {k} bf16")
     with load(params, tmp_path, "fp8w", "c") as m:
